@@ -1,0 +1,699 @@
+// lb_kernels.hpp -- gfx950 kernels of the fine-box lattice-Boltzmann step.
+//
+//   k_chain   one workgroup per chain: trilinear interpolation of the fluid
+//             velocity at each bead from the pre-collision moments, the MD
+//             substeps (FENE, exact friction update, centre-of-mass pin) and
+//             the spreading records (stencil base, fractional offsets,
+//             friction impulse) plus the chain's stencil bounding box.
+//   k_lb      the fused step over a work list: interior tiles do pull
+//             streaming, gather the spread force from the records of the
+//             chains whose box overlaps the tile (fixed bead order, no
+//             atomics), collide and store; boundary items store the boundary
+//             equilibrium populations that point into the interior.  On check
+//             steps every item writes FP64 partial sums of mass and momentum
+//             at t_{n+1}; the last workgroup to finish reduces them in a fixed
+//             order per box and advances the device step counter.
+//   k_set_pre / k_read / k_read_sites   state upload and readout.
+#pragma once
+#include "lb_device.hpp"
+
+namespace lbdev {
+
+constexpr int WG = 256;
+constexpr int MAX_SLOTS = 4;   // tile plane positions per thread (ex*ey <= 1024)
+constexpr int MAX_BOX_CHAINS = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------- chain
+template <int S, bool PER>
+__global__ __launch_bounds__(WG) void k_chain(const BoxDesc* __restrict__ boxes,
+                                              const ChainDesc* __restrict__ chains,
+                                              const typename Store<S>::T* __restrict__ a0,
+                                              const typename Store<S>::T* __restrict__ a1,
+                                              typename Store<S>::R* __restrict__ pos,
+                                              typename Store<S>::R* __restrict__ vel,
+                                              int total_beads, int4* __restrict__ rec_base,
+                                              typename Store<S>::R* __restrict__ rec_d,
+                                              typename Store<S>::R* __restrict__ rec_dp,
+                                              int* __restrict__ bbox, DevState* __restrict__ st,
+                                              double rho0_d, int pre) {
+  using R = typename Store<S>::R;
+  const int ci = blockIdx.x;
+  const ChainDesc c = chains[ci];
+  const BoxDesc& b = boxes[c.box];
+  if (__hip_atomic_load(&st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE)
+    return;
+  const R rho0 = (R)rho0_d;
+  const long long step = st->step;
+  const int par = (int)(step & 1);
+  const typename Store<S>::T* src = (par ? a1 : a0) + b.off;
+  const int j = threadIdx.x;
+  const bool act = j < c.nb;
+  const int gj = c.first + j;
+
+  __shared__ R spx[WG], spy[WG], spz[WG];
+  __shared__ R bfx[WG], bfy[WG], bfz[WG];
+  __shared__ R red[3][WG];
+  __shared__ int sflag;
+  __shared__ int sbox[6];
+  if (j == 0) {
+    sflag = 0;
+    sbox[0] = sbox[1] = sbox[2] = 0x7fffffff;
+    sbox[3] = sbox[4] = sbox[5] = -0x7fffffff;
+  }
+  R rx = 0, ry = 0, rz = 0, vx = 0, vy = 0, vz = 0;
+  const size_t pin = (size_t)par * total_beads * 3, pout = (size_t)(par ^ 1) * total_beads * 3;
+  if (act) {
+    rx = pos[pin + 3 * gj];
+    ry = pos[pin + 3 * gj + 1];
+    rz = pos[pin + 3 * gj + 2];
+    vx = vel[pin + 3 * gj];
+    vy = vel[pin + 3 * gj + 1];
+    vz = vel[pin + 3 * gj + 2];
+  }
+  __syncthreads();
+
+  // stencil at t_n: R = anchor + rel, anchor split into integer + fractional parts
+  int base[3] = {0, 0, 0};
+  R dl[3] = {0, 0, 0};
+  if (act) {
+    const R rr[3] = {rx, ry, rz};
+    const int n3[3] = {b.nx, b.ny, b.nz};
+    bool out = false;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const R r = (R)c.af[a] + rr[a];
+      const R fl = floor(r);
+      base[a] = c.ai[a] + (int)fl;
+      dl[a] = r - fl;
+      if (!((b.pmask >> a) & 1)) {
+        if (base[a] < 1 || base[a] + 1 > n3[a] - 2) out = true;
+      } else {
+        base[a] = ((base[a] % n3[a]) + n3[a]) % n3[a];
+      }
+    }
+    if (out) atomicOr(&sflag, 1);
+  }
+  __syncthreads();
+  if (sflag) {
+    if (j == 0) atomicMin(&st->err_key, (ci << 4) | EC_BEAD_OUT);
+    return;
+  }
+
+  // fluid velocity at the bead: sum over the 8 corners of weight x j/rho
+  R ux = 0, uy = 0, uz = 0;
+  if (act) {
+#pragma unroll 1
+    for (int cc = 0; cc < 8; cc++) {
+      const int o0 = cc & 1, o1 = (cc >> 1) & 1, o2 = (cc >> 2) & 1;
+      int qx = base[0] + o0, qy = base[1] + o1, qz = base[2] + o2;
+      if (PER) {
+        if (b.pmask & 1) qx = wrapc(qx, b.nx);
+        if (b.pmask & 2) qy = wrapc(qy, b.ny);
+        if (b.pmask & 4) qz = wrapc(qz, b.nz);
+      }
+      const R w = (o0 ? dl[0] : (R)1 - dl[0]) * (o1 ? dl[1] : (R)1 - dl[1]) *
+                  (o2 ? dl[2] : (R)1 - dl[2]);
+      R d[Q];
+      load_pre<S, PER>(src, b, qx, qy, qz, pre != 0, d);
+      R drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        drho += d[i];
+        if (CX[i]) jx += (R)CX[i] * d[i];
+        if (CY[i]) jy += (R)CY[i] * d[i];
+        if (CZ[i]) jz += (R)CZ[i] * d[i];
+      }
+      const R wr = w / (rho0 + drho);
+      ux += wr * jx;
+      uy += wr * jy;
+      uz += wr * jz;
+    }
+  }
+
+  // MD substeps
+  const R h = (R)1 / (R)c.substeps;
+  const R decay = (R)c.decay;
+  const R zeta = (R)c.zeta, mass = (R)c.mass, fk = (R)c.fene_k;
+  const R r02 = (R)(c.fene_r0 * c.fene_r0);
+  R dpx = 0, dpy = 0, dpz = 0;
+  for (int s = 0; s < c.substeps; s++) {
+    spx[j] = rx;
+    spy[j] = ry;
+    spz[j] = rz;
+    __syncthreads();
+    R fx = 0, fy = 0, fz = 0;
+    if (act && j + 1 < c.nb) {
+      const R ex = spx[j + 1] - rx, ey = spy[j + 1] - ry, ez = spz[j + 1] - rz;
+      const R r2 = ex * ex + ey * ey + ez * ez;
+      if (r2 >= r02) {
+        atomicOr(&sflag, 2);
+      } else {
+        R fac;
+        if (S != 0 && r2 > (R)0.8 * r02) {
+          // near full extension: evaluate the FENE factor in FP64
+          const double r2d = (double)ex * ex + (double)ey * ey + (double)ez * ez;
+          fac = (R)(c.fene_k / (1.0 - r2d / (c.fene_r0 * c.fene_r0)));
+        } else {
+          fac = fk / ((R)1 - r2 / r02);
+        }
+        fx = fac * ex;
+        fy = fac * ey;
+        fz = fac * ez;
+      }
+    }
+    bfx[j] = fx;
+    bfy[j] = fy;
+    bfz[j] = fz;
+    __syncthreads();
+    if (sflag) break;
+    if (act) {
+      R Fx = bfx[j], Fy = bfy[j], Fz = bfz[j];
+      if (j > 0) {
+        Fx -= bfx[j - 1];
+        Fy -= bfy[j - 1];
+        Fz -= bfz[j - 1];
+      }
+      const R tx = ux + Fx / zeta, ty = uy + Fy / zeta, tz = uz + Fz / zeta;
+      const R nvx = tx + (vx - tx) * decay, nvy = ty + (vy - ty) * decay,
+              nvz = tz + (vz - tz) * decay;
+      dpx += mass * (nvx - vx) - Fx * h;
+      dpy += mass * (nvy - vy) - Fy * h;
+      dpz += mass * (nvz - vz) - Fz * h;
+      vx = nvx;
+      vy = nvy;
+      vz = nvz;
+      rx += h * vx;
+      ry += h * vy;
+      rz += h * vz;
+    }
+    if (c.fix_com) {
+      // fixed-order tree sums of velocity and relative position
+#pragma unroll 1
+      for (int pass = 0; pass < 2; pass++) {
+        red[0][j] = act ? (pass ? rx : vx) : (R)0;
+        red[1][j] = act ? (pass ? ry : vy) : (R)0;
+        red[2][j] = act ? (pass ? rz : vz) : (R)0;
+        __syncthreads();
+        for (int o = WG / 2; o > 0; o >>= 1) {
+          if (j < o) {
+            red[0][j] += red[0][j + o];
+            red[1][j] += red[1][j + o];
+            red[2][j] += red[2][j + o];
+          }
+          __syncthreads();
+        }
+        const R inb = (R)1 / (R)c.nb;
+        const R mx = red[0][0] * inb, my = red[1][0] * inb, mz = red[2][0] * inb;
+        __syncthreads();
+        if (pass == 0) {
+          vx -= mx;
+          vy -= my;
+          vz -= mz;
+        } else {
+          rx -= mx;
+          ry -= my;
+          rz -= mz;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (sflag) {
+    if (j == 0) atomicMin(&st->err_key, (ci << 4) | EC_FENE);
+    return;
+  }
+  if (act) {
+    pos[pout + 3 * gj] = rx;
+    pos[pout + 3 * gj + 1] = ry;
+    pos[pout + 3 * gj + 2] = rz;
+    vel[pout + 3 * gj] = vx;
+    vel[pout + 3 * gj + 1] = vy;
+    vel[pout + 3 * gj + 2] = vz;
+    rec_base[gj] = make_int4(base[0], base[1], base[2], 0);
+    rec_d[3 * gj] = dl[0];
+    rec_d[3 * gj + 1] = dl[1];
+    rec_d[3 * gj + 2] = dl[2];
+    rec_dp[3 * gj] = dpx;
+    rec_dp[3 * gj + 1] = dpy;
+    rec_dp[3 * gj + 2] = dpz;
+    atomicMin(&sbox[0], base[0]);
+    atomicMin(&sbox[1], base[1]);
+    atomicMin(&sbox[2], base[2]);
+    atomicMax(&sbox[3], base[0] + 1);
+    atomicMax(&sbox[4], base[1] + 1);
+    atomicMax(&sbox[5], base[2] + 1);
+  }
+  __syncthreads();
+  if (j == 0) {
+    if (b.pmask) {
+      // wrapped stencils: every tile of the box checks this chain
+      bbox[6 * ci + 0] = 0;
+      bbox[6 * ci + 1] = 0;
+      bbox[6 * ci + 2] = 0;
+      bbox[6 * ci + 3] = b.nx - 1;
+      bbox[6 * ci + 4] = b.ny - 1;
+      bbox[6 * ci + 5] = b.nz - 1;
+    } else {
+      for (int a = 0; a < 6; a++) bbox[6 * ci + a] = sbox[a];
+    }
+  }
+}
+
+// ----------------------------------------------------- boundary helpers
+// Velocity u_b of boundary node q on face f at step n (Sec. 2-3): affine
+// u_b = A(t_n)(q - x_c) or bilinear on the face x linear in time.
+template <typename R>
+__device__ __forceinline__ void boundary_velocity(const BoxDesc& b, int f, const int q[3],
+                                                  long long n, R u[3]) {
+  long long rel = n - b.bc_t0;
+  if (rel < 0) rel = 0;
+  long long k = rel / b.bc_dt;
+  long long rem = rel - k * b.bc_dt;
+  if (k >= b.bc_ns) {
+    k = b.bc_ns - 1;
+    rem = 0;
+  }
+  bool two = rem > 0 && k + 1 < b.bc_ns;
+  const R th = (R)rem / (R)b.bc_dt;
+  if (b.bc_mode == 0) {
+    const double* A0 = (const double*)b.bc + 9 * k;
+    const double* A1 = A0 + 9;
+    const R rx = (R)q[0] - (R)0.5 * (R)(b.nx - 1);
+    const R ry = (R)q[1] - (R)0.5 * (R)(b.ny - 1);
+    const R rz = (R)q[2] - (R)0.5 * (R)(b.nz - 1);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      R m0 = (R)A0[3 * a], m1 = (R)A0[3 * a + 1], m2 = (R)A0[3 * a + 2];
+      if (two) {
+        m0 = ((R)1 - th) * m0 + th * (R)A1[3 * a];
+        m1 = ((R)1 - th) * m1 + th * (R)A1[3 * a + 1];
+        m2 = ((R)1 - th) * m2 + th * (R)A1[3 * a + 2];
+      }
+      u[a] = m0 * rx + m1 * ry + m2 * rz;
+    }
+    return;
+  }
+  const int a = f >> 1;
+  const int au = (a == 0) ? 1 : 0;
+  const int av = (a == 2) ? 1 : 2;
+  const int n3[3] = {b.nx, b.ny, b.nz};
+  const int nu = n3[au], nv = n3[av];
+  const int Rr = b.bc_res;
+  const long long su = (long long)q[au] * (Rr - 1), sv = (long long)q[av] * (Rr - 1);
+  const int p = (int)(su / (nu - 1)), qq = (int)(sv / (nv - 1));
+  const R al = (R)(su - (long long)p * (nu - 1)) / (R)(nu - 1);
+  const R be = (R)(sv - (long long)qq * (nv - 1)) / (R)(nv - 1);
+  const int p1 = p + 1 < Rr ? p + 1 : p, q1 = qq + 1 < Rr ? qq + 1 : qq;
+  const R* Sb = (const R*)b.bc;
+  const size_t fs = (size_t)Rr * Rr * 3;
+  R v0[3], v1[3] = {0, 0, 0};
+#pragma unroll
+  for (int t = 0; t < 2; t++) {
+    if (t == 1 && !two) break;
+    const R* Sk = Sb + ((size_t)(k + t) * 6 + f) * fs;
+    R* out = t ? v1 : v0;
+#pragma unroll
+    for (int cmp = 0; cmp < 3; cmp++) {
+      const R s00 = Sk[((size_t)qq * Rr + p) * 3 + cmp], s01 = Sk[((size_t)qq * Rr + p1) * 3 + cmp];
+      const R s10 = Sk[((size_t)q1 * Rr + p) * 3 + cmp], s11 = Sk[((size_t)q1 * Rr + p1) * 3 + cmp];
+      out[cmp] = ((R)1 - al) * ((R)1 - be) * s00 + al * ((R)1 - be) * s01 + ((R)1 - al) * be * s10 +
+                 al * be * s11;
+    }
+  }
+#pragma unroll
+  for (int cmp = 0; cmp < 3; cmp++) u[cmp] = two ? ((R)1 - th) * v0[cmp] + th * v1[cmp] : v0[cmp];
+}
+
+__device__ __forceinline__ bool is_interior(const BoxDesc& b, int x, int y, int z) {
+  return ((b.pmask & 1) || (x >= 1 && x <= b.nx - 2)) && ((b.pmask & 2) || (y >= 1 && y <= b.ny - 2)) &&
+         ((b.pmask & 4) || (z >= 1 && z <= b.nz - 2));
+}
+
+// ----------------------------------------------------------- fused step
+struct LbArgs {
+  const BoxDesc* boxes;
+  const Item* items;
+  const int* order;        // [n_entries], -1 = empty slot
+  int n_entries;
+  void* a0;
+  void* a1;
+  const ChainDesc* chains;
+  const int4* rec_base;
+  const void* rec_d;
+  const void* rec_dp;
+  const int* bbox;
+  DevState* st;
+  double* partials;        // [n_items][4]
+  const int* box_items;    // CSR lists of item indices per box
+  const int* box_items_off;
+  double* mass_mom;        // [n_boxes][5]
+  int n_boxes;
+  int reduce_every;
+  double rho0, omega, om_bulk, om_ghost;
+  int pre;
+  int advance;
+};
+
+template <int S, int COLL, bool PER>
+__global__ __launch_bounds__(WG) void k_lb(LbArgs A) {
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  __shared__ double sred[4][WG / 64];
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  const bool skip =
+      __hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
+  if (skip) return;  // uniform: the latch is set before this launch or not at all
+  const long long step = A.st->step;
+  const int par = (int)(step & 1);
+  const bool check = A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0;
+  const R rho0 = (R)A.rho0, omega = (R)A.omega, omb = (R)A.om_bulk, omg = (R)A.om_ghost;
+  const T* __restrict__ srcA = (const T*)(par ? A.a1 : A.a0);
+  T* __restrict__ dstA = (T*)(par ? A.a0 : A.a1);
+  const bool pre = A.pre != 0;
+
+  for (int e = blockIdx.x; e < A.n_entries; e += gridDim.x) {
+    const int ii = A.order[e];
+    if (ii < 0) continue;
+    const Item it = A.items[ii];
+    const BoxDesc& b = A.boxes[it.box];
+    const T* __restrict__ src = srcA + b.off;
+    T* __restrict__ dst = dstA + b.off;
+    const int64_t nn = b.nn;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+
+    if (it.kind == ITEM_TILE) {
+      // chains whose stencil box overlaps this tile
+      unsigned long long cmask = 0;
+      for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
+        const int* bb = A.bbox + 6 * (b.chain_first + c);
+        const bool ov = bb[0] <= it.x0 + it.ex - 1 && bb[3] >= it.x0 && bb[1] <= it.y0 + it.ey - 1 &&
+                        bb[4] >= it.y0 && bb[2] <= it.z0 + it.ez - 1 && bb[5] >= it.z0;
+        if (ov) cmask |= 1ull << c;
+      }
+      const int plane = it.ex * it.ey;
+      int px[MAX_SLOTS], py[MAX_SLOTS];
+      int ns = 0;
+#pragma unroll
+      for (int r = 0; r < MAX_SLOTS; r++) {
+        const int p = tid + r * WG;
+        px[r] = 0;
+        py[r] = 0;
+        if (p < plane) {
+          px[r] = it.x0 + p % it.ex;
+          py[r] = it.y0 + p / it.ex;
+          ns = r + 1;
+        }
+      }
+      for (int z = it.z0; z < it.z0 + it.ez; z++) {
+#pragma unroll
+        for (int r = 0; r < MAX_SLOTS; r++) {
+          if (r >= ns) break;
+          const int x = px[r], y = py[r];
+          const int node = (z * b.ny + y) * b.nx + x;
+          R d[Q];
+          load_pre<S, PER>(src, b, x, y, z, pre, d);
+          // spread force: g(x) = - sum_j w_jx dP_j in fixed chain/bead order
+          R gx = 0, gy = 0, gz = 0;
+          if (cmask) {
+            const R* rd = (const R*)A.rec_d;
+            const R* rp = (const R*)A.rec_dp;
+            for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
+              if (!((cmask >> c) & 1ull)) continue;
+              const int gc = b.chain_first + c;
+              const int* bb = A.bbox + 6 * gc;
+              if (z < bb[2] || z > bb[5]) continue;
+              const ChainDesc& ch = A.chains[gc];
+              const bool inside = x >= bb[0] && x <= bb[3] && y >= bb[1] && y <= bb[4];
+              if (!inside) continue;
+              for (int jb = ch.first; jb < ch.first + ch.nb; jb++) {
+                const int4 bs = A.rec_base[jb];
+                int ox = x - bs.x, oy = y - bs.y, oz = z - bs.z;
+                if (PER) {
+                  if ((b.pmask & 1) && ox < 0) ox += b.nx;
+                  if ((b.pmask & 2) && oy < 0) oy += b.ny;
+                  if ((b.pmask & 4) && oz < 0) oz += b.nz;
+                }
+                if ((unsigned)ox > 1u || (unsigned)oy > 1u || (unsigned)oz > 1u) continue;
+                const R w = (ox ? rd[3 * jb] : (R)1 - rd[3 * jb]) *
+                            (oy ? rd[3 * jb + 1] : (R)1 - rd[3 * jb + 1]) *
+                            (oz ? rd[3 * jb + 2] : (R)1 - rd[3 * jb + 2]);
+                gx -= w * rp[3 * jb];
+                gy -= w * rp[3 * jb + 1];
+                gz -= w * rp[3 * jb + 2];
+              }
+            }
+          }
+          collide<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+#pragma unroll
+          for (int i = 0; i < Q; i++) dst[i * nn + node] = St::enc(d[i], b.enc[WCLS[i]]);
+          if (check) {
+            // contribution of this node's stored populations to M, P at t_{n+1}
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+              int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+              if (PER) {
+                if (b.pmask & 1) tx = wrapc(tx, b.nx);
+                if (b.pmask & 2) ty = wrapc(ty, b.ny);
+                if (b.pmask & 4) tz = wrapc(tz, b.nz);
+              }
+              if (!is_interior(b, tx, ty, tz)) continue;
+              const double v = (double)St::dec(St::enc(d[i], b.enc[WCLS[i]]), b.dec[WCLS[i]]);
+              acc[0] += v;
+              if (CX[i]) acc[1] += CX[i] * v;
+              if (CY[i]) acc[2] += CY[i] * v;
+              if (CZ[i]) acc[3] += CZ[i] * v;
+            }
+          }
+        }
+      }
+    } else {
+      // boundary chunk: equilibrium at rho0 and u_b(t_n) for the populations
+      // that stream into the interior
+      for (int k = it.x0 + tid; k < it.x0 + it.ex; k += WG) {
+        int f = 0, kk = k;
+        while (f < 5 && kk >= b.face_cnt[f]) {
+          kk -= b.face_cnt[f];
+          f++;
+        }
+        const int a = f >> 1;
+        const int au = (a == 0) ? 1 : 0;
+        const int av = (a == 2) ? 1 : 2;
+        const int lu = b.face_len[f][au];
+        int q[3];
+        q[a] = b.face_start[f][a];
+        q[au] = b.face_start[f][au] + kk % lu;
+        q[av] = b.face_start[f][av] + kk / lu;
+        R u[3];
+        boundary_velocity<R>(b, f, q, step, u);
+        R eq[Q];
+        eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
+        const int node = (q[2] * b.ny + q[1]) * b.nx + q[0];
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+          int tx = q[0] + CX[i], ty = q[1] + CY[i], tz = q[2] + CZ[i];
+          if (PER) {
+            if (b.pmask & 1) tx = wrapc(tx, b.nx);
+            if (b.pmask & 2) ty = wrapc(ty, b.ny);
+            if (b.pmask & 4) tz = wrapc(tz, b.nz);
+          }
+          if (!is_interior(b, tx, ty, tz)) continue;
+          const T v = St::enc(eq[i], b.enc[WCLS[i]]);
+          dst[i * nn + node] = v;
+          if (check) {
+            const double dv = (double)St::dec(v, b.dec[WCLS[i]]);
+            acc[0] += dv;
+            if (CX[i]) acc[1] += CX[i] * dv;
+            if (CY[i]) acc[2] += CY[i] * dv;
+            if (CZ[i]) acc[3] += CZ[i] * dv;
+          }
+        }
+      }
+    }
+    if (check) {
+      // fixed-order reduction: wave shuffle -> LDS -> one partial per item
+#pragma unroll
+      for (int m = 0; m < 4; m++) {
+        const double v = wave_sum(acc[m]);
+        if ((tid & 63) == 0) sred[m][tid >> 6] = v;
+      }
+      __syncthreads();
+      if (tid < 4) {
+        double s = 0.0;
+        for (int w = 0; w < WG / 64; w++) s += sred[tid][w];
+        A.partials[4 * ii + tid] = s;
+      }
+      __syncthreads();
+    }
+  }
+
+  // last workgroup: per-box fixed-order sums, finiteness check, step advance
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&A.st->done, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0x7fffffff;
+  __syncthreads();
+  if (check) {
+    for (int bx = tid; bx < A.n_boxes; bx += WG) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = A.box_items_off[bx]; q < A.box_items_off[bx + 1]; q++) {
+        const int item = A.box_items[q];
+#pragma unroll
+        for (int m = 0; m < 4; m++)
+          s[m] += __hip_atomic_load(&A.partials[4 * item + m], __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+      }
+      const double M = A.rho0 * A.boxes[bx].interior + s[0];
+      double* mm = A.mass_mom + 5 * bx;
+      mm[0] = (double)(step + 1);
+      mm[1] = M;
+      mm[2] = s[1];
+      mm[3] = s[2];
+      mm[4] = s[3];
+      if (!(isfinite(M) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]))) atomicMin(&s_bad, bx);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    A.st->done = 0;
+    if (s_bad != 0x7fffffff) {
+      atomicMin(&A.st->err_key, (s_bad << 4) | EC_UNSTABLE);
+    } else if (A.advance) {
+      A.st->step = step + 1;
+    }
+    __threadfence();
+  }
+}
+
+// ------------------------------------------------------- state upload
+// pre-collision state of one box from FP64 populations [19][nn] (mode 0) or
+// from the equilibrium of a velocity field u[nn][3] (mode 1) or rest (mode 2)
+template <int S>
+__global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T* __restrict__ dst,
+                                                const double* __restrict__ in, int mode, double rho0) {
+  using St = Store<S>;
+  using R = typename St::R;
+  const int64_t nn = b.nn;
+  for (int64_t node = (int64_t)blockIdx.x * WG + threadIdx.x; node < nn;
+       node += (int64_t)gridDim.x * WG) {
+    const int x = (int)(node % b.nx);
+    const int y = (int)((node / b.nx) % b.ny);
+    const int z = (int)(node / ((int64_t)b.nx * b.ny));
+    R d[Q];
+    if (!is_interior(b, x, y, z) || mode == 2) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = 0;
+    } else if (mode == 0) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = (R)(in[i * nn + node] - WD[WCLS[i]] * rho0);
+    } else {
+      // deviation of f_eq(rho0, u): computed in FP64 then rounded once
+      double ud[3] = {in[3 * node], in[3 * node + 1], in[3 * node + 2]};
+      double eq[Q];
+      eq_dev<double>(0.0, rho0, ud[0], ud[1], ud[2], eq);
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = (R)eq[i];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) dst[i * nn + node] = St::enc(d[i], b.enc[WCLS[i]]);
+  }
+}
+
+// ------------------------------------------------------------ readout
+// what: 0 populations [19][nn], 1 rho [nn], 2 u [nn][3]
+template <int S, bool PER>
+__global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>::T* __restrict__ src,
+                                             double* __restrict__ out, int what, int pre, double rho0) {
+  using R = typename Store<S>::R;
+  const int64_t nn = b.nn;
+  for (int64_t node = (int64_t)blockIdx.x * WG + threadIdx.x; node < nn;
+       node += (int64_t)gridDim.x * WG) {
+    const int x = (int)(node % b.nx);
+    const int y = (int)((node / b.nx) % b.ny);
+    const int z = (int)(node / ((int64_t)b.nx * b.ny));
+    double f[Q];
+    if (is_interior(b, x, y, z)) {
+      R d[Q];
+      load_pre<S, PER>(src, b, x, y, z, pre != 0, d);
+#pragma unroll
+      for (int i = 0; i < Q; i++) f[i] = WD[WCLS[i]] * rho0 + (double)d[i];
+      if (what == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = f[i];
+      } else {
+        double drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          drho += (double)d[i];
+          jx += CX[i] * (double)d[i];
+          jy += CY[i] * (double)d[i];
+          jz += CZ[i] * (double)d[i];
+        }
+        const double rho = rho0 + drho;
+        if (what == 1) {
+          out[node] = rho;
+        } else {
+          out[3 * node] = jx / rho;
+          out[3 * node + 1] = jy / rho;
+          out[3 * node + 2] = jz / rho;
+        }
+      }
+    } else {
+      if (what == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = WD[WCLS[i]] * rho0;
+      } else if (what == 1) {
+        out[node] = rho0;
+      } else {
+        out[3 * node] = out[3 * node + 1] = out[3 * node + 2] = 0.0;
+      }
+    }
+  }
+}
+
+template <int S, bool PER>
+__global__ __launch_bounds__(WG) void k_read_sites(BoxDesc b, const typename Store<S>::T* __restrict__ src,
+                                                   const int* __restrict__ xyz, int n,
+                                                   double* __restrict__ out, int pre, double rho0) {
+  using R = typename Store<S>::R;
+  const int k = blockIdx.x * WG + threadIdx.x;
+  if (k >= n) return;
+  R d[Q];
+  load_pre<S, PER>(src, b, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2], pre != 0, d);
+#pragma unroll
+  for (int i = 0; i < Q; i++) out[Q * k + i] = WD[WCLS[i]] * rho0 + (double)d[i];
+}
+
+// bead positions/velocities of one parity buffer back to absolute FP64 coordinates
+template <typename R>
+__global__ void k_read_beads(const ChainDesc* __restrict__ chains, int c0, int c1,
+                             const R* __restrict__ buf, double* __restrict__ out, int add_anchor) {
+  int o = 0;
+  for (int c = c0; c < c1; c++) {
+    const ChainDesc ch = chains[c];
+    for (int j = threadIdx.x; j < ch.nb; j += blockDim.x)
+      for (int a = 0; a < 3; a++) {
+        double v = (double)buf[3 * (ch.first + j) + a];
+        if (add_anchor) v = (double)ch.ai[a] + (ch.af[a] + v);
+        out[3 * (o + j) + a] = v;
+      }
+    o += ch.nb;
+  }
+}
+
+}  // namespace lbdev

@@ -1,0 +1,1268 @@
+// lbm.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// A context owns two structure-of-arrays population arenas (all boxes back to
+// back), the boundary histories, the chain state (double-buffered by step
+// parity) and a work list of items (interior tiles and boundary chunks) for the
+// fused kernel.  Per step it launches k_chain (when chains exist) and k_lb on
+// the context stream; every per-step quantity (time index, buffer parity,
+// check steps) is read on the device from DevState, so a chunk of steps can
+// be captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lb_kernels.hpp"
+
+using namespace lbdev;
+
+namespace {
+
+constexpr int BND_CHUNK = 512;
+
+struct BoxHost {
+  lb_box dim;
+  int64_t nn = 0, off = 0;
+  int64_t interior = 0;
+  int ox = 1, oy = 1, oz = 1;  // first interior coordinate per axis
+  int ix = 0, iy = 0, iz = 0;  // interior extent per axis
+  bool has_layer = false;
+  bool has_bc = false;
+  int bc_mode = -1, bc_dt = 1, bc_ns = 0, bc_res = 0;
+  int64_t bc_t0 = 0;
+  void* d_bc = nullptr;
+  int ex = 0, ey = 0, ez = 0;  // tile shape
+  int face_cnt[6] = {0, 0, 0, 0, 0, 0};
+  int face_start[6][3] = {};
+  int face_len[6][3] = {};
+  int nbnd = 0;
+};
+
+struct ChainHost {
+  lb_chain p;
+  int box;
+  std::vector<double> pos, vel;
+};
+
+using LbLaunch = void (*)(dim3, hipStream_t, const LbArgs&);
+using ChainLaunch = void (*)(int, hipStream_t, const BoxDesc*, const ChainDesc*, const void*,
+                             const void*, void*, void*, int, int4*, void*, void*, int*, DevState*,
+                             double, int);
+
+template <int S, int C, bool P>
+void launch_lb(dim3 g, hipStream_t s, const LbArgs& a) {
+  hipLaunchKernelGGL((k_lb<S, C, P>), g, dim3(WG), 0, s, a);
+}
+
+template <int S, bool P>
+void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc* chains,
+                  const void* a0, const void* a1, void* pos, void* vel, int total, int4* rb,
+                  void* rd, void* rp, int* bbox, DevState* st, double rho0, int pre) {
+  using T = typename Store<S>::T;
+  using R = typename Store<S>::R;
+  hipLaunchKernelGGL((k_chain<S, P>), dim3(nch), dim3(WG), 0, s, boxes, chains, (const T*)a0,
+                     (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox, st, rho0, pre);
+}
+
+template <int S>
+void launch_read(bool per, int nblk, hipStream_t s, const BoxDesc& d, const void* src, double* out,
+                 int what, int pre, double r0) {
+  using T = typename Store<S>::T;
+  if (per)
+    hipLaunchKernelGGL((k_read<S, true>), dim3(nblk), dim3(WG), 0, s, d, (const T*)src, out, what, pre, r0);
+  else
+    hipLaunchKernelGGL((k_read<S, false>), dim3(nblk), dim3(WG), 0, s, d, (const T*)src, out, what, pre, r0);
+}
+
+template <int S>
+void launch_sites(bool per, int nblk, hipStream_t s, const BoxDesc& d, const void* src,
+                  const int* xyz, int n, double* out, int pre, double r0) {
+  using T = typename Store<S>::T;
+  if (per)
+    hipLaunchKernelGGL((k_read_sites<S, true>), dim3(nblk), dim3(WG), 0, s, d, (const T*)src, xyz, n, out, pre, r0);
+  else
+    hipLaunchKernelGGL((k_read_sites<S, false>), dim3(nblk), dim3(WG), 0, s, d, (const T*)src, xyz, n, out, pre, r0);
+}
+
+template <int S>
+LbLaunch pick_lb(int coll, bool per) {
+  if (coll == 0) return per ? launch_lb<S, 0, true> : launch_lb<S, 0, false>;
+  return per ? launch_lb<S, 1, true> : launch_lb<S, 1, false>;
+}
+
+size_t store_bytes(int s) { return s == LB_STORE_F64 ? 8 : (s == LB_STORE_F32 ? 4 : 2); }
+size_t real_bytes(int s) { return s == LB_STORE_F64 ? 8 : 4; }
+
+}  // namespace
+
+struct lb_ctx {
+  lb_config cfg{};
+  std::vector<BoxHost> bx;
+  std::vector<ChainHost> ch;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t cap_stream = nullptr;
+  int S = 0, coll = 0;
+  bool per = false;
+  int fp16_exp = 14;
+  void* arena[2] = {nullptr, nullptr};
+  int64_t arena_elems = 0;
+  // device tables
+  BoxDesc* d_boxes = nullptr;
+  Item* d_items = nullptr;
+  int* d_order = nullptr;
+  int* d_box_items = nullptr;
+  int* d_box_items_off = nullptr;
+  double* d_partials = nullptr;
+  double* d_mass_mom = nullptr;
+  DevState* d_st = nullptr;
+  ChainDesc* d_chains = nullptr;
+  void* d_pos = nullptr;
+  void* d_vel = nullptr;
+  int4* d_rec_base = nullptr;
+  void* d_rec_d = nullptr;
+  void* d_rec_dp = nullptr;
+  int* d_bbox = nullptr;
+  int total_beads = 0;
+  int n_items = 0, n_entries = 0, grid = 0;
+  std::vector<Item> items;
+  std::vector<BoxDesc> h_boxes;
+  bool tables_ready = false;
+  bool chains_ready = false;
+  bool state_pre = true;
+  int64_t host_step = 0;
+  lb_status latched = LB_OK;
+  hipGraphExec_t gexec = nullptr;
+  int gsteps = 0;
+  LbLaunch lb_fn = nullptr;
+  ChainLaunch chain_fn = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  int t_steps = 0, t_lb = 0, t_chain = 0;
+  std::string err, desc;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+lb_status fail(lb_ctx* c, lb_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIPCHK(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, LB_ERR_HIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void* dalloc(lb_ctx* ctx, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  if (ctx->cfg.dev_alloc) {
+    p = ctx->cfg.dev_alloc(bytes, ctx->cfg.alloc_user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  return p;
+}
+
+void dfree(lb_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->cfg.dev_free)
+    ctx->cfg.dev_free(p, ctx->cfg.alloc_user);
+  else
+    (void)hipFree(p);
+}
+
+template <typename X>
+X* dalloc_t(lb_ctx* ctx, size_t n, bool* ok) {
+  X* p = (X*)dalloc(ctx, n * sizeof(X));
+  if (!p) *ok = false;
+  return p;
+}
+
+void drop_graph(lb_ctx* ctx) {
+  if (ctx->gexec) {
+    (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+  }
+}
+
+void default_tile(BoxHost& b) {
+  const int ix = b.ix;
+  b.ex = ix <= 128 ? ix : 64;
+  b.ey = std::max(1, std::min(b.iy, 256 / std::max(1, b.ex)));
+  if (b.ex * b.ey < 128 && b.iy > b.ey) b.ey = std::min(b.iy, (512 + b.ex - 1) / b.ex);
+  while (b.ex * b.ey > WG * MAX_SLOTS) b.ey--;
+  b.ez = std::min(b.iz, 4);
+}
+
+std::string box_key(const lb_ctx* ctx, const BoxHost& b) {
+  std::ostringstream s;
+  s << "S" << ctx->S << "C" << ctx->coll << "_" << b.dim.nx << "x" << b.dim.ny << "x" << b.dim.nz
+    << "p" << b.dim.periodic_mask;
+  return s.str();
+}
+
+void load_tune_cache(lb_ctx* ctx) {
+  if (!ctx->cfg.tune_cache) return;
+  std::ifstream in(ctx->cfg.tune_cache);
+  if (!in) return;
+  std::map<std::string, std::vector<int>> entries;
+  std::string line;
+  while (std::getline(in, line)) {
+    // {"key": "...", "ex": a, "ey": b, "ez": c}
+    auto kp = line.find("\"key\"");
+    if (kp == std::string::npos) continue;
+    auto q1 = line.find('"', line.find(':', kp) + 1);
+    auto q2 = line.find('"', q1 + 1);
+    if (q1 == std::string::npos || q2 == std::string::npos) continue;
+    std::string key = line.substr(q1 + 1, q2 - q1 - 1);
+    auto num = [&](const char* name) {
+      auto p = line.find(std::string("\"") + name + "\"");
+      if (p == std::string::npos) return -1;
+      return atoi(line.c_str() + line.find(':', p) + 1);
+    };
+    entries[key] = {num("ex"), num("ey"), num("ez")};
+  }
+  for (auto& b : ctx->bx) {
+    auto it = entries.find(box_key(ctx, b));
+    if (it == entries.end()) continue;
+    const auto& v = it->second;
+    if (v[0] >= 1 && v[1] >= 1 && v[2] >= 1 && v[0] <= b.ix && v[1] <= b.iy && v[2] <= b.iz &&
+        v[0] * v[1] <= WG * MAX_SLOTS) {
+      b.ex = v[0];
+      b.ey = v[1];
+      b.ez = v[2];
+    }
+  }
+}
+
+void free_tables(lb_ctx* ctx) {
+  dfree(ctx, ctx->d_items);
+  dfree(ctx, ctx->d_order);
+  dfree(ctx, ctx->d_box_items);
+  dfree(ctx, ctx->d_box_items_off);
+  dfree(ctx, ctx->d_partials);
+  ctx->d_items = nullptr;
+  ctx->d_order = nullptr;
+  ctx->d_box_items = nullptr;
+  ctx->d_box_items_off = nullptr;
+  ctx->d_partials = nullptr;
+  ctx->tables_ready = false;
+  drop_graph(ctx);
+}
+
+// Work list: items numbered box by box (box order), so each box owns a
+// contiguous item range (fixed-order reduction); the launch order places boxes
+// largest first and cuts the sequence into 8 contiguous pieces of equal work,
+// one per XCD (workgroup w runs on XCD w % 8), so tiles that share halo rows
+// share an L2.
+lb_status build_tables(lb_ctx* ctx, int grid_override) {
+  free_tables(ctx);
+  std::vector<Item> items;
+  std::vector<int> box_off(ctx->bx.size() + 1, 0);
+  std::vector<double> work;
+  for (size_t bi = 0; bi < ctx->bx.size(); bi++) {
+    BoxHost& b = ctx->bx[bi];
+    box_off[bi] = (int)items.size();
+    for (int k = 0; k < b.nbnd; k += BND_CHUNK) {
+      Item it{};
+      it.box = (int)bi;
+      it.kind = ITEM_BOUNDARY;
+      it.x0 = k;
+      it.ex = std::min(BND_CHUNK, b.nbnd - k);
+      items.push_back(it);
+      work.push_back(0.25 * it.ex);
+    }
+    for (int z = 0; z < b.iz; z += b.ez)
+      for (int y = 0; y < b.iy; y += b.ey)
+        for (int x = 0; x < b.ix; x += b.ex) {
+          Item it{};
+          it.box = (int)bi;
+          it.kind = ITEM_TILE;
+          it.x0 = b.ox + x;
+          it.y0 = b.oy + y;
+          it.z0 = b.oz + z;
+          it.ex = std::min(b.ex, b.ix - x);
+          it.ey = std::min(b.ey, b.iy - y);
+          it.ez = std::min(b.ez, b.iz - z);
+          items.push_back(it);
+          work.push_back((double)it.ex * it.ey * it.ez);
+        }
+  }
+  box_off[ctx->bx.size()] = (int)items.size();
+  const int n_items = (int)items.size();
+  // launch sequence: boxes by decreasing interior volume (stable)
+  std::vector<int> boxes(ctx->bx.size());
+  std::iota(boxes.begin(), boxes.end(), 0);
+  std::stable_sort(boxes.begin(), boxes.end(),
+                   [&](int a, int b) { return ctx->bx[a].interior > ctx->bx[b].interior; });
+  std::vector<int> seq;
+  seq.reserve(n_items);
+  for (int b : boxes)
+    for (int i = box_off[b]; i < box_off[b + 1]; i++) seq.push_back(i);
+  double total = 0;
+  for (double w : work) total += w;
+  std::vector<std::vector<int>> piece(8);
+  double acc = 0;
+  for (int i : seq) {
+    int x = (int)std::min(7.0, std::floor(acc / (total / 8.0 + 1e-30)));
+    piece[x].push_back(i);
+    acc += work[i];
+  }
+  size_t maxlen = 0;
+  for (auto& p : piece) maxlen = std::max(maxlen, p.size());
+  std::vector<int> order(8 * maxlen, -1);
+  for (int x = 0; x < 8; x++)
+    for (size_t j = 0; j < piece[x].size(); j++) order[8 * j + x] = piece[x][j];
+  ctx->n_items = n_items;
+  ctx->n_entries = (int)order.size();
+  int g = grid_override > 0 ? grid_override : ctx->n_entries;
+  g = std::max(8, (g + 7) / 8 * 8);
+  ctx->grid = std::min(g, std::max(8, ctx->n_entries));
+  bool ok = true;
+  ctx->d_items = dalloc_t<Item>(ctx, items.size(), &ok);
+  ctx->d_order = dalloc_t<int>(ctx, order.size(), &ok);
+  ctx->d_box_items = dalloc_t<int>(ctx, n_items, &ok);
+  ctx->d_box_items_off = dalloc_t<int>(ctx, box_off.size(), &ok);
+  ctx->d_partials = dalloc_t<double>(ctx, 4 * (size_t)n_items, &ok);
+  if (!ok) return fail(ctx, LB_ERR_OOM, "work-list allocation failed");
+  std::vector<int> ident(n_items);
+  std::iota(ident.begin(), ident.end(), 0);
+  HIPCHK(hipMemcpy(ctx->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->d_box_items, ident.data(), ident.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->d_box_items_off, box_off.data(), box_off.size() * sizeof(int),
+                   hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(ctx->d_partials, 0, 4 * sizeof(double) * (size_t)n_items));
+  ctx->items = items;
+  ctx->tables_ready = true;
+  std::ostringstream d;
+  d << "items=" << n_items << " entries=" << ctx->n_entries << " grid=" << ctx->grid << " tiles:";
+  std::map<std::string, int> seen;
+  for (auto& b : ctx->bx) {
+    std::ostringstream k;
+    k << " " << b.dim.nx << "x" << b.dim.ny << "x" << b.dim.nz << "->" << b.ex << "x" << b.ey << "x"
+      << b.ez;
+    if (!seen.count(k.str())) {
+      seen[k.str()] = 1;
+      d << k.str();
+    }
+  }
+  ctx->desc = d.str();
+  return LB_OK;
+}
+
+lb_status upload_boxes(lb_ctx* ctx) {
+  ctx->h_boxes.resize(ctx->bx.size());
+  // chains sorted by box, stable
+  std::vector<int> corder(ctx->ch.size());
+  std::iota(corder.begin(), corder.end(), 0);
+  std::stable_sort(corder.begin(), corder.end(),
+                   [&](int a, int b) { return ctx->ch[a].box < ctx->ch[b].box; });
+  std::vector<int> cfirst(ctx->bx.size(), 0), ccount(ctx->bx.size(), 0);
+  for (size_t k = 0; k < corder.size(); k++) {
+    int b = ctx->ch[corder[k]].box;
+    if (ccount[b] == 0) cfirst[b] = (int)k;
+    ccount[b]++;
+  }
+  const double s2 = std::ldexp(1.0, ctx->fp16_exp);
+  for (size_t i = 0; i < ctx->bx.size(); i++) {
+    const BoxHost& b = ctx->bx[i];
+    BoxDesc d{};
+    d.off = b.off;
+    d.nn = b.nn;
+    d.nx = b.dim.nx;
+    d.ny = b.dim.ny;
+    d.nz = b.dim.nz;
+    d.pmask = (int)(b.dim.periodic_mask & 7u);
+    d.bc_mode = b.has_bc ? b.bc_mode : -1;
+    d.bc_dt = b.bc_dt;
+    d.bc_ns = b.bc_ns;
+    d.bc_res = b.bc_res;
+    d.bc_t0 = b.bc_t0;
+    d.bc = b.d_bc;
+    d.chain_first = cfirst[i];
+    d.chain_count = ccount[i];
+    d.nbnd = b.nbnd;
+    for (int f = 0; f < 6; f++) {
+      d.face_cnt[f] = b.face_cnt[f];
+      for (int a = 0; a < 3; a++) {
+        d.face_start[f][a] = b.face_start[f][a];
+        d.face_len[f][a] = b.face_len[f][a];
+      }
+    }
+    for (int c = 0; c < 3; c++) {
+      d.enc[c] = (float)(s2 / WD[c]);
+      d.dec[c] = (float)(WD[c] / s2);
+    }
+    d.interior = (double)b.interior;
+    ctx->h_boxes[i] = d;
+  }
+  HIPCHK(hipMemcpy(ctx->d_boxes, ctx->h_boxes.data(), ctx->h_boxes.size() * sizeof(BoxDesc),
+                   hipMemcpyHostToDevice));
+  return LB_OK;
+}
+
+template <typename R>
+void to_real(const std::vector<double>& in, std::vector<R>& out) {
+  out.resize(in.size());
+  for (size_t i = 0; i < in.size(); i++) out[i] = (R)in[i];
+}
+
+// chain tables, bead state (into the parity buffer of the current step),
+// spreading records
+lb_status upload_chains(lb_ctx* ctx) {
+  dfree(ctx, ctx->d_chains);
+  dfree(ctx, ctx->d_pos);
+  dfree(ctx, ctx->d_vel);
+  dfree(ctx, ctx->d_rec_base);
+  dfree(ctx, ctx->d_rec_d);
+  dfree(ctx, ctx->d_rec_dp);
+  dfree(ctx, ctx->d_bbox);
+  ctx->d_chains = nullptr;
+  ctx->d_pos = ctx->d_vel = nullptr;
+  ctx->d_rec_base = nullptr;
+  ctx->d_rec_d = ctx->d_rec_dp = nullptr;
+  ctx->d_bbox = nullptr;
+  std::vector<int> corder(ctx->ch.size());
+  std::iota(corder.begin(), corder.end(), 0);
+  std::stable_sort(corder.begin(), corder.end(),
+                   [&](int a, int b) { return ctx->ch[a].box < ctx->ch[b].box; });
+  std::vector<ChainDesc> cd;
+  std::vector<double> rel, vel;
+  int first = 0;
+  for (int k : corder) {
+    const ChainHost& c = ctx->ch[k];
+    ChainDesc d{};
+    d.box = c.box;
+    d.first = first;
+    d.nb = c.p.n_beads;
+    d.substeps = c.p.md_substeps;
+    d.fix_com = c.p.fix_com;
+    d.zeta = c.p.zeta;
+    d.mass = c.p.mass;
+    d.fene_k = c.p.fene_k;
+    d.fene_r0 = c.p.fene_r0;
+    d.decay = std::exp(-c.p.zeta * (1.0 / c.p.md_substeps) / c.p.mass);
+    for (int a = 0; a < 3; a++) {
+      const double fl = std::floor(c.p.anchor[a]);
+      d.ai[a] = (int)fl;
+      d.af[a] = c.p.anchor[a] - fl;
+    }
+    for (int j = 0; j < d.nb; j++)
+      for (int a = 0; a < 3; a++) {
+        rel.push_back((c.pos[3 * j + a] - d.ai[a]) - d.af[a]);
+        vel.push_back(c.vel[3 * j + a]);
+      }
+    first += d.nb;
+    cd.push_back(d);
+  }
+  ctx->total_beads = first;
+  bool ok = true;
+  const size_t rb = real_bytes(ctx->S);
+  const size_t nbd = std::max(1, first);
+  ctx->d_chains = dalloc_t<ChainDesc>(ctx, std::max<size_t>(1, cd.size()), &ok);
+  ctx->d_pos = dalloc(ctx, 2 * 3 * nbd * rb);
+  ctx->d_vel = dalloc(ctx, 2 * 3 * nbd * rb);
+  ctx->d_rec_base = dalloc_t<int4>(ctx, nbd, &ok);
+  ctx->d_rec_d = dalloc(ctx, 3 * nbd * rb);
+  ctx->d_rec_dp = dalloc(ctx, 3 * nbd * rb);
+  ctx->d_bbox = dalloc_t<int>(ctx, 6 * std::max<size_t>(1, cd.size()), &ok);
+  if (!ok || !ctx->d_pos || !ctx->d_vel || !ctx->d_rec_d || !ctx->d_rec_dp)
+    return fail(ctx, LB_ERR_OOM, "chain allocation failed");
+  if (!cd.empty())
+    HIPCHK(hipMemcpy(ctx->d_chains, cd.data(), cd.size() * sizeof(ChainDesc), hipMemcpyHostToDevice));
+  const int par = (int)(ctx->host_step & 1);
+  char* pbase = (char*)ctx->d_pos + (size_t)par * 3 * nbd * rb;
+  char* vbase = (char*)ctx->d_vel + (size_t)par * 3 * nbd * rb;
+  if (first) {
+    if (ctx->S == LB_STORE_F64) {
+      HIPCHK(hipMemcpy(pbase, rel.data(), rel.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(vbase, vel.data(), vel.size() * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> r, v;
+      to_real(rel, r);
+      to_real(vel, v);
+      HIPCHK(hipMemcpy(pbase, r.data(), r.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(vbase, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
+  // empty bounding boxes until the first chain step
+  std::vector<int> bb(6 * std::max<size_t>(1, cd.size()));
+  for (size_t c = 0; c < bb.size() / 6; c++) {
+    bb[6 * c] = bb[6 * c + 1] = bb[6 * c + 2] = 1 << 30;
+    bb[6 * c + 3] = bb[6 * c + 4] = bb[6 * c + 5] = -(1 << 30);
+  }
+  HIPCHK(hipMemcpy(ctx->d_bbox, bb.data(), bb.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(ctx->d_rec_base, 0, nbd * sizeof(int4)));
+  HIPCHK(hipMemset(ctx->d_rec_d, 0, 3 * nbd * rb));
+  HIPCHK(hipMemset(ctx->d_rec_dp, 0, 3 * nbd * rb));
+  ctx->chains_ready = true;
+  return upload_boxes(ctx);
+}
+
+lb_status prepare(lb_ctx* ctx) {
+  if (!ctx->chains_ready) {
+    lb_status s = upload_chains(ctx);
+    if (s) return s;
+  }
+  if (!ctx->tables_ready) {
+    lb_status s = build_tables(ctx, ctx->grid > 0 ? ctx->grid : 0);
+    if (s) return s;
+  }
+  return LB_OK;
+}
+
+LbArgs make_args(lb_ctx* ctx, int pre, int advance, int reduce_every) {
+  LbArgs a{};
+  a.boxes = ctx->d_boxes;
+  a.items = ctx->d_items;
+  a.order = ctx->d_order;
+  a.n_entries = ctx->n_entries;
+  a.a0 = ctx->arena[0];
+  a.a1 = ctx->arena[1];
+  a.chains = ctx->d_chains;
+  a.rec_base = ctx->d_rec_base;
+  a.rec_d = ctx->d_rec_d;
+  a.rec_dp = ctx->d_rec_dp;
+  a.bbox = ctx->d_bbox;
+  a.st = ctx->d_st;
+  a.partials = ctx->d_partials;
+  a.box_items = ctx->d_box_items;
+  a.box_items_off = ctx->d_box_items_off;
+  a.mass_mom = ctx->d_mass_mom;
+  a.n_boxes = (int)ctx->bx.size();
+  a.reduce_every = reduce_every;
+  a.rho0 = ctx->cfg.rho0;
+  a.omega = 1.0 / ctx->cfg.tau;
+  a.om_bulk = 1.0 / ctx->cfg.tau_bulk;
+  a.om_ghost = ctx->cfg.ghost_rate;
+  a.pre = pre;
+  a.advance = advance;
+  return a;
+}
+
+hipEvent_t next_event(lb_ctx* ctx) {
+  if (ctx->ev_used >= (int)ctx->ev.size()) {
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    ctx->ev.push_back(e);
+  }
+  return ctx->ev[ctx->ev_used++];
+}
+
+void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed) {
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+  if (timed) {
+    e0 = next_event(ctx);
+    (void)hipEventRecord(e0, s);
+  }
+  if (!ctx->ch.empty())
+    ctx->chain_fn((int)ctx->ch.size(), s, ctx->d_boxes, ctx->d_chains, ctx->arena[0], ctx->arena[1],
+                  ctx->d_pos, ctx->d_vel, ctx->total_beads, ctx->d_rec_base, ctx->d_rec_d,
+                  ctx->d_rec_dp, ctx->d_bbox, ctx->d_st, ctx->cfg.rho0, pre);
+  if (timed) {
+    e1 = next_event(ctx);
+    (void)hipEventRecord(e1, s);
+  }
+  ctx->lb_fn(dim3(ctx->grid), s, make_args(ctx, pre, 1, ctx->cfg.reduce_every));
+  if (timed) {
+    e2 = next_event(ctx);
+    (void)hipEventRecord(e2, s);
+  }
+}
+
+void face_tables(BoxHost& b) {
+  const int n3[3] = {b.dim.nx, b.dim.ny, b.dim.nz};
+  const unsigned pm = b.dim.periodic_mask;
+  b.nbnd = 0;
+  for (int f = 0; f < 6; f++) {
+    const int a = f / 2;
+    if ((pm >> a) & 1u) {
+      b.face_cnt[f] = 0;
+      for (int k = 0; k < 3; k++) b.face_start[f][k] = 0, b.face_len[f][k] = 1;
+      continue;
+    }
+    int cnt = 1;
+    for (int k = 0; k < 3; k++) {
+      if (k == a) {
+        b.face_start[f][k] = (f % 2) ? n3[k] - 1 : 0;
+        b.face_len[f][k] = 1;
+      } else if (k < a && !((pm >> k) & 1u)) {
+        b.face_start[f][k] = 1;
+        b.face_len[f][k] = n3[k] - 2;
+      } else {
+        b.face_start[f][k] = 0;
+        b.face_len[f][k] = n3[k];
+      }
+      cnt *= b.face_len[f][k];
+    }
+    b.face_cnt[f] = cnt;
+    b.nbnd += cnt;
+  }
+}
+
+lb_status check_box(lb_ctx* ctx, int32_t box) {
+  if (!ctx) return LB_ERR_ARG;
+  if (box < 0 || box >= (int)ctx->bx.size()) return fail(ctx, LB_ERR_ARG, "box index out of range");
+  return LB_OK;
+}
+
+lb_status decode_error(lb_ctx* ctx, int key, int64_t step) {
+  const int code = key & 15, owner = key >> 4;
+  std::ostringstream m;
+  lb_status st = LB_ERR_UNSTABLE;
+  if (code == EC_BEAD_OUT) {
+    st = LB_ERR_BEAD_OUT;
+    m << "bead stencil left the interior (chain " << owner << ") at step " << step;
+  } else if (code == EC_FENE) {
+    st = LB_ERR_FENE;
+    m << "FENE bond reached R0 (chain " << owner << ") at step " << step;
+  } else {
+    m << "non-finite mass or momentum in box " << owner << " at step " << step;
+  }
+  ctx->err = m.str();
+  ctx->latched = st;
+  return st;
+}
+
+lb_status sync_state(lb_ctx* ctx, DevState* out) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(out, ctx->d_st, sizeof(DevState), hipMemcpyDeviceToHost));
+  if (out->err_key != ERR_NONE && ctx->latched == LB_OK) decode_error(ctx, out->err_key, out->step);
+  return LB_OK;
+}
+
+}  // namespace
+
+// =========================================================== C ABI
+extern "C" {
+
+lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
+  if (!cfg || !out) return LB_ERR_ARG;
+  *out = nullptr;
+  if (cfg->n_boxes < 1 || !cfg->boxes) return LB_ERR_ARG;
+  if (!(cfg->tau > 0.5) || (cfg->collision == LB_MRT && !(cfg->tau_bulk > 0.5))) return LB_ERR_ARG;
+  if (cfg->collision != LB_BGK && cfg->collision != LB_MRT) return LB_ERR_ARG;
+  if (cfg->storage < LB_STORE_F64 || cfg->storage > LB_STORE_F16DEV) return LB_ERR_ARG;
+  if (!(cfg->rho0 > 0) || cfg->reduce_every < 0 || cfg->fp16_exp < 0 || cfg->fp16_exp > 24)
+    return LB_ERR_ARG;
+  if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return LB_ERR_ARG;
+  lb_ctx* ctx = new lb_ctx();
+  ctx->cfg = *cfg;
+  if (cfg->collision == LB_BGK) {
+    ctx->cfg.tau_bulk = cfg->tau;
+    ctx->cfg.ghost_rate = 1.0 / cfg->tau;
+  }
+  ctx->cfg.boxes = nullptr;
+  ctx->S = cfg->storage;
+  ctx->coll = cfg->collision;
+  ctx->fp16_exp = cfg->fp16_exp ? cfg->fp16_exp : 14;
+  int64_t off = 0;
+  for (int i = 0; i < cfg->n_boxes; i++) {
+    BoxHost b;
+    b.dim = cfg->boxes[i];
+    const int n3[3] = {b.dim.nx, b.dim.ny, b.dim.nz};
+    int64_t nn = 1;
+    for (int a = 0; a < 3; a++) {
+      const bool p = (b.dim.periodic_mask >> a) & 1u;
+      if (n3[a] < (p ? 1 : 3) || n3[a] > 4096) {
+        delete ctx;
+        return LB_ERR_ARG;
+      }
+      nn *= n3[a];
+    }
+    if (nn * Q >= ((int64_t)1 << 40) || nn >= ((int64_t)1 << 31)) {
+      delete ctx;
+      return LB_ERR_ARG;
+    }
+    const unsigned pm = b.dim.periodic_mask & 7u;
+    b.dim.periodic_mask = pm;
+    b.ox = (pm & 1) ? 0 : 1;
+    b.oy = (pm & 2) ? 0 : 1;
+    b.oz = (pm & 4) ? 0 : 1;
+    b.ix = (pm & 1) ? n3[0] : n3[0] - 2;
+    b.iy = (pm & 2) ? n3[1] : n3[1] - 2;
+    b.iz = (pm & 4) ? n3[2] : n3[2] - 2;
+    b.interior = (int64_t)b.ix * b.iy * b.iz;
+    b.has_layer = pm != 7u;
+    b.nn = nn;
+    b.off = off;
+    off += nn * Q;
+    if (pm) ctx->per = true;
+    face_tables(b);
+    default_tile(b);
+    ctx->bx.push_back(b);
+  }
+  ctx->arena_elems = off;
+  if (cfg->stream) {
+    ctx->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return LB_ERR_HIP;
+    }
+    ctx->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    lb_free(ctx);
+    return LB_ERR_HIP;
+  }
+  const size_t sb = store_bytes(ctx->S);
+  ctx->arena[0] = dalloc(ctx, (size_t)off * sb);
+  ctx->arena[1] = dalloc(ctx, (size_t)off * sb);
+  bool ok = ctx->arena[0] && ctx->arena[1];
+  ctx->d_boxes = dalloc_t<BoxDesc>(ctx, ctx->bx.size(), &ok);
+  ctx->d_mass_mom = dalloc_t<double>(ctx, 5 * ctx->bx.size(), &ok);
+  ctx->d_st = dalloc_t<DevState>(ctx, 1, &ok);
+  if (!ok) {
+    lb_free(ctx);
+    return LB_ERR_OOM;
+  }
+  // rest state: all deviations zero, in both buffers
+  if (hipMemset(ctx->arena[0], 0, (size_t)off * sb) != hipSuccess ||
+      hipMemset(ctx->arena[1], 0, (size_t)off * sb) != hipSuccess ||
+      hipMemset(ctx->d_mass_mom, 0, 5 * sizeof(double) * ctx->bx.size()) != hipSuccess) {
+    lb_free(ctx);
+    return LB_ERR_HIP;
+  }
+  DevState st{};
+  st.step = 0;
+  st.err_key = ERR_NONE;
+  st.done = 0;
+  if (hipMemcpy(ctx->d_st, &st, sizeof(st), hipMemcpyHostToDevice) != hipSuccess) {
+    lb_free(ctx);
+    return LB_ERR_HIP;
+  }
+  switch (ctx->S) {
+    case 0: ctx->lb_fn = pick_lb<0>(ctx->coll, ctx->per); break;
+    case 1: ctx->lb_fn = pick_lb<1>(ctx->coll, ctx->per); break;
+    default: ctx->lb_fn = pick_lb<2>(ctx->coll, ctx->per); break;
+  }
+  if (ctx->S == 0)
+    ctx->chain_fn = ctx->per ? launch_chain<0, true> : launch_chain<0, false>;
+  else if (ctx->S == 1)
+    ctx->chain_fn = ctx->per ? launch_chain<1, true> : launch_chain<1, false>;
+  else
+    ctx->chain_fn = ctx->per ? launch_chain<2, true> : launch_chain<2, false>;
+  load_tune_cache(ctx);
+  if (upload_boxes(ctx) != LB_OK) {
+    lb_free(ctx);
+    return LB_ERR_HIP;
+  }
+  *out = ctx;
+  return LB_OK;
+}
+
+lb_status lb_set_initial(lb_ctx* ctx, int32_t box, const double* u) {
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  if (!ctx->state_pre) return fail(ctx, LB_ERR_STATE, "lb_set_initial after the first lb_step");
+  BoxHost& b = ctx->bx[box];
+  double* d_u = nullptr;
+  if (u) {
+    d_u = (double*)dalloc(ctx, 3 * sizeof(double) * b.nn);
+    if (!d_u) return fail(ctx, LB_ERR_OOM, "initial-field staging allocation failed");
+    HIPCHK(hipMemcpyAsync(d_u, u, 3 * sizeof(double) * b.nn, hipMemcpyHostToDevice, ctx->stream));
+  }
+  const int par = (int)(ctx->host_step & 1);
+  const int nblk = (int)std::min<int64_t>((b.nn + WG - 1) / WG, 65535);
+  const BoxDesc& d = ctx->h_boxes[box];
+  const size_t sb = store_bytes(ctx->S);
+  void* dst = (char*)ctx->arena[par] + (size_t)b.off * sb;
+  const int mode = u ? 1 : 2;
+  switch (ctx->S) {
+    case 0: hipLaunchKernelGGL(k_set_pre<0>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (double*)dst, d_u, mode, ctx->cfg.rho0); break;
+    case 1: hipLaunchKernelGGL(k_set_pre<1>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (float*)dst, d_u, mode, ctx->cfg.rho0); break;
+    default: hipLaunchKernelGGL(k_set_pre<2>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (_Float16*)dst, d_u, mode, ctx->cfg.rho0); break;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  dfree(ctx, d_u);
+  return LB_OK;
+}
+
+lb_status lb_set_boundary(lb_ctx* ctx, int32_t box, const lb_boundary* bc) {
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  if (!bc || !bc->data || bc->dt < 1 || bc->n_samples < 1)
+    return fail(ctx, LB_ERR_ARG, "invalid boundary description");
+  if (bc->mode != LB_BC_AFFINE && bc->mode != LB_BC_SAMPLED)
+    return fail(ctx, LB_ERR_ARG, "unknown boundary mode");
+  if (bc->mode == LB_BC_SAMPLED && (bc->res < 2 || bc->res > 8192))
+    return fail(ctx, LB_ERR_ARG, "sampled boundary needs res >= 2");
+  BoxHost& b = ctx->bx[box];
+  size_t per = bc->mode == LB_BC_AFFINE ? 9 : (size_t)6 * bc->res * bc->res * 3;
+  size_t n = per * bc->n_samples;
+  void* dptr = nullptr;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (bc->mode == LB_BC_AFFINE || ctx->S == LB_STORE_F64) {
+    std::vector<double> v(n);
+    if (bc->mode == LB_BC_SAMPLED && !bc->data_is_f64) {
+      const float* f = (const float*)bc->data;
+      for (size_t i = 0; i < n; i++) v[i] = f[i];
+    } else {
+      std::memcpy(v.data(), bc->data, n * sizeof(double));
+    }
+    dptr = dalloc(ctx, n * sizeof(double));
+    if (!dptr) return fail(ctx, LB_ERR_OOM, "boundary allocation failed");
+    HIPCHK(hipMemcpy(dptr, v.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> v(n);
+    if (bc->data_is_f64) {
+      const double* f = (const double*)bc->data;
+      for (size_t i = 0; i < n; i++) v[i] = (float)f[i];
+    } else {
+      std::memcpy(v.data(), bc->data, n * sizeof(float));
+    }
+    dptr = dalloc(ctx, n * sizeof(float));
+    if (!dptr) return fail(ctx, LB_ERR_OOM, "boundary allocation failed");
+    HIPCHK(hipMemcpy(dptr, v.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  }
+  dfree(ctx, b.d_bc);
+  b.d_bc = dptr;
+  b.has_bc = true;
+  b.bc_mode = bc->mode;
+  b.bc_t0 = bc->t0;
+  b.bc_dt = bc->dt;
+  b.bc_ns = bc->n_samples;
+  b.bc_res = bc->res;
+  drop_graph(ctx);
+  return upload_boxes(ctx);
+}
+
+lb_status lb_couple_chain(lb_ctx* ctx, int32_t box, const lb_chain* chain, const double* pos,
+                          const double* vel) {
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  if (!ctx->state_pre) return fail(ctx, LB_ERR_STATE, "lb_couple_chain after the first lb_step");
+  if (!chain || !pos || chain->n_beads < 1 || chain->n_beads > WG || chain->md_substeps < 1 ||
+      !(chain->zeta > 0) || !(chain->mass > 0) || !(chain->fene_r0 > 0) || chain->fene_k < 0)
+    return fail(ctx, LB_ERR_ARG, "invalid chain (1 <= n_beads <= 256, zeta, mass, R0 > 0)");
+  int count = 0;
+  for (auto& c : ctx->ch) count += c.box == box;
+  if (count >= MAX_BOX_CHAINS) return fail(ctx, LB_ERR_ARG, "at most 64 chains per box");
+  ChainHost c;
+  c.p = *chain;
+  c.box = box;
+  c.pos.assign(pos, pos + 3 * chain->n_beads);
+  c.vel.assign(3 * chain->n_beads, 0.0);
+  if (vel) c.vel.assign(vel, vel + 3 * chain->n_beads);
+  ctx->ch.push_back(c);
+  ctx->chains_ready = false;
+  drop_graph(ctx);
+  return LB_OK;
+}
+
+lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
+  if (!ctx || n_steps < 0) return LB_ERR_ARG;
+  if (ctx->latched) return ctx->latched;
+  if (n_steps == 0) return LB_OK;
+  for (auto& b : ctx->bx) {
+    if (!b.has_layer) continue;
+    if (!b.has_bc) return fail(ctx, LB_ERR_STATE, "a box with a boundary layer has no boundary");
+    const int64_t first = ctx->host_step, last = ctx->host_step + n_steps - 1;
+    const int64_t end = b.bc_t0 + (int64_t)(b.bc_ns - 1) * b.bc_dt;
+    if (first < b.bc_t0 || last > end)
+      return fail(ctx, LB_ERR_ARG, "steps beyond the boundary samples (no extrapolation)");
+  }
+  lb_status s = prepare(ctx);
+  if (s) return s;
+  int left = n_steps;
+  const bool timed = ctx->timing;
+  if (timed) {
+    ctx->ev_used = 0;
+    ctx->t_steps = 0;
+  }
+  if (ctx->state_pre) {
+    enqueue_step(ctx, ctx->stream, 1, timed);
+    HIPCHK(hipGetLastError());
+    ctx->state_pre = false;
+    left--;
+    if (timed) ctx->t_steps++;
+  }
+  const int gs = ctx->cfg.graph_steps;
+  if (gs > 0 && !timed) {
+    while (left >= gs) {
+      if (!ctx->gexec || ctx->gsteps != gs) {
+        drop_graph(ctx);
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+        for (int k = 0; k < gs; k++) enqueue_step(ctx, ctx->cap_stream, 0, false);
+        HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
+        HIPCHK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        ctx->gsteps = gs;
+      }
+      HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+      left -= gs;
+    }
+  }
+  while (left > 0) {
+    enqueue_step(ctx, ctx->stream, 0, timed);
+    left--;
+    if (timed) ctx->t_steps++;
+  }
+  HIPCHK(hipGetLastError());
+  ctx->host_step += n_steps;
+  return LB_OK;
+}
+
+lb_status lb_sync(lb_ctx* ctx) {
+  if (!ctx) return LB_ERR_ARG;
+  DevState st;
+  lb_status s = sync_state(ctx, &st);
+  if (s) return s;
+  return ctx->latched;
+}
+
+lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, size_t dst_bytes,
+                         int32_t dst_on_device) {
+  if (!ctx || !dst) return LB_ERR_ARG;
+  if (field != LB_F_STEP) {
+    lb_status s = check_box(ctx, box);
+    if (s) return s;
+  }
+  lb_status s = prepare(ctx);
+  if (s) return s;
+  DevState st;
+  s = sync_state(ctx, &st);
+  if (s) return s;
+  const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (field == LB_F_STEP) {
+    if (dst_bytes != sizeof(int64_t)) return fail(ctx, LB_ERR_BUFSIZE, "LB_F_STEP needs 8 bytes");
+    int64_t v = st.step;
+    HIPCHK(hipMemcpy(dst, &v, 8, dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    return ctx->latched;
+  }
+  BoxHost& b = ctx->bx[box];
+  if (field == LB_F_MASS_MOM) {
+    if (dst_bytes != 5 * sizeof(double)) return fail(ctx, LB_ERR_BUFSIZE, "LB_F_MASS_MOM needs 40 bytes");
+    HIPCHK(hipMemcpy(dst, ctx->d_mass_mom + 5 * box, 5 * sizeof(double), kind));
+    return ctx->latched;
+  }
+  const int par = (int)(st.step & 1);
+  if (field == LB_F_BEAD_POS || field == LB_F_BEAD_VEL) {
+    int c0 = ctx->h_boxes[box].chain_first, c1 = c0 + ctx->h_boxes[box].chain_count;
+    int nb = 0;
+    for (auto& c : ctx->ch) nb += (c.box == box) ? c.p.n_beads : 0;
+    if (dst_bytes != (size_t)nb * 3 * sizeof(double))
+      return fail(ctx, LB_ERR_BUFSIZE, "bead buffer must be [beads][3] doubles");
+    if (nb == 0) return ctx->latched;
+    double* tmp = (double*)dalloc(ctx, (size_t)nb * 3 * sizeof(double));
+    if (!tmp) return fail(ctx, LB_ERR_OOM, "readout allocation failed");
+    const size_t rb = real_bytes(ctx->S);
+    const size_t nbd = std::max(1, ctx->total_beads);
+    const void* src = (char*)(field == LB_F_BEAD_POS ? ctx->d_pos : ctx->d_vel) + (size_t)par * 3 * nbd * rb;
+    if (ctx->S == 0)
+      hipLaunchKernelGGL(k_read_beads<double>, dim3(1), dim3(WG), 0, ctx->stream, ctx->d_chains, c0, c1,
+                         (const double*)src, tmp, field == LB_F_BEAD_POS ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_read_beads<float>, dim3(1), dim3(WG), 0, ctx->stream, ctx->d_chains, c0, c1,
+                         (const float*)src, tmp, field == LB_F_BEAD_POS ? 1 : 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(dst, tmp, (size_t)nb * 3 * sizeof(double), kind));
+    dfree(ctx, tmp);
+    return ctx->latched;
+  }
+  int what;
+  size_t need;
+  if (field == LB_F_POP) {
+    what = 0;
+    need = (size_t)Q * b.nn * sizeof(double);
+  } else if (field == LB_F_RHO) {
+    what = 1;
+    need = (size_t)b.nn * sizeof(double);
+  } else if (field == LB_F_U) {
+    what = 2;
+    need = (size_t)3 * b.nn * sizeof(double);
+  } else {
+    return fail(ctx, LB_ERR_ARG, "unknown field");
+  }
+  if (dst_bytes != need) return fail(ctx, LB_ERR_BUFSIZE, "field buffer size mismatch");
+  double* out = dst_on_device ? (double*)dst : (double*)dalloc(ctx, need);
+  if (!out) return fail(ctx, LB_ERR_OOM, "readout allocation failed");
+  const size_t sb = store_bytes(ctx->S);
+  const void* src = (char*)ctx->arena[par] + (size_t)b.off * sb;
+  const int nblk = (int)std::min<int64_t>((b.nn + WG - 1) / WG, 65535);
+  const int pre = ctx->state_pre ? 1 : 0;
+  const BoxDesc& d = ctx->h_boxes[box];
+  const double r0 = ctx->cfg.rho0;
+  if (ctx->S == 0) launch_read<0>(ctx->per, nblk, ctx->stream, d, src, out, what, pre, r0);
+  else if (ctx->S == 1) launch_read<1>(ctx->per, nblk, ctx->stream, d, src, out, what, pre, r0);
+  else launch_read<2>(ctx->per, nblk, ctx->stream, d, src, out, what, pre, r0);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!dst_on_device) {
+    HIPCHK(hipMemcpy(dst, out, need, hipMemcpyDeviceToHost));
+    dfree(ctx, out);
+  }
+  return ctx->latched;
+}
+
+lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out) {
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  if (n < 0 || (n > 0 && (!xyz || !out))) return fail(ctx, LB_ERR_ARG, "invalid site list");
+  if (n == 0) return LB_OK;
+  const BoxHost& b = ctx->bx[box];
+  for (int k = 0; k < n; k++) {
+    const int x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
+    const bool in = ((b.dim.periodic_mask & 1) ? (x >= 0 && x < b.dim.nx) : (x >= 1 && x <= b.dim.nx - 2)) &&
+                    ((b.dim.periodic_mask & 2) ? (y >= 0 && y < b.dim.ny) : (y >= 1 && y <= b.dim.ny - 2)) &&
+                    ((b.dim.periodic_mask & 4) ? (z >= 0 && z < b.dim.nz) : (z >= 1 && z <= b.dim.nz - 2));
+    if (!in) return fail(ctx, LB_ERR_ARG, "site outside the interior");
+  }
+  s = prepare(ctx);
+  if (s) return s;
+  DevState st;
+  s = sync_state(ctx, &st);
+  if (s) return s;
+  int* d_xyz = (int*)dalloc(ctx, (size_t)3 * n * sizeof(int));
+  double* d_out = (double*)dalloc(ctx, (size_t)Q * n * sizeof(double));
+  if (!d_xyz || !d_out) return fail(ctx, LB_ERR_OOM, "site readout allocation failed");
+  HIPCHK(hipMemcpy(d_xyz, xyz, (size_t)3 * n * sizeof(int), hipMemcpyHostToDevice));
+  const int par = (int)(st.step & 1);
+  const size_t sb = store_bytes(ctx->S);
+  const void* src = (char*)ctx->arena[par] + (size_t)b.off * sb;
+  const BoxDesc& d = ctx->h_boxes[box];
+  const int pre = ctx->state_pre ? 1 : 0;
+  const int nblk = (n + WG - 1) / WG;
+  const double r0 = ctx->cfg.rho0;
+  if (ctx->S == 0) launch_sites<0>(ctx->per, nblk, ctx->stream, d, src, d_xyz, n, d_out, pre, r0);
+  else if (ctx->S == 1) launch_sites<1>(ctx->per, nblk, ctx->stream, d, src, d_xyz, n, d_out, pre, r0);
+  else launch_sites<2>(ctx->per, nblk, ctx->stream, d, src, d_xyz, n, d_out, pre, r0);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(out, d_out, (size_t)Q * n * sizeof(double), hipMemcpyDeviceToHost));
+  dfree(ctx, d_xyz);
+  dfree(ctx, d_out);
+  return ctx->latched;
+}
+
+lb_status lb_write_state(lb_ctx* ctx, int32_t box, lb_field field, const void* src, size_t bytes) {
+  if (!ctx || !src) return LB_ERR_ARG;
+  if (!ctx->state_pre) return fail(ctx, LB_ERR_STATE, "lb_write_state after the first lb_step");
+  if (field == LB_F_STEP) {
+    if (bytes != 8) return fail(ctx, LB_ERR_BUFSIZE, "LB_F_STEP needs 8 bytes");
+    int64_t n;
+    std::memcpy(&n, src, 8);
+    if (n < 0) return fail(ctx, LB_ERR_ARG, "negative step");
+    const int old_par = (int)(ctx->host_step & 1), new_par = (int)(n & 1);
+    if (old_par != new_par) {
+      const size_t sb = store_bytes(ctx->S);
+      HIPCHK(hipMemcpy(ctx->arena[new_par], ctx->arena[old_par], (size_t)ctx->arena_elems * sb,
+                       hipMemcpyDeviceToDevice));
+      ctx->chains_ready = false;  // bead state is re-uploaded into the new parity
+    }
+    ctx->host_step = n;
+    DevState st{};
+    st.step = n;
+    st.err_key = ERR_NONE;
+    HIPCHK(hipMemcpy(ctx->d_st, &st, sizeof(st), hipMemcpyHostToDevice));
+    return LB_OK;
+  }
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  BoxHost& b = ctx->bx[box];
+  if (field == LB_F_BEAD_POS || field == LB_F_BEAD_VEL) {
+    size_t nb = 0;
+    for (auto& c : ctx->ch) nb += (c.box == box) ? c.p.n_beads : 0;
+    if (bytes != nb * 3 * sizeof(double)) return fail(ctx, LB_ERR_BUFSIZE, "bead state size mismatch");
+    const double* p = (const double*)src;
+    size_t o = 0;
+    for (auto& c : ctx->ch) {
+      if (c.box != box) continue;
+      auto& v = field == LB_F_BEAD_POS ? c.pos : c.vel;
+      v.assign(p + o, p + o + 3 * c.p.n_beads);
+      o += 3 * c.p.n_beads;
+    }
+    ctx->chains_ready = false;
+    return LB_OK;
+  }
+  if (field != LB_F_POP) return fail(ctx, LB_ERR_ARG, "only POP, BEAD_POS, BEAD_VEL, STEP are writable");
+  if (bytes != (size_t)Q * b.nn * sizeof(double)) return fail(ctx, LB_ERR_BUFSIZE, "POP size mismatch");
+  double* d_in = (double*)dalloc(ctx, bytes);
+  if (!d_in) return fail(ctx, LB_ERR_OOM, "staging allocation failed");
+  HIPCHK(hipMemcpy(d_in, src, bytes, hipMemcpyHostToDevice));
+  const int par = (int)(ctx->host_step & 1);
+  const size_t sb = store_bytes(ctx->S);
+  void* dst = (char*)ctx->arena[par] + (size_t)b.off * sb;
+  const int nblk = (int)std::min<int64_t>((b.nn + WG - 1) / WG, 65535);
+  const BoxDesc& d = ctx->h_boxes[box];
+  switch (ctx->S) {
+    case 0: hipLaunchKernelGGL(k_set_pre<0>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (double*)dst, d_in, 0, ctx->cfg.rho0); break;
+    case 1: hipLaunchKernelGGL(k_set_pre<1>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (float*)dst, d_in, 0, ctx->cfg.rho0); break;
+    default: hipLaunchKernelGGL(k_set_pre<2>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (_Float16*)dst, d_in, 0, ctx->cfg.rho0); break;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  dfree(ctx, d_in);
+  return LB_OK;
+}
+
+lb_status lb_set_timing(lb_ctx* ctx, int32_t on) {
+  if (!ctx) return LB_ERR_ARG;
+  ctx->timing = on != 0;
+  return LB_OK;
+}
+
+lb_status lb_get_timing(lb_ctx* ctx, double out[4]) {
+  if (!ctx || !out) return LB_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double step_ms = 0, lb_ms = 0, ch_ms = 0;
+  const int n = ctx->ev_used / 3;
+  for (int k = 0; k < n; k++) {
+    float a = 0, b = 0, c = 0;
+    HIPCHK(hipEventElapsedTime(&a, ctx->ev[3 * k], ctx->ev[3 * k + 1]));
+    HIPCHK(hipEventElapsedTime(&b, ctx->ev[3 * k + 1], ctx->ev[3 * k + 2]));
+    ch_ms += a;
+    lb_ms += b;
+    if (k + 1 < n) {
+      HIPCHK(hipEventElapsedTime(&c, ctx->ev[3 * k], ctx->ev[3 * (k + 1)]));
+      step_ms += c;
+    }
+  }
+  double bytes = 0;
+  for (auto& b : ctx->bx) bytes += 2.0 * Q * store_bytes(ctx->S) * (double)b.interior;
+  out[0] = n > 1 ? step_ms / (n - 1) : (n ? (ch_ms + lb_ms) : 0);
+  out[1] = n ? lb_ms / n : 0;
+  out[2] = (n && !ctx->ch.empty()) ? ch_ms / n : 0;
+  out[3] = bytes;
+  return LB_OK;
+}
+
+lb_status lb_autotune(lb_ctx* ctx, int32_t trials) {
+  if (!ctx || trials < 1) return LB_ERR_ARG;
+  if (ctx->latched) return ctx->latched;
+  lb_status s = prepare(ctx);
+  if (s) return s;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto time_now = [&](double* ms) -> lb_status {
+    LbArgs a = make_args(ctx, 0, 0, 0);
+    ctx->lb_fn(dim3(ctx->grid), ctx->stream, a);  // warm-up
+    HIPCHK(hipEventRecord(e0, ctx->stream));
+    for (int t = 0; t < trials; t++) ctx->lb_fn(dim3(ctx->grid), ctx->stream, a);
+    HIPCHK(hipEventRecord(e1, ctx->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float f = 0;
+    HIPCHK(hipEventElapsedTime(&f, e0, e1));
+    *ms = f / trials;
+    return LB_OK;
+  };
+  // coordinate descent over box-size classes, then over the persistent grid size
+  std::map<std::string, std::vector<int>> classes;
+  for (size_t i = 0; i < ctx->bx.size(); i++) classes[box_key(ctx, ctx->bx[i])].push_back((int)i);
+  double best = 0;
+  s = build_tables(ctx, 0);
+  if (s) return s;
+  s = time_now(&best);
+  if (s) return s;
+  for (auto& kv : classes) {
+    BoxHost& ref = ctx->bx[kv.second[0]];
+    std::vector<std::array<int, 3>> cands;
+    std::vector<int> exs;
+    for (int ex : {ref.ix, 32, 64, 128, 256})
+      if (ex >= 1 && ex <= ref.ix && std::find(exs.begin(), exs.end(), ex) == exs.end()) exs.push_back(ex);
+    for (int ex : exs)
+      for (int pl : {256, 512, 1024}) {
+        int ey = std::max(1, std::min(ref.iy, pl / ex));
+        if (ex * ey > WG * MAX_SLOTS) continue;
+        for (int ez : {1, 2, 4, 8, 16}) {
+          if (ez > ref.iz) continue;
+          cands.push_back({ex, ey, ez});
+        }
+      }
+    std::array<int, 3> keep = {ref.ex, ref.ey, ref.ez};
+    for (auto& c : cands) {
+      for (int i : kv.second) ctx->bx[i].ex = c[0], ctx->bx[i].ey = c[1], ctx->bx[i].ez = c[2];
+      s = build_tables(ctx, 0);
+      if (s) return s;
+      double ms;
+      s = time_now(&ms);
+      if (s) return s;
+      if (ms < best) {
+        best = ms;
+        keep = c;
+      }
+    }
+    for (int i : kv.second) ctx->bx[i].ex = keep[0], ctx->bx[i].ey = keep[1], ctx->bx[i].ez = keep[2];
+  }
+  s = build_tables(ctx, 0);
+  if (s) return s;
+  int best_grid = ctx->grid;
+  for (int g : {2048, 4096, 8192, 16384}) {
+    if (g >= ctx->n_entries) continue;
+    s = build_tables(ctx, g);
+    if (s) return s;
+    double ms;
+    s = time_now(&ms);
+    if (s) return s;
+    if (ms < best) {
+      best = ms;
+      best_grid = ctx->grid;
+    }
+  }
+  s = build_tables(ctx, best_grid);
+  if (s) return s;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ctx->cfg.tune_cache) {
+    std::ofstream o(ctx->cfg.tune_cache, std::ios::app);
+    for (auto& kv : classes) {
+      const BoxHost& b = ctx->bx[kv.second[0]];
+      o << "{\"key\": \"" << kv.first << "\", \"ex\": " << b.ex << ", \"ey\": " << b.ey
+        << ", \"ez\": " << b.ez << "}\n";
+    }
+  }
+  return LB_OK;
+}
+
+const char* lb_describe(const lb_ctx* ctx) { return ctx ? ctx->desc.c_str() : ""; }
+
+const char* lb_last_error(const lb_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void lb_free(lb_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  drop_graph(ctx);
+  free_tables(ctx);
+  for (auto& b : ctx->bx) dfree(ctx, b.d_bc);
+  dfree(ctx, ctx->arena[0]);
+  dfree(ctx, ctx->arena[1]);
+  dfree(ctx, ctx->d_boxes);
+  dfree(ctx, ctx->d_mass_mom);
+  dfree(ctx, ctx->d_st);
+  dfree(ctx, ctx->d_chains);
+  dfree(ctx, ctx->d_pos);
+  dfree(ctx, ctx->d_vel);
+  dfree(ctx, ctx->d_rec_base);
+  dfree(ctx, ctx->d_rec_d);
+  dfree(ctx, ctx->d_rec_dp);
+  dfree(ctx, ctx->d_bbox);
+  for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""Shared test setup: build one case on both the FP64 oracle and the GPU library
+from the same seeded inputs, and compare what they return."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_0809_4958_amd import inputs
+
+
+def bead_mass(n_beads):
+    """Bead mass: the whole chain weighs half a fluid node (rho0 a^3 = 1).  The
+    exact per-step friction update hands m (V - u) to the fluid; once the
+    chain (kT = 0, no excluded volume) has collapsed onto a few nodes, the
+    relative-velocity map multiplies by about -(n_beads m)/M with M >= 1 the
+    fluid mass seen by the stencil, so n_beads m < 1 is required."""
+    return 0.5 / n_beads
+
+
+def rel_l2(a, b, mask=None):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if mask is not None:
+        a = a[mask]
+        b = b[mask]
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
+
+
+class Case:
+    """Inputs of one box: dims, collision, boundary, chains, initial field."""
+
+    def __init__(self, dims, collision=oracle.BGK, tau=0.8, tau_bulk=None, ghost_rate=1.0,
+                 periodic_mask=0, bc=None, u0=None, chains=(), reduce_every=0):
+        self.dims = tuple(dims)
+        self.collision = collision
+        self.tau = tau
+        self.tau_bulk = tau if tau_bulk is None else tau_bulk
+        self.ghost_rate = ghost_rate
+        self.pmask = periodic_mask
+        self.bc = bc              # (mode, data, t0, dt, res)
+        self.u0 = u0
+        self.chains = list(chains)  # dicts: pos, vel, substeps, fix_com, zeta, fene_k, fene_r0, anchor
+        self.reduce_every = reduce_every
+
+    def oracle_box(self):
+        ob = oracle.OracleBox(self.dims, collision=self.collision, tau=self.tau,
+                              tau_bulk=self.tau_bulk, ghost_rate=self.ghost_rate,
+                              periodic_mask=self.pmask, reduce_every=self.reduce_every)
+        ob.set_initial(self.u0)
+        if self.bc is not None:
+            mode, data, t0, dt, res = self.bc
+            ob.set_boundary(mode, np.asarray(data, dtype=np.float64), t0=t0, dt=dt, res=res)
+        for c in self.chains:
+            ob.add_chain(c["pos"], c.get("vel"), substeps=c.get("substeps", 10),
+                         fix_com=c.get("fix_com", True), zeta=c.get("zeta", 5.0),
+                         mass=c.get("mass", bead_mass(len(c["pos"]))),
+                         fene_k=c.get("fene_k", 1.0), fene_r0=c.get("fene_r0", 2.0),
+                         anchor=c.get("anchor"))
+        return ob
+
+    def add_to(self, ctx, box=0):
+        ctx.set_initial(box, self.u0)
+        if self.bc is not None:
+            mode, data, t0, dt, res = self.bc
+            ctx.set_boundary(box, mode, data, t0=t0, dt=dt, res=res)
+        for c in self.chains:
+            ctx.couple_chain(box, c["pos"], c.get("vel"), substeps=c.get("substeps", 10),
+                             fix_com=c.get("fix_com", True), zeta=c.get("zeta", 5.0),
+                             mass=c.get("mass", bead_mass(len(c["pos"]))),
+                             fene_k=c.get("fene_k", 1.0), fene_r0=c.get("fene_r0", 2.0),
+                             anchor=c.get("anchor"))
+
+    @property
+    def n_beads(self):
+        return sum(len(c["pos"]) for c in self.chains)
+
+
+def cfg0_case(n_steps=200, n=32):
+    """Plain FP64 configuration: n^3 BGK tau = 0.8, rest start, affine OU
+    boundary (correlation 500 steps, rms 1e-3), one 16-bead FENE chain
+    (k = 1, R0 = 2, zeta = 5) at the box centre."""
+    A = inputs.ou_strain(n_steps, inputs.rng(0, 0), corr_steps=500.0, rms=1e-3)
+    xc = np.full(3, (n - 1) / 2.0)
+    pos, vel = inputs.chain_init(16, xc, inputs.rng(0, 2))
+    chain = dict(pos=pos, vel=vel, substeps=10, fix_com=True, zeta=5.0, fene_k=1.0, fene_r0=2.0,
+                 anchor=xc)
+    return Case((n, n, n), collision=oracle.BGK, tau=0.8, bc=(oracle.BC_AFFINE, A, 0, 1, 0),
+                chains=[chain], reduce_every=50)
+
+
+def ks_case(n, n_steps, dt=20, res=17, tau=0.6, n_beads=16, config_idx=1, box_idx=0,
+            collision=oracle.MRT, f32_samples=True):
+    """KS-driven box (tracer frame, Eq. (1) scaling, width 2 eta): MRT, sampled
+    corner-aligned face grid every dt steps, one chain at the centre."""
+    units, u0, faces = inputs.ks_box_inputs(config_idx, box_idx, n=n, tau=tau, n_steps=n_steps,
+                                            dt=dt, res=res)
+    if f32_samples:
+        faces = faces.astype(np.float32)
+    xc = np.full(3, (n - 1) / 2.0)
+    chains = []
+    if n_beads:
+        pos, vel = inputs.chain_init(n_beads, xc, inputs.rng(config_idx, 2))
+        chains.append(dict(pos=pos, vel=vel, anchor=xc))
+    return Case((n, n, n), collision=collision, tau=tau, tau_bulk=tau, ghost_rate=1.0,
+                bc=(oracle.BC_SAMPLED, faces, 0, dt, res), u0=u0, chains=chains, reduce_every=100)

@@ -1,0 +1,270 @@
+"""GPU parity: the HIP library against the FP64 oracle on identical seeded inputs.
+
+Tolerances (relative L2 over the interior, velocity u = j/rho):
+FP64 storage 1e-12, FP32 storage 1e-5, FP16-deviation storage 1e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from lbcase import Case, cfg0_case, ks_case, rel_l2
+from paper_0809_4958_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_0809_4958_amd.lbm")
+
+STORE = {"f64": 0, "f32": 1, "f16": 2}
+TOL_U = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_ctx(case, storage="f64", **kw):
+    ctx = lbm.Context([case.dims + (case.pmask,)], collision=case.collision, tau=case.tau,
+                      tau_bulk=case.tau_bulk, ghost_rate=case.ghost_rate, storage=STORE[storage],
+                      reduce_every=case.reduce_every, **kw)
+    case.add_to(ctx, 0)
+    return ctx
+
+
+def compare(ctx, ob, case, storage, box=0):
+    mask = ob.interior_mask()
+    _, u_o = ob.rho_u()
+    u_g = ctx.read(box, lbm.F_U)
+    f_o = ob.pop()
+    f_g = ctx.read(box, lbm.F_POP)
+    _, w = oracle.lattice()
+    dev_o = f_o - w[:, None, None, None]
+    dev_g = f_g - w[:, None, None, None]
+    res = {"u": rel_l2(u_g, u_o, mask), "pop": rel_l2(dev_g[:, mask], dev_o[:, mask])}
+    if case.n_beads:
+        p_o, v_o = ob.beads()
+        p_g = ctx.read(box, lbm.F_BEAD_POS, n_beads=case.n_beads)
+        v_g = ctx.read(box, lbm.F_BEAD_VEL, n_beads=case.n_beads)
+        anc = np.concatenate([np.broadcast_to(c["anchor"], (len(c["pos"]), 3)) for c in case.chains])
+        res["bead_pos"] = rel_l2(p_g - anc, p_o - anc)
+        res["bead_vel"] = rel_l2(v_g, v_o) if np.linalg.norm(v_o) > 0 else np.abs(v_g).max()
+    return res
+
+
+def test_cfg0_fp64_full_run():
+    """32^3 BGK tau 0.8, affine OU boundary, 16-bead chain, 200 steps: 1e-12."""
+    case = cfg0_case()
+    say("case cfg0 fp64 32^3 200 steps")
+    ob = case.oracle_box()
+    assert ob.step(200) == 0
+    ctx = make_ctx(case, "f64")
+    ctx.step(200)
+    ctx.sync()
+    assert ctx.read(0, lbm.F_STEP) == 200
+    r = compare(ctx, ob, case, "f64")
+    say("cfg0", r)
+    assert r["u"] < 1e-12 and r["pop"] < 1e-12
+    assert r["bead_pos"] < 1e-12 and r["bead_vel"] < 1e-12
+    mm_o = ob.mass_mom()
+    mm_g = ctx.read(0, lbm.F_MASS_MOM)
+    assert mm_g[0] == mm_o[0] == 200
+    assert abs(mm_g[1] - mm_o[1]) / mm_o[1] < 1e-13
+    assert np.abs(mm_g[2:] - mm_o[2:]).max() < 1e-12 * mm_o[1]
+
+
+@pytest.mark.parametrize("coll", [oracle.BGK, oracle.MRT])
+def test_ks_sampled_fp64(coll):
+    """KS-driven sampled boundary, ragged tiles (26^3), MRT/BGK, chain: 1e-12."""
+    case = ks_case(26, 60, dt=20, res=9, tau=0.6, n_beads=8, collision=coll, f32_samples=False)
+    say("case ks fp64", coll)
+    ob = case.oracle_box()
+    assert ob.step(60) == 0
+    ctx = make_ctx(case, "f64")
+    ctx.step(60)
+    r = compare(ctx, ob, case, "f64")
+    say("ks fp64", coll, r)
+    assert r["u"] < 1e-12 and r["pop"] < 1e-12 and r["bead_pos"] < 1e-12
+
+
+def test_periodic_and_mixed_axes_fp64():
+    """Periodic x and z with equilibrium walls in y (odd sizes), chain without
+    the centre-of-mass pin crossing no wall."""
+    rng = np.random.default_rng(5)
+    dims = (17, 13, 6)
+    u0 = 1e-3 * rng.standard_normal(dims[::-1] + (3,))
+    A = inputs.ou_strain(41, rng, corr_steps=20.0, rms=1e-3)
+    pos, vel = inputs.chain_init(5, [8.3, 6.1, 2.7], rng)
+    chain = dict(pos=pos, vel=1e-3 * rng.standard_normal((5, 3)), fix_com=False, anchor=[8.3, 6.1, 2.7])
+    case = Case(dims, collision=oracle.MRT, tau=0.7, tau_bulk=0.9, ghost_rate=1.2, periodic_mask=5,
+                bc=(oracle.BC_AFFINE, A, 0, 1, 0), u0=u0, chains=[chain], reduce_every=7)
+    say("case periodic-mixed fp64")
+    ob = case.oracle_box()
+    assert ob.step(40) == 0
+    ctx = make_ctx(case, "f64")
+    ctx.step(40)
+    r = compare(ctx, ob, case, "f64")
+    say("periodic", r)
+    assert r["u"] < 1e-12 and r["pop"] < 1e-12 and r["bead_pos"] < 1e-12
+    mm_o, mm_g = ob.mass_mom(), ctx.read(0, lbm.F_MASS_MOM)
+    assert mm_g[0] == mm_o[0] == 35
+    assert abs(mm_g[1] - mm_o[1]) < 1e-12 * mm_o[1]
+
+
+def test_fully_periodic_conservation_fp64():
+    rng = np.random.default_rng(8)
+    dims = (12, 10, 14)
+    u0 = 1e-2 * rng.standard_normal(dims[::-1] + (3,))
+    pos, _ = inputs.chain_init(6, [5.5, 4.5, 6.5], rng)
+    chain = dict(pos=pos, vel=1e-2 * rng.standard_normal((6, 3)), fix_com=False, zeta=3.0,
+                 anchor=[5.5, 4.5, 6.5])
+    case = Case(dims, collision=oracle.BGK, tau=0.9, periodic_mask=7, u0=u0, chains=[chain])
+    say("case fully periodic fp64")
+    ob = case.oracle_box()
+    assert ob.step(30) == 0
+    ctx = make_ctx(case, "f64")
+    ctx.step(30)
+    r = compare(ctx, ob, case, "f64")
+    say("fully periodic", r)
+    assert r["u"] < 1e-12 and r["pop"] < 1e-12 and r["bead_pos"] < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_reduced_precision_storage(storage):
+    """FP32 compute with FP32 / FP16-deviation storage vs the FP64 oracle."""
+    case = ks_case(32, 400, dt=20, res=17, tau=0.6, n_beads=16)
+    say("case ks", storage, "32^3 400 steps")
+    ob = case.oracle_box()
+    assert ob.step(400) == 0
+    ctx = make_ctx(case, storage)
+    ctx.step(400)
+    r = compare(ctx, ob, case, storage)
+    say(storage, r)
+    assert r["u"] < TOL_U[storage]
+
+
+def test_edge_shapes_fp64():
+    """Smallest box (one interior node), long thin and ragged boxes in one batch."""
+    rng = np.random.default_rng(3)
+    cases = []
+    for dims in [(3, 3, 3), (40, 4, 5), (7, 33, 9)]:
+        A = inputs.ou_strain(11, rng, corr_steps=10.0, rms=1e-2)
+        cases.append(Case(dims, collision=oracle.MRT, tau=0.75, tau_bulk=1.1,
+                          bc=(oracle.BC_AFFINE, A, 0, 2, 0)))
+    ctx = lbm.Context([c.dims for c in cases], collision=lbm.MRT, tau=0.75, tau_bulk=1.1,
+                      storage=0)
+    for k, c in enumerate(cases):
+        c.add_to(ctx, k)
+    ctx.step(20)
+    for k, c in enumerate(cases):
+        ob = c.oracle_box()
+        assert ob.step(20) == 0
+        r = compare(ctx, ob, c, "f64", box=k)
+        say("edge", c.dims, r)
+        assert r["u"] < 1e-12 and r["pop"] < 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batched_equals_single_bitwise(storage):
+    """Uneven boxes in one launch give bitwise the same populations and beads
+    as each box run alone."""
+    cases = [ks_case(n, 40, dt=20, res=9, n_beads=6, config_idx=2, box_idx=i)
+             for i, n in enumerate([20, 32, 24])]
+    batch = lbm.Context([c.dims for c in cases], collision=lbm.MRT, tau=0.6, tau_bulk=0.6,
+                        storage=STORE[storage], reduce_every=10)
+    for k, c in enumerate(cases):
+        c.add_to(batch, k)
+    batch.step(40)
+    for k, c in enumerate(cases):
+        single = make_ctx(c, storage)
+        single.step(40)
+        a = batch.read(k, lbm.F_POP)
+        b = single.read(0, lbm.F_POP)
+        assert np.array_equal(a, b), f"box {k}"
+        pa = batch.read(k, lbm.F_BEAD_POS, n_beads=c.n_beads)
+        pb = single.read(0, lbm.F_BEAD_POS, n_beads=c.n_beads)
+        assert np.array_equal(pa, pb)
+        single.close()
+
+
+def test_graph_replay_and_determinism_bitwise():
+    case = ks_case(24, 60, dt=20, res=9, n_beads=8, config_idx=3)
+    runs = []
+    for graph_steps in (0, 0, 7):
+        ctx = make_ctx(case, "f16", graph_steps=graph_steps)
+        ctx.step(25)
+        ctx.step(35)
+        runs.append((ctx.read(0, lbm.F_POP), ctx.read(0, lbm.F_BEAD_POS, n_beads=8),
+                     ctx.read(0, lbm.F_MASS_MOM)))
+        ctx.close()
+    for r in runs[1:]:
+        assert np.array_equal(r[0], runs[0][0])
+        assert np.array_equal(r[1], runs[0][1])
+        assert np.array_equal(r[2], runs[0][2])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_checkpoint_resume_bitwise(storage):
+    case = ks_case(20, 60, dt=20, res=9, n_beads=6, config_idx=4)
+    full = make_ctx(case, storage)
+    full.step(60)
+    ref = full.read(0, lbm.F_POP)
+    ref_p = full.read(0, lbm.F_BEAD_POS, n_beads=6)
+    half = make_ctx(case, storage)
+    half.step(30)
+    pop = half.read(0, lbm.F_POP)
+    bp = half.read(0, lbm.F_BEAD_POS, n_beads=6)
+    bv = half.read(0, lbm.F_BEAD_VEL, n_beads=6)
+    fresh = make_ctx(case, storage)
+    fresh.write_state(0, lbm.F_STEP, 30)
+    fresh.write_state(0, lbm.F_POP, pop)
+    fresh.write_state(0, lbm.F_BEAD_POS, bp)
+    fresh.write_state(0, lbm.F_BEAD_VEL, bv)
+    fresh.step(30)
+    assert fresh.read(0, lbm.F_STEP) == 60
+    assert np.array_equal(fresh.read(0, lbm.F_POP), ref)
+    assert np.array_equal(fresh.read(0, lbm.F_BEAD_POS, n_beads=6), ref_p)
+
+
+def test_error_codes_match_oracle():
+    # bead stencil leaves the interior at the first step
+    n = 12
+    A = np.zeros((30, 9))
+    pos = np.array([[9.6, 5.0, 5.0], [10.2, 5.1, 5.0]])
+    c = Case((n, n, n), bc=(oracle.BC_AFFINE, A, 0, 1, 0),
+             chains=[dict(pos=pos, fix_com=False, anchor=pos.mean(0))])
+    ob = c.oracle_box()
+    assert ob.step(5) == oracle.ERR_BEAD_OUT
+    ctx = make_ctx(c)
+    ctx.step(5)
+    assert ctx.sync_status() == lbm.ERR_BEAD_OUT
+    assert ctx.read(0, lbm.F_STEP, strict=False)[0] == ob.error()[1] == 0
+    assert ctx.step_status(1) == lbm.ERR_BEAD_OUT
+    # overstretched bond
+    pos = np.array([[5.0, 5.0, 5.0], [7.01, 5.0, 5.0]])
+    c = Case((n, n, n), bc=(oracle.BC_AFFINE, A, 0, 1, 0),
+             chains=[dict(pos=pos, fix_com=True, anchor=pos.mean(0))])
+    ob = c.oracle_box()
+    assert ob.step(5) == oracle.ERR_FENE
+    ctx = make_ctx(c)
+    ctx.step(5)
+    assert ctx.sync_status() == lbm.ERR_FENE
+    # non-finite state caught by the mass check at t_2 (K = 2), frozen at t_1
+    c = Case((n, n, n), bc=(oracle.BC_AFFINE, A, 0, 1, 0), reduce_every=2)
+    ob = c.oracle_box()
+    f = ob.pop()
+    f[3, 5, 5, 5] = np.nan
+    ob.set_populations(f)
+    assert ob.step(5) == oracle.ERR_UNSTABLE
+    assert ob.error() == (oracle.ERR_UNSTABLE, 1)
+    ctx = make_ctx(c)
+    ctx.write_state(0, lbm.F_POP, f)
+    ctx.step(5)
+    assert ctx.sync_status() == lbm.ERR_UNSTABLE
+    assert ctx.read(0, lbm.F_STEP, strict=False)[0] == 1
+    # stepping beyond the samples is refused on the host
+    c = Case((n, n, n), bc=(oracle.BC_AFFINE, A[:3], 0, 1, 0))
+    ctx = make_ctx(c)
+    assert ctx.step_status(3) == 0
+    assert ctx.step_status(1) == lbm.ERR_ARG
