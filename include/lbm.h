@@ -88,7 +88,7 @@ typedef struct {
   lb_storage storage;
   double rho0;             /* rest density; also the density of the boundary equilibrium */
   int32_t reduce_every;    /* K > 0: record mass and momentum of the interior at t_n, n % K == 0 */
-  int32_t fp16_exp;        /* s of LB_STORE_F16DEV, 0 = 14; |h| < 65504 needs |f/w - rho0| < 65504 / 2^s */
+  int32_t fp16_exp;        /* s of LB_STORE_F16DEV, 0 = 10; |h| < 65504 needs |f/w - rho0| < 65504 / 2^s */
   void* stream;            /* hipStream_t or NULL */
   /* device allocator hook (e.g. PyTorch's caching allocator); NULL = hipMalloc/hipFree */
   void* (*dev_alloc)(size_t bytes, void* user);
@@ -160,7 +160,11 @@ typedef enum {
   LB_F_BEAD_POS = 3,  /* FP64 [beads of the box][3], chains in coupling order */
   LB_F_BEAD_VEL = 4,  /* FP64 [beads of the box][3] */
   LB_F_MASS_MOM = 5,  /* FP64 [5]: step of the latest check, M, Px, Py, Pz */
-  LB_F_STEP = 6       /* int64 [1]: current step (the context's, box ignored) */
+  LB_F_STEP = 6,      /* int64 [1]: current step (the context's, box ignored) */
+  LB_F_POP_DEV = 7,   /* FP64 [19][nz][ny][nx] pre-collision deviations f_i - w_i rho0: the
+                         exact image of the stored state (checkpoints); boundary nodes read 0 */
+  LB_F_BEAD_REL = 8   /* FP64 [beads][3] bead position minus its chain's anchor, as stored
+                         (exact image; checkpoints) */
 } lb_field;
 
 /* Copies a field of one box at the current step to dst (host memory, or
@@ -173,7 +177,9 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
  * [n][3], out = host FP64 [n][19]. */
 lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out);
 
-/* Restores state for resume: LB_F_POP (FP64 [19][nz][ny][nx], interior used),
+/* Restores state for resume: LB_F_POP or LB_F_POP_DEV (FP64 [19][nz][ny][nx],
+ * interior used; LB_F_POP_DEV round-trips bit for bit in every storage mode),
+ * LB_F_BEAD_REL (FP64 [beads][3], exact),
  * LB_F_BEAD_POS / LB_F_BEAD_VEL (FP64 [beads][3]), LB_F_STEP (int64 [1]).
  * Only before the first lb_step of the context. */
 lb_status lb_write_state(lb_ctx* ctx, int32_t box, lb_field field, const void* src, size_t bytes);

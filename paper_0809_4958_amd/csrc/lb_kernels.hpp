@@ -361,7 +361,7 @@ struct LbArgs {
 };
 
 template <int S, int COLL, bool PER>
-__global__ __launch_bounds__(WG) void k_lb(LbArgs A) {
+__global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -400,24 +400,13 @@ __global__ __launch_bounds__(WG) void k_lb(LbArgs A) {
         if (ov) cmask |= 1ull << c;
       }
       const int plane = it.ex * it.ey;
-      int px[MAX_SLOTS], py[MAX_SLOTS];
-      int ns = 0;
-#pragma unroll
-      for (int r = 0; r < MAX_SLOTS; r++) {
-        const int p = tid + r * WG;
-        px[r] = 0;
-        py[r] = 0;
-        if (p < plane) {
-          px[r] = it.x0 + p % it.ex;
-          py[r] = it.y0 + p / it.ex;
-          ns = r + 1;
-        }
-      }
-      for (int z = it.z0; z < it.z0 + it.ez; z++) {
-#pragma unroll
-        for (int r = 0; r < MAX_SLOTS; r++) {
-          if (r >= ns) break;
-          const int x = px[r], y = py[r];
+#pragma unroll 1
+      for (int p = tid; p < plane; p += WG) {
+        // each thread marches one (x, y) column of the tile along z
+        const int x = it.x0 + p % it.ex;
+        const int y = it.y0 + p / it.ex;
+#pragma unroll 1
+        for (int z = it.z0; z < it.z0 + it.ez; z++) {
           const int node = (z * b.ny + y) * b.nx + x;
           R d[Q];
           load_pre<S, PER>(src, b, x, y, z, pre, d);
@@ -581,8 +570,9 @@ __global__ __launch_bounds__(WG) void k_lb(LbArgs A) {
 }
 
 // ------------------------------------------------------- state upload
-// pre-collision state of one box from FP64 populations [19][nn] (mode 0) or
-// from the equilibrium of a velocity field u[nn][3] (mode 1) or rest (mode 2)
+// pre-collision state of one box from FP64 populations [19][nn] (mode 0), from
+// the equilibrium of a velocity field u[nn][3] (mode 1), rest (mode 2), or FP64
+// deviations f_i - w_i rho0 [19][nn] (mode 3)
 template <int S>
 __global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T* __restrict__ dst,
                                                 const double* __restrict__ in, int mode, double rho0) {
@@ -601,6 +591,9 @@ __global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T*
     } else if (mode == 0) {
 #pragma unroll
       for (int i = 0; i < Q; i++) d[i] = (R)(in[i * nn + node] - WD[WCLS[i]] * rho0);
+    } else if (mode == 3) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = (R)in[i * nn + node];
     } else {
       // deviation of f_eq(rho0, u): computed in FP64 then rounded once
       double ud[3] = {in[3 * node], in[3 * node + 1], in[3 * node + 2]};
@@ -615,7 +608,7 @@ __global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T*
 }
 
 // ------------------------------------------------------------ readout
-// what: 0 populations [19][nn], 1 rho [nn], 2 u [nn][3]
+// what: 0 populations [19][nn], 1 rho [nn], 2 u [nn][3], 3 deviations [19][nn]
 template <int S, bool PER>
 __global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>::T* __restrict__ src,
                                              double* __restrict__ out, int what, int pre, double rho0) {
@@ -635,6 +628,9 @@ __global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>:
       if (what == 0) {
 #pragma unroll
         for (int i = 0; i < Q; i++) out[i * nn + node] = f[i];
+      } else if (what == 3) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = (double)d[i];
       } else {
         double drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -657,6 +653,9 @@ __global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>:
       if (what == 0) {
 #pragma unroll
         for (int i = 0; i < Q; i++) out[i * nn + node] = WD[WCLS[i]] * rho0;
+      } else if (what == 3) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = 0.0;
       } else if (what == 1) {
         out[node] = rho0;
       } else {

@@ -52,6 +52,7 @@ struct ChainHost {
   lb_chain p;
   int box;
   std::vector<double> pos, vel;
+  bool pos_is_rel = false;  // pos holds positions minus the anchor (exact restore)
 };
 
 using LbLaunch = void (*)(dim3, hipStream_t, const LbArgs&);
@@ -188,6 +189,24 @@ void dfree(lb_ctx* ctx, void* p) {
     (void)hipFree(p);
 }
 
+// All initialisation is ordered on the context stream: null-stream memsets and
+// copies do not order against a non-blocking stream.
+hipError_t h2d(lb_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(ctx->stream);
+}
+
+hipError_t copy_sync(lb_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, ctx->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(ctx->stream);
+}
+
+hipError_t dzero(lb_ctx* ctx, void* dst, size_t bytes) {
+  return hipMemsetAsync(dst, 0, bytes, ctx->stream);
+}
+
 template <typename X>
 X* dalloc_t(lb_ctx* ctx, size_t n, bool* ok) {
   X* p = (X*)dalloc(ctx, n * sizeof(X));
@@ -202,13 +221,16 @@ void drop_graph(lb_ctx* ctx) {
   }
 }
 
+// Default tile: whole interior rows in x (coalesced, one box row per wave
+// segment), about 512 (x, y) positions per workgroup (two per thread) and a
+// deep z march so that the z+-1 planes a node pulls from are re-read from
+// cache by the same thread; y halo overhead (ey+2)/ey, z halo (ez+2)/ez.
 void default_tile(BoxHost& b) {
   const int ix = b.ix;
   b.ex = ix <= 128 ? ix : 64;
-  b.ey = std::max(1, std::min(b.iy, 256 / std::max(1, b.ex)));
-  if (b.ex * b.ey < 128 && b.iy > b.ey) b.ey = std::min(b.iy, (512 + b.ex - 1) / b.ex);
+  b.ey = std::max(1, std::min(b.iy, 512 / std::max(1, b.ex)));
   while (b.ex * b.ey > WG * MAX_SLOTS) b.ey--;
-  b.ez = std::min(b.iz, 4);
+  b.ez = std::min(b.iz, 16);
 }
 
 std::string box_key(const lb_ctx* ctx, const BoxHost& b) {
@@ -344,12 +366,11 @@ lb_status build_tables(lb_ctx* ctx, int grid_override) {
   if (!ok) return fail(ctx, LB_ERR_OOM, "work-list allocation failed");
   std::vector<int> ident(n_items);
   std::iota(ident.begin(), ident.end(), 0);
-  HIPCHK(hipMemcpy(ctx->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(ctx->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(ctx->d_box_items, ident.data(), ident.size() * sizeof(int), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(ctx->d_box_items_off, box_off.data(), box_off.size() * sizeof(int),
-                   hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(ctx->d_partials, 0, 4 * sizeof(double) * (size_t)n_items));
+  HIPCHK(h2d(ctx, ctx->d_items, items.data(), items.size() * sizeof(Item)));
+  HIPCHK(h2d(ctx, ctx->d_order, order.data(), order.size() * sizeof(int)));
+  HIPCHK(h2d(ctx, ctx->d_box_items, ident.data(), ident.size() * sizeof(int)));
+  HIPCHK(h2d(ctx, ctx->d_box_items_off, box_off.data(), box_off.size() * sizeof(int)));
+  HIPCHK(dzero(ctx, ctx->d_partials, 4 * sizeof(double) * (size_t)n_items));
   ctx->items = items;
   ctx->tables_ready = true;
   std::ostringstream d;
@@ -414,8 +435,7 @@ lb_status upload_boxes(lb_ctx* ctx) {
     d.interior = (double)b.interior;
     ctx->h_boxes[i] = d;
   }
-  HIPCHK(hipMemcpy(ctx->d_boxes, ctx->h_boxes.data(), ctx->h_boxes.size() * sizeof(BoxDesc),
-                   hipMemcpyHostToDevice));
+  HIPCHK(h2d(ctx, ctx->d_boxes, ctx->h_boxes.data(), ctx->h_boxes.size() * sizeof(BoxDesc)));
   return LB_OK;
 }
 
@@ -467,7 +487,7 @@ lb_status upload_chains(lb_ctx* ctx) {
     }
     for (int j = 0; j < d.nb; j++)
       for (int a = 0; a < 3; a++) {
-        rel.push_back((c.pos[3 * j + a] - d.ai[a]) - d.af[a]);
+        rel.push_back(c.pos_is_rel ? c.pos[3 * j + a] : (c.pos[3 * j + a] - d.ai[a]) - d.af[a]);
         vel.push_back(c.vel[3 * j + a]);
       }
     first += d.nb;
@@ -487,20 +507,20 @@ lb_status upload_chains(lb_ctx* ctx) {
   if (!ok || !ctx->d_pos || !ctx->d_vel || !ctx->d_rec_d || !ctx->d_rec_dp)
     return fail(ctx, LB_ERR_OOM, "chain allocation failed");
   if (!cd.empty())
-    HIPCHK(hipMemcpy(ctx->d_chains, cd.data(), cd.size() * sizeof(ChainDesc), hipMemcpyHostToDevice));
+    HIPCHK(h2d(ctx, ctx->d_chains, cd.data(), cd.size() * sizeof(ChainDesc)));
   const int par = (int)(ctx->host_step & 1);
   char* pbase = (char*)ctx->d_pos + (size_t)par * 3 * nbd * rb;
   char* vbase = (char*)ctx->d_vel + (size_t)par * 3 * nbd * rb;
   if (first) {
     if (ctx->S == LB_STORE_F64) {
-      HIPCHK(hipMemcpy(pbase, rel.data(), rel.size() * 8, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(vbase, vel.data(), vel.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(h2d(ctx, pbase, rel.data(), rel.size() * 8));
+      HIPCHK(h2d(ctx, vbase, vel.data(), vel.size() * 8));
     } else {
       std::vector<float> r, v;
       to_real(rel, r);
       to_real(vel, v);
-      HIPCHK(hipMemcpy(pbase, r.data(), r.size() * 4, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(vbase, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(h2d(ctx, pbase, r.data(), r.size() * 4));
+      HIPCHK(h2d(ctx, vbase, v.data(), v.size() * 4));
     }
   }
   // empty bounding boxes until the first chain step
@@ -509,10 +529,10 @@ lb_status upload_chains(lb_ctx* ctx) {
     bb[6 * c] = bb[6 * c + 1] = bb[6 * c + 2] = 1 << 30;
     bb[6 * c + 3] = bb[6 * c + 4] = bb[6 * c + 5] = -(1 << 30);
   }
-  HIPCHK(hipMemcpy(ctx->d_bbox, bb.data(), bb.size() * sizeof(int), hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(ctx->d_rec_base, 0, nbd * sizeof(int4)));
-  HIPCHK(hipMemset(ctx->d_rec_d, 0, 3 * nbd * rb));
-  HIPCHK(hipMemset(ctx->d_rec_dp, 0, 3 * nbd * rb));
+  HIPCHK(h2d(ctx, ctx->d_bbox, bb.data(), bb.size() * sizeof(int)));
+  HIPCHK(dzero(ctx, ctx->d_rec_base, nbd * sizeof(int4)));
+  HIPCHK(dzero(ctx, ctx->d_rec_d, 3 * nbd * rb));
+  HIPCHK(dzero(ctx, ctx->d_rec_dp, 3 * nbd * rb));
   ctx->chains_ready = true;
   return upload_boxes(ctx);
 }
@@ -644,7 +664,7 @@ lb_status decode_error(lb_ctx* ctx, int key, int64_t step) {
 
 lb_status sync_state(lb_ctx* ctx, DevState* out) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  HIPCHK(hipMemcpy(out, ctx->d_st, sizeof(DevState), hipMemcpyDeviceToHost));
+  HIPCHK(copy_sync(ctx, out, ctx->d_st, sizeof(DevState), hipMemcpyDeviceToHost));
   if (out->err_key != ERR_NONE && ctx->latched == LB_OK) decode_error(ctx, out->err_key, out->step);
   return LB_OK;
 }
@@ -673,7 +693,7 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   ctx->cfg.boxes = nullptr;
   ctx->S = cfg->storage;
   ctx->coll = cfg->collision;
-  ctx->fp16_exp = cfg->fp16_exp ? cfg->fp16_exp : 14;
+  ctx->fp16_exp = cfg->fp16_exp ? cfg->fp16_exp : 10;
   int64_t off = 0;
   for (int i = 0; i < cfg->n_boxes; i++) {
     BoxHost b;
@@ -736,9 +756,9 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     return LB_ERR_OOM;
   }
   // rest state: all deviations zero, in both buffers
-  if (hipMemset(ctx->arena[0], 0, (size_t)off * sb) != hipSuccess ||
-      hipMemset(ctx->arena[1], 0, (size_t)off * sb) != hipSuccess ||
-      hipMemset(ctx->d_mass_mom, 0, 5 * sizeof(double) * ctx->bx.size()) != hipSuccess) {
+  if (dzero(ctx, ctx->arena[0], (size_t)off * sb) != hipSuccess ||
+      dzero(ctx, ctx->arena[1], (size_t)off * sb) != hipSuccess ||
+      dzero(ctx, ctx->d_mass_mom, 5 * sizeof(double) * ctx->bx.size()) != hipSuccess) {
     lb_free(ctx);
     return LB_ERR_HIP;
   }
@@ -746,7 +766,7 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   st.step = 0;
   st.err_key = ERR_NONE;
   st.done = 0;
-  if (hipMemcpy(ctx->d_st, &st, sizeof(st), hipMemcpyHostToDevice) != hipSuccess) {
+  if (h2d(ctx, ctx->d_st, &st, sizeof(st)) != hipSuccess) {
     lb_free(ctx);
     return LB_ERR_HIP;
   }
@@ -822,7 +842,7 @@ lb_status lb_set_boundary(lb_ctx* ctx, int32_t box, const lb_boundary* bc) {
     }
     dptr = dalloc(ctx, n * sizeof(double));
     if (!dptr) return fail(ctx, LB_ERR_OOM, "boundary allocation failed");
-    HIPCHK(hipMemcpy(dptr, v.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(h2d(ctx, dptr, v.data(), n * sizeof(double)));
   } else {
     std::vector<float> v(n);
     if (bc->data_is_f64) {
@@ -833,7 +853,7 @@ lb_status lb_set_boundary(lb_ctx* ctx, int32_t box, const lb_boundary* bc) {
     }
     dptr = dalloc(ctx, n * sizeof(float));
     if (!dptr) return fail(ctx, LB_ERR_OOM, "boundary allocation failed");
-    HIPCHK(hipMemcpy(dptr, v.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(h2d(ctx, dptr, v.data(), n * sizeof(float)));
   }
   dfree(ctx, b.d_bc);
   b.d_bc = dptr;
@@ -948,17 +968,20 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
   if (field == LB_F_STEP) {
     if (dst_bytes != sizeof(int64_t)) return fail(ctx, LB_ERR_BUFSIZE, "LB_F_STEP needs 8 bytes");
     int64_t v = st.step;
-    HIPCHK(hipMemcpy(dst, &v, 8, dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    if (dst_on_device)
+      HIPCHK(h2d(ctx, dst, &v, 8));
+    else
+      std::memcpy(dst, &v, 8);
     return ctx->latched;
   }
   BoxHost& b = ctx->bx[box];
   if (field == LB_F_MASS_MOM) {
     if (dst_bytes != 5 * sizeof(double)) return fail(ctx, LB_ERR_BUFSIZE, "LB_F_MASS_MOM needs 40 bytes");
-    HIPCHK(hipMemcpy(dst, ctx->d_mass_mom + 5 * box, 5 * sizeof(double), kind));
+    HIPCHK(copy_sync(ctx, dst, ctx->d_mass_mom + 5 * box, 5 * sizeof(double), kind));
     return ctx->latched;
   }
   const int par = (int)(st.step & 1);
-  if (field == LB_F_BEAD_POS || field == LB_F_BEAD_VEL) {
+  if (field == LB_F_BEAD_POS || field == LB_F_BEAD_VEL || field == LB_F_BEAD_REL) {
     int c0 = ctx->h_boxes[box].chain_first, c1 = c0 + ctx->h_boxes[box].chain_count;
     int nb = 0;
     for (auto& c : ctx->ch) nb += (c.box == box) ? c.p.n_beads : 0;
@@ -969,23 +992,25 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
     if (!tmp) return fail(ctx, LB_ERR_OOM, "readout allocation failed");
     const size_t rb = real_bytes(ctx->S);
     const size_t nbd = std::max(1, ctx->total_beads);
-    const void* src = (char*)(field == LB_F_BEAD_POS ? ctx->d_pos : ctx->d_vel) + (size_t)par * 3 * nbd * rb;
+    const bool is_pos = field != LB_F_BEAD_VEL;
+    const void* src = (char*)(is_pos ? ctx->d_pos : ctx->d_vel) + (size_t)par * 3 * nbd * rb;
     if (ctx->S == 0)
       hipLaunchKernelGGL(k_read_beads<double>, dim3(1), dim3(WG), 0, ctx->stream, ctx->d_chains, c0, c1,
                          (const double*)src, tmp, field == LB_F_BEAD_POS ? 1 : 0);
     else
       hipLaunchKernelGGL(k_read_beads<float>, dim3(1), dim3(WG), 0, ctx->stream, ctx->d_chains, c0, c1,
                          (const float*)src, tmp, field == LB_F_BEAD_POS ? 1 : 0);
+    (void)is_pos;
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    HIPCHK(hipMemcpy(dst, tmp, (size_t)nb * 3 * sizeof(double), kind));
+    HIPCHK(copy_sync(ctx, dst, tmp, (size_t)nb * 3 * sizeof(double), kind));
     dfree(ctx, tmp);
     return ctx->latched;
   }
   int what;
   size_t need;
-  if (field == LB_F_POP) {
-    what = 0;
+  if (field == LB_F_POP || field == LB_F_POP_DEV) {
+    what = field == LB_F_POP ? 0 : 3;
     need = (size_t)Q * b.nn * sizeof(double);
   } else if (field == LB_F_RHO) {
     what = 1;
@@ -1011,7 +1036,7 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (!dst_on_device) {
-    HIPCHK(hipMemcpy(dst, out, need, hipMemcpyDeviceToHost));
+    HIPCHK(copy_sync(ctx, dst, out, need, hipMemcpyDeviceToHost));
     dfree(ctx, out);
   }
   return ctx->latched;
@@ -1038,7 +1063,7 @@ lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz,
   int* d_xyz = (int*)dalloc(ctx, (size_t)3 * n * sizeof(int));
   double* d_out = (double*)dalloc(ctx, (size_t)Q * n * sizeof(double));
   if (!d_xyz || !d_out) return fail(ctx, LB_ERR_OOM, "site readout allocation failed");
-  HIPCHK(hipMemcpy(d_xyz, xyz, (size_t)3 * n * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(h2d(ctx, d_xyz, xyz, (size_t)3 * n * sizeof(int)));
   const int par = (int)(st.step & 1);
   const size_t sb = store_bytes(ctx->S);
   const void* src = (char*)ctx->arena[par] + (size_t)b.off * sb;
@@ -1051,7 +1076,7 @@ lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz,
   else launch_sites<2>(ctx->per, nblk, ctx->stream, d, src, d_xyz, n, d_out, pre, r0);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  HIPCHK(hipMemcpy(out, d_out, (size_t)Q * n * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(copy_sync(ctx, out, d_out, (size_t)Q * n * sizeof(double), hipMemcpyDeviceToHost));
   dfree(ctx, d_xyz);
   dfree(ctx, d_out);
   return ctx->latched;
@@ -1068,7 +1093,7 @@ lb_status lb_write_state(lb_ctx* ctx, int32_t box, lb_field field, const void* s
     const int old_par = (int)(ctx->host_step & 1), new_par = (int)(n & 1);
     if (old_par != new_par) {
       const size_t sb = store_bytes(ctx->S);
-      HIPCHK(hipMemcpy(ctx->arena[new_par], ctx->arena[old_par], (size_t)ctx->arena_elems * sb,
+      HIPCHK(copy_sync(ctx, ctx->arena[new_par], ctx->arena[old_par], (size_t)ctx->arena_elems * sb,
                        hipMemcpyDeviceToDevice));
       ctx->chains_ready = false;  // bead state is re-uploaded into the new parity
     }
@@ -1076,13 +1101,13 @@ lb_status lb_write_state(lb_ctx* ctx, int32_t box, lb_field field, const void* s
     DevState st{};
     st.step = n;
     st.err_key = ERR_NONE;
-    HIPCHK(hipMemcpy(ctx->d_st, &st, sizeof(st), hipMemcpyHostToDevice));
+    HIPCHK(h2d(ctx, ctx->d_st, &st, sizeof(st)));
     return LB_OK;
   }
   lb_status s = check_box(ctx, box);
   if (s) return s;
   BoxHost& b = ctx->bx[box];
-  if (field == LB_F_BEAD_POS || field == LB_F_BEAD_VEL) {
+  if (field == LB_F_BEAD_POS || field == LB_F_BEAD_VEL || field == LB_F_BEAD_REL) {
     size_t nb = 0;
     for (auto& c : ctx->ch) nb += (c.box == box) ? c.p.n_beads : 0;
     if (bytes != nb * 3 * sizeof(double)) return fail(ctx, LB_ERR_BUFSIZE, "bead state size mismatch");
@@ -1090,27 +1115,30 @@ lb_status lb_write_state(lb_ctx* ctx, int32_t box, lb_field field, const void* s
     size_t o = 0;
     for (auto& c : ctx->ch) {
       if (c.box != box) continue;
-      auto& v = field == LB_F_BEAD_POS ? c.pos : c.vel;
+      auto& v = field == LB_F_BEAD_VEL ? c.vel : c.pos;
       v.assign(p + o, p + o + 3 * c.p.n_beads);
+      c.pos_is_rel = field == LB_F_BEAD_REL ? true : (field == LB_F_BEAD_POS ? false : c.pos_is_rel);
       o += 3 * c.p.n_beads;
     }
     ctx->chains_ready = false;
     return LB_OK;
   }
-  if (field != LB_F_POP) return fail(ctx, LB_ERR_ARG, "only POP, BEAD_POS, BEAD_VEL, STEP are writable");
+  if (field != LB_F_POP && field != LB_F_POP_DEV)
+    return fail(ctx, LB_ERR_ARG, "only POP, POP_DEV, BEAD_POS, BEAD_VEL, STEP are writable");
+  const int mode = field == LB_F_POP ? 0 : 3;
   if (bytes != (size_t)Q * b.nn * sizeof(double)) return fail(ctx, LB_ERR_BUFSIZE, "POP size mismatch");
   double* d_in = (double*)dalloc(ctx, bytes);
   if (!d_in) return fail(ctx, LB_ERR_OOM, "staging allocation failed");
-  HIPCHK(hipMemcpy(d_in, src, bytes, hipMemcpyHostToDevice));
+  HIPCHK(h2d(ctx, d_in, src, bytes));
   const int par = (int)(ctx->host_step & 1);
   const size_t sb = store_bytes(ctx->S);
   void* dst = (char*)ctx->arena[par] + (size_t)b.off * sb;
   const int nblk = (int)std::min<int64_t>((b.nn + WG - 1) / WG, 65535);
   const BoxDesc& d = ctx->h_boxes[box];
   switch (ctx->S) {
-    case 0: hipLaunchKernelGGL(k_set_pre<0>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (double*)dst, d_in, 0, ctx->cfg.rho0); break;
-    case 1: hipLaunchKernelGGL(k_set_pre<1>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (float*)dst, d_in, 0, ctx->cfg.rho0); break;
-    default: hipLaunchKernelGGL(k_set_pre<2>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (_Float16*)dst, d_in, 0, ctx->cfg.rho0); break;
+    case 0: hipLaunchKernelGGL(k_set_pre<0>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (double*)dst, d_in, mode, ctx->cfg.rho0); break;
+    case 1: hipLaunchKernelGGL(k_set_pre<1>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (float*)dst, d_in, mode, ctx->cfg.rho0); break;
+    default: hipLaunchKernelGGL(k_set_pre<2>, dim3(nblk), dim3(WG), 0, ctx->stream, d, (_Float16*)dst, d_in, mode, ctx->cfg.rho0); break;
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -247,33 +247,33 @@ def face_samples(ks: KSField, tracer: Tracer, dims: tuple[int, int, int], units:
     tracer must have been integrated to the matching Kolmogorov times
     step/tau~_eta.  Face f lies at node coordinate 0 (even f) or n-1 (odd f)
     along axis f//2; entry [v][u] holds grid point (u, v) along the face's
-    tangential axes (lower-index axis = u).
+    tangential axes (lower-index axis = u).  Evaluated for all sample times at
+    once: u = Re sum_n (A_n - i B_n) e^{i(k_n.X(t) + w_n t)} e^{i k_n.r}, with
+    e^{i k_n.r} tabulated once per face.
     """
     dims = tuple(int(d) for d in dims)
     centre = [(d - 1) / 2.0 for d in dims]
-    out = np.empty((len(step_times), 6, res, res, 3))
-    for it, step in enumerate(step_times):
-        tk = float(step) / units.tau_eta
-        x_tr = tracer.pos[it]
-        v_tr = tracer.vel[it]
-        for f in range(6):
-            a = f // 2
-            au, av = FACE_AXES[f]
-            axes = [None, None, None]
-            axes[a] = np.array([(0.0 if f % 2 == 0 else dims[a] - 1.0) - centre[a]])
-            axes[au] = _sample_offsets(dims[au], res, centre[au])
-            axes[av] = _sample_offsets(dims[av], res, centre[av])
-            axes = [np.asarray(o) / units.eta for o in axes]
-            g = ks.grid_velocity(x_tr, tk, axes)          # [z, y, x, 3]
-            g = g - v_tr
-            # reorder to [v][u]
-            if a == 0:
-                face = g[:, :, 0, :]                       # [z(v), y(u)]
-            elif a == 1:
-                face = g[:, 0, :, :]                       # [z(v), x(u)]
-            else:
-                face = g[0, :, :, :]                       # [y(v), x(u)]
-            out[it, f] = face * units.u_scale
+    T = len(step_times)
+    tk = np.asarray(step_times, dtype=np.float64) / units.tau_eta
+    # per-time mode coefficients C[t, n, c] = (A - iB)_{n,c} e^{i(k_n . X(t) + w_n t)}
+    ph = tracer.pos[:T] @ ks.k.T + ks.omega[None, :] * tk[:, None]          # [T, n]
+    amp = ks.A - 1j * ks.B                                                 # [n, 3]
+    coef = np.exp(1j * ph)[:, :, None] * amp[None, :, :]                   # [T, n, 3]
+    cflat = np.ascontiguousarray(coef.transpose(0, 2, 1)).reshape(T * 3, -1)  # [(t,c), n]
+    out = np.empty((T, 6, res, res, 3))
+    for f in range(6):
+        a = f // 2
+        au, av = FACE_AXES[f]
+        r_a = ((0.0 if f % 2 == 0 else dims[a] - 1.0) - centre[a]) / units.eta
+        ou = _sample_offsets(dims[au], res, centre[au]) / units.eta
+        ov = _sample_offsets(dims[av], res, centre[av]) / units.eta
+        e_a = np.exp(1j * ks.k[:, a] * r_a)                                   # [n]
+        eu = np.exp(1j * np.outer(ou, ks.k[:, au]))                           # [res(u), n]
+        ev = np.exp(1j * np.outer(ov, ks.k[:, av]))                           # [res(v), n]
+        m = (ev[:, None, :] * eu[None, :, :]) * e_a[None, None, :]            # [v, u, n]
+        vals = np.real(cflat @ m.reshape(res * res, -1).T)                   # [(t,c), v*u]
+        vals = vals.reshape(T, 3, res, res).transpose(0, 2, 3, 1)            # [t, v, u, c]
+        out[:, f] = (vals - tracer.vel[:T, None, None, :]) * units.u_scale
     return out
 
 

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "LB_OK", -1: "LB_ERR_ARG", -2: "LB_ERR_OOM", -3: "LB_ERR_HIP"
 BGK, MRT = 0, 1
 STORE_F64, STORE_F32, STORE_F16DEV = 0, 1, 2
 BC_AFFINE, BC_SAMPLED = 0, 1
-F_RHO, F_U, F_POP, F_BEAD_POS, F_BEAD_VEL, F_MASS_MOM, F_STEP = range(7)
+F_RHO, F_U, F_POP, F_BEAD_POS, F_BEAD_VEL, F_MASS_MOM, F_STEP, F_POP_DEV, F_BEAD_REL = range(9)
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
 FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
@@ -247,13 +247,13 @@ class Context:
         return self._nbeads.get(box, 0) if hasattr(self, "_nbeads") else 0
 
     def read(self, box, field, n_beads=0, strict=True):
-        if field == F_POP:
+        if field in (F_POP, F_POP_DEV):
             shp = (Q,) + self.shape(box)
         elif field == F_RHO:
             shp = self.shape(box)
         elif field == F_U:
             shp = self.shape(box) + (3,)
-        elif field in (F_BEAD_POS, F_BEAD_VEL):
+        elif field in (F_BEAD_POS, F_BEAD_VEL, F_BEAD_REL):
             shp = (n_beads, 3)
         elif field == F_MASS_MOM:
             shp = (5,)

@@ -17,6 +17,14 @@ def bead_mass(n_beads):
     return 0.5 / n_beads
 
 
+# Random-walk bond length of the initial chains, in lattice spacings.  With
+# k = 1 and kT = 0 the chain collapses from its initial shape; bonds of 0.05
+# give spring forces k b comparable to zeta times the boundary-driven flow
+# (|f/w - 1| stays at the per-cent level), while unit bonds drive |f/w - 1|
+# to O(1) near the chain and the lattice fluid out of its stable range.
+CHAIN_BOND = 0.05
+
+
 def rel_l2(a, b, mask=None):
     a = np.asarray(a)
     b = np.asarray(b)
@@ -82,7 +90,7 @@ def cfg0_case(n_steps=200, n=32):
     (k = 1, R0 = 2, zeta = 5) at the box centre."""
     A = inputs.ou_strain(n_steps, inputs.rng(0, 0), corr_steps=500.0, rms=1e-3)
     xc = np.full(3, (n - 1) / 2.0)
-    pos, vel = inputs.chain_init(16, xc, inputs.rng(0, 2))
+    pos, vel = inputs.chain_init(16, xc, inputs.rng(0, 2), bond=CHAIN_BOND)
     chain = dict(pos=pos, vel=vel, substeps=10, fix_com=True, zeta=5.0, fene_k=1.0, fene_r0=2.0,
                  anchor=xc)
     return Case((n, n, n), collision=oracle.BGK, tau=0.8, bc=(oracle.BC_AFFINE, A, 0, 1, 0),
@@ -100,7 +108,7 @@ def ks_case(n, n_steps, dt=20, res=17, tau=0.6, n_beads=16, config_idx=1, box_id
     xc = np.full(3, (n - 1) / 2.0)
     chains = []
     if n_beads:
-        pos, vel = inputs.chain_init(n_beads, xc, inputs.rng(config_idx, 2))
+        pos, vel = inputs.chain_init(n_beads, xc, inputs.rng(config_idx, 2), bond=CHAIN_BOND)
         chains.append(dict(pos=pos, vel=vel, anchor=xc))
     return Case((n, n, n), collision=collision, tau=tau, tau_bulk=tau, ghost_rate=1.0,
                 bc=(oracle.BC_SAMPLED, faces, 0, dt, res), u0=u0, chains=chains, reduce_every=100)
