@@ -200,6 +200,12 @@ lb_status lb_autotune(lb_ctx* ctx, int32_t trials);
 lb_status lb_set_timing(lb_ctx* ctx, int32_t on);
 lb_status lb_get_timing(lb_ctx* ctx, double out[4]);
 
+/* Practical HBM ceiling: copies a device buffer of `bytes` (rounded down to a
+ * multiple of 16) with 16-byte loads and stores, `iters` times, and returns in
+ * gbs the measured (read + write) bytes per second / 1e9.  Allocates and frees
+ * its two buffers with hipMalloc; runs on the current device's null stream. */
+lb_status lb_copy_probe(size_t bytes, int32_t iters, double* gbs);
+
 /* Description of the chosen launch configuration (tile shapes, grid size). */
 const char* lb_describe(const lb_ctx* ctx);
 const char* lb_last_error(const lb_ctx* ctx);

@@ -79,7 +79,8 @@ __host__ __device__ constexpr bool basis_orthogonal() {
 }
 static_assert(basis_orthogonal(), "MRT basis is not weighted-orthogonal");
 
-enum : int { ITEM_TILE = 0, ITEM_BOUNDARY = 1 };
+enum : int { ITEM_TILE = 0, ITEM_BOUNDARY = 1, ITEM_ROWS = 2 };
+constexpr int MAX_RECT = 12;
 
 struct BoxDesc {
   int64_t off;          // element offset of pop[0] of this box in each population arena
@@ -90,13 +91,17 @@ struct BoxDesc {
   int64_t bc_t0;
   const void* bc;       // affine: double [ns][9]; sampled: T [ns][6][res][res][3]
   int chain_first, chain_count;
-  int nbnd;             // boundary nodes of this box
-  int face_cnt[6];      // nodes per face in enumeration order
-  int face_start[6][3]; // start coordinate of each face's node ranges
-  int face_len[6][3];   // extent of each face along x, y, z
+  int nbnd;             // boundary nodes enumerated by boundary items
+  int n_rect;           // boundary rectangles (a face, or part of one)
+  int rect_face[MAX_RECT];      // face of the rectangle's nodes (-x,+x,-y,+y,-z,+z)
+  int rect_cnt[MAX_RECT];       // nodes in the rectangle
+  int rect_start[MAX_RECT][3];  // first node coordinate along x, y, z
+  int rect_len[MAX_RECT][3];    // extent along x, y, z
   float dec[3];         // FP16 decode factor per weight class: w 2^-s
   float enc[3];         // FP16 encode factor per weight class: 2^s / w
   double interior;      // number of interior nodes
+  int fast;             // non-periodic and 19*nn*sizeof(T) < 2^32 (32-bit offsets)
+  int vec;              // rows handled as 16-byte vectors (ITEM_ROWS) incl. the x-face nodes
 };
 
 struct Item {
@@ -117,8 +122,7 @@ struct DevState {
   long long step;       // time index n of the current state
   int err_key;          // 0x7fffffff when no error; else min over (owner << 4 | code index)
   int pad;
-  unsigned int done;    // workgroups finished in the current fused launch
-  unsigned int pad2;
+  long long pad2;
 };
 
 constexpr int ERR_NONE = 0x7fffffff;
@@ -146,6 +150,10 @@ template <> struct Store<2> {
 
 template <typename R>
 __device__ __forceinline__ R wgt(int i) { return (R)WD[WCLS[i]]; }
+
+// 1/rho: exact division in FP64, the hardware reciprocal (1 ulp) in FP32
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Equilibrium deviation f_eq_i(rho, u) - w_i rho0 = w_i [drho + rho(3 cu + 9/2 cu^2 - 3/2 u^2)]
 template <typename R>
@@ -255,6 +263,185 @@ __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omeg
   }
 }
 
+// ---------------------------------------------------------------------------
+// MRT in pair form.  Directions come in opposite pairs (2p-1, 2p), p = 1..9,
+// with representative velocities (1,0,0) (0,1,0) (0,0,1) (1,1,0) (1,-1,0)
+// (1,0,1) (1,0,-1) (0,1,1) (0,1,-1).  Even basis polynomials see the pair sum
+// s_p = d_{2p-1} + d_{2p}, odd ones the difference a_p = d_{2p-1} - d_{2p}, and
+// the moments of the weighted-orthogonal basis share partial sums; the
+// compile-time checks below tie these hand-written transforms to basis().
+template <typename R>
+__host__ __device__ constexpr void mrt_forward(const R d[Q], R m[Q]) {
+  R s[10] = {}, a[10] = {};
+  for (int p = 1; p <= 9; p++) {
+    s[p] = d[2 * p - 1] + d[2 * p];
+    a[p] = d[2 * p - 1] - d[2 * p];
+  }
+  const R Sa = s[1] + s[2] + s[3];
+  const R Sd = s[4] + s[5] + s[6] + s[7] + s[8] + s[9];
+  m[0] = d[0] + Sa + Sd;
+  const R Ax = a[4] + a[5] + a[6] + a[7];
+  const R Ay = a[4] - a[5] + a[8] + a[9];
+  const R Az = a[6] - a[7] + a[8] - a[9];
+  m[1] = a[1] + Ax;
+  m[2] = a[2] + Ay;
+  m[3] = a[3] + Az;
+  m[4] = Sd - d[0];
+  const R X = (s[1] + s[1]) - s[2] - s[3];
+  const R Y = (s[4] + s[5] + s[6] + s[7]) - (s[8] + s[9]) - (s[8] + s[9]);
+  m[5] = X + Y;
+  m[17] = Y - X;
+  const R P = s[2] - s[3];
+  const R Rr = s[4] + s[5] - s[6] - s[7];
+  m[6] = P + Rr;
+  m[18] = Rr - P;
+  m[7] = s[4] - s[5];
+  m[8] = s[8] - s[9];
+  m[9] = s[6] - s[7];
+  m[16] = d[0] - Sa - Sa + Sd;
+  m[10] = Ax - a[1] - a[1];
+  m[11] = Ay - a[2] - a[2];
+  m[12] = Az - a[3] - a[3];
+  m[13] = a[4] + a[5] - a[6] - a[7];
+  m[14] = a[5] - a[4] + a[8] + a[9];
+  m[15] = a[6] - a[7] - a[8] + a[9];
+}
+
+// Back transform of moments already divided by b_k: d_i = w_i sum_k e_k(c_i) M_k.
+// GZ: the nine ghost moments are zero (not read).
+template <typename R, bool GZ>
+__host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q]) {
+  const R g10 = GZ ? R(0) : M[10], g11 = GZ ? R(0) : M[11], g12 = GZ ? R(0) : M[12];
+  const R g13 = GZ ? R(0) : M[13], g14 = GZ ? R(0) : M[14], g15 = GZ ? R(0) : M[15];
+  const R g16 = GZ ? R(0) : M[16], g17 = GZ ? R(0) : M[17], g18 = GZ ? R(0) : M[18];
+  const R w0 = R(WD[0]), w1 = R(WD[1]), w2 = R(WD[2]);
+  d[0] = w0 * (M[0] - M[4] + g16);
+  const R E1 = M[0] + (M[5] + M[5]) - (g16 + g16) - (g17 + g17);
+  const R O1 = M[1] - (g10 + g10);
+  const R E2 = M[0] - M[5] + M[6] - (g16 + g16) + g17 - g18;
+  const R O2 = M[2] - (g11 + g11);
+  const R E3 = M[0] - M[5] - M[6] - (g16 + g16) + g17 + g18;
+  const R O3 = M[3] - (g12 + g12);
+  const R Bd = M[0] + M[4] + g16;           // common to the six diagonal pairs
+  const R C45 = Bd + M[5] + M[6] + g17 + g18;
+  const R C67 = Bd + M[5] - M[6] + g17 - g18;
+  const R C89 = Bd - (M[5] + M[5]) - (g17 + g17);
+  const R E4 = C45 + M[7], E5 = C45 - M[7];
+  const R E6 = C67 + M[9], E7 = C67 - M[9];
+  const R E8 = C89 + M[8], E9 = C89 - M[8];
+  const R x10 = M[1] + g10, y11 = M[2] + g11, z12 = M[3] + g12;
+  const R O4 = x10 + y11 + g13 - g14;
+  const R O5 = x10 - y11 + g13 + g14;
+  const R O6 = x10 + z12 - g13 + g15;
+  const R O7 = x10 - z12 - g13 - g15;
+  const R O8 = y11 + z12 + g14 - g15;
+  const R O9 = y11 - z12 + g14 + g15;
+  d[1] = w1 * (E1 + O1);
+  d[2] = w1 * (E1 - O1);
+  d[3] = w1 * (E2 + O2);
+  d[4] = w1 * (E2 - O2);
+  d[5] = w1 * (E3 + O3);
+  d[6] = w1 * (E3 - O3);
+  d[7] = w2 * (E4 + O4);
+  d[8] = w2 * (E4 - O4);
+  d[9] = w2 * (E5 + O5);
+  d[10] = w2 * (E5 - O5);
+  d[11] = w2 * (E6 + O6);
+  d[12] = w2 * (E6 - O6);
+  d[13] = w2 * (E7 + O7);
+  d[14] = w2 * (E7 - O7);
+  d[15] = w2 * (E8 + O8);
+  d[16] = w2 * (E8 - O8);
+  d[17] = w2 * (E9 + O9);
+  d[18] = w2 * (E9 - O9);
+}
+
+__host__ __device__ constexpr bool pair_forward_matches_basis() {
+  for (int i = 0; i < Q; i++) {
+    double d[Q] = {}, m[Q] = {};
+    d[i] = 1.0;
+    mrt_forward<double>(d, m);
+    for (int k = 0; k < Q; k++)
+      if (m[k] != (double)basis(k, CX[i], CY[i], CZ[i])) return false;
+  }
+  return true;
+}
+__host__ __device__ constexpr bool pair_backward_matches_basis() {
+  for (int k = 0; k < Q; k++) {
+    double M[Q] = {}, d[Q] = {};
+    M[k] = 1.0;
+    mrt_backward<double, false>(M, d);
+    for (int i = 0; i < Q; i++) {
+      const double want = WD[WCLS[i]] * basis(k, CX[i], CY[i], CZ[i]);
+      const double diff = d[i] - want;
+      if (diff > 1e-15 || diff < -1e-15) return false;
+    }
+  }
+  return true;
+}
+static_assert(pair_forward_matches_basis(), "pair-form forward transform != basis");
+static_assert(pair_backward_matches_basis(), "pair-form back transform != basis");
+
+// MRT collision in pair form on deviations (moments of d equal those of f for
+// k >= 1; m_0 is the density deviation).  GZ: ghost relaxation rate 1.
+template <typename R, bool GZ>
+__device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rho0, R omega,
+                                                  R om_bulk, R om_ghost) {
+  R m[Q];
+  mrt_forward<R>(d, m);
+  const R drho = m[0];
+  const R rho = rho0 + drho;
+  const R inv = recip(rho);
+  const R ux = (m[1] + (R)0.5 * gx) * inv;
+  const R uy = (m[2] + (R)0.5 * gy) * inv;
+  const R uz = (m[3] + (R)0.5 * gz) * inv;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R ug = ux * gx + uy * gy + uz * gz;
+  R M[Q];
+  M[0] = drho;
+  M[1] = (m[1] + gx) * (R)3;
+  M[2] = (m[2] + gy) * (R)3;
+  M[3] = (m[3] + gz) * (R)3;
+  const R gb = (R)1 - om_bulk, hb = (R)0.5 * ((R)1 + gb);
+  const R gs = (R)1 - omega, hs = (R)0.5 * ((R)1 + gs);
+  {
+    const R eq = rho * uu;
+    M[4] = (eq + gb * (m[4] - eq) + hb * ((R)2 * ug)) * (R)1.5;
+  }
+  {
+    const R eq = rho * ((R)3 * ux * ux - uu);
+    M[5] = (eq + gs * (m[5] - eq) + hs * ((R)2 * ((R)3 * ux * gx - ug))) * (R)0.75;
+  }
+  {
+    const R eq = rho * (uy * uy - uz * uz);
+    M[6] = (eq + gs * (m[6] - eq) + hs * ((R)2 * (uy * gy - uz * gz))) * (R)2.25;
+  }
+  {
+    const R eq = rho * ux * uy;
+    M[7] = (eq + gs * (m[7] - eq) + hs * (ux * gy + uy * gx)) * (R)9;
+  }
+  {
+    const R eq = rho * uy * uz;
+    M[8] = (eq + gs * (m[8] - eq) + hs * (uy * gz + uz * gy)) * (R)9;
+  }
+  {
+    const R eq = rho * ux * uz;
+    M[9] = (eq + gs * (m[9] - eq) + hs * (ux * gz + uz * gx)) * (R)9;
+  }
+  if (!GZ) {
+    const R gg = (R)1 - om_ghost;
+#pragma unroll
+    for (int k = 10; k < Q; k++) M[k] = gg * m[k] * (R)INVB[k];
+  }
+  mrt_backward<R, GZ>(M, d);
+}
+
+// Arena layout: rows of 19 populations, pop[z][y][i][x] (x fastest).  The
+// populations a node pulls lie in at most nine neighbouring row blocks.
+__host__ __device__ __forceinline__ int64_t aidx(const BoxDesc& b, int i, int x, int y, int z) {
+  return ((int64_t)(z * b.ny + y) * Q + i) * b.nx + x;
+}
+
 // Neighbour coordinate with wrap on periodic axes.
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -266,11 +453,9 @@ __device__ __forceinline__ void load_pre(const typename Store<S>::T* __restrict_
                                          const BoxDesc& b, int x, int y, int z, bool pre,
                                          typename Store<S>::R d[Q]) {
   using St = Store<S>;
-  const int64_t nn = b.nn;
   if (pre) {
-    const int node = (z * b.ny + y) * b.nx + x;
 #pragma unroll
-    for (int i = 0; i < Q; i++) d[i] = St::dec(src[i * nn + node], b.dec[WCLS[i]]);
+    for (int i = 0; i < Q; i++) d[i] = St::dec(src[aidx(b, i, x, y, z)], b.dec[WCLS[i]]);
     return;
   }
 #pragma unroll
@@ -281,8 +466,7 @@ __device__ __forceinline__ void load_pre(const typename Store<S>::T* __restrict_
       if (b.pmask & 2) sy = wrapc(sy, b.ny);
       if (b.pmask & 4) sz = wrapc(sz, b.nz);
     }
-    const int node = (sz * b.ny + sy) * b.nx + sx;
-    d[i] = St::dec(src[i * nn + node], b.dec[WCLS[i]]);
+    d[i] = St::dec(src[aidx(b, i, sx, sy, sz)], b.dec[WCLS[i]]);
   }
 }
 

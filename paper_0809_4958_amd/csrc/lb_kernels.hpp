@@ -11,8 +11,9 @@
 //             atomics), collide and store; boundary items store the boundary
 //             equilibrium populations that point into the interior.  On check
 //             steps every item writes FP64 partial sums of mass and momentum
-//             at t_{n+1}; the last workgroup to finish reduces them in a fixed
-//             order per box and advances the device step counter.
+//             at t_{n+1}.
+//   k_finalize one workgroup after k_lb: reduces the partials in a fixed
+//             order per box, checks finiteness, advances the step counter.
 //   k_set_pre / k_read / k_read_sites   state upload and readout.
 #pragma once
 #include "lb_device.hpp"
@@ -335,7 +336,6 @@ __device__ __forceinline__ bool is_interior(const BoxDesc& b, int x, int y, int 
          ((b.pmask & 4) || (z >= 1 && z <= b.nz - 2));
 }
 
-// ----------------------------------------------------------- fused step
 struct LbArgs {
   const BoxDesc* boxes;
   const Item* items;
@@ -360,13 +360,326 @@ struct LbArgs {
   int advance;
 };
 
-template <int S, int COLL, bool PER>
-__global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
+// Collision dispatcher: 0 BGK, 1 MRT, 2 MRT with ghost rate 1.
+template <typename R, int COLL>
+__device__ __forceinline__ void collide_any(R d[Q], R gx, R gy, R gz, R rho0, R omega, R omb,
+                                            R omg) {
+  if (COLL == 0) collide<R, 0>(d, gx, gy, gz, rho0, omega, omb, omg);
+  else if (COLL == 1) collide_mrt_pairs<R, false>(d, gx, gy, gz, rho0, omega, omb, omg);
+  else collide_mrt_pairs<R, true>(d, gx, gy, gz, rho0, omega, omb, omg);
+}
+
+// Spread force g(x) = - sum_j w_jx dP_j at node (x, y, z): chains whose stencil
+// box overlaps the tile (cmask), beads in fixed order, no atomics.
+template <typename R, bool PER>
+__device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
+                                             unsigned long long cmask, int x, int y, int z, R& gx,
+                                             R& gy, R& gz) {
+  const R* rd = (const R*)A.rec_d;
+  const R* rp = (const R*)A.rec_dp;
+  for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
+    if (!((cmask >> c) & 1ull)) continue;
+    const int gc = b.chain_first + c;
+    const int* bb = A.bbox + 6 * gc;
+    if (z < bb[2] || z > bb[5]) continue;
+    if (!(x >= bb[0] && x <= bb[3] && y >= bb[1] && y <= bb[4])) continue;
+    const ChainDesc& ch = A.chains[gc];
+    for (int jb = ch.first; jb < ch.first + ch.nb; jb++) {
+      const int4 bs = A.rec_base[jb];
+      int ox = x - bs.x, oy = y - bs.y, oz = z - bs.z;
+      if (PER) {
+        if ((b.pmask & 1) && ox < 0) ox += b.nx;
+        if ((b.pmask & 2) && oy < 0) oy += b.ny;
+        if ((b.pmask & 4) && oz < 0) oz += b.nz;
+      }
+      if ((unsigned)ox > 1u || (unsigned)oy > 1u || (unsigned)oz > 1u) continue;
+      const R w = (ox ? rd[3 * jb] : (R)1 - rd[3 * jb]) *
+                  (oy ? rd[3 * jb + 1] : (R)1 - rd[3 * jb + 1]) *
+                  (oz ? rd[3 * jb + 2] : (R)1 - rd[3 * jb + 2]);
+      gx -= w * rp[3 * jb];
+      gy -= w * rp[3 * jb + 1];
+      gz -= w * rp[3 * jb + 2];
+    }
+  }
+}
+
+// Contribution of the stored populations of node (x, y, z) to the interior's
+// mass and momentum at t_{n+1} (those that stream to an interior node).
+template <int S, bool PER>
+__device__ __forceinline__ void check_acc(const BoxDesc& b, int x, int y, int z,
+                                          const typename Store<S>::R d[Q], double acc[4]) {
+  using St = Store<S>;
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+    if (PER) {
+      if (b.pmask & 1) tx = wrapc(tx, b.nx);
+      if (b.pmask & 2) ty = wrapc(ty, b.ny);
+      if (b.pmask & 4) tz = wrapc(tz, b.nz);
+    }
+    if (!is_interior(b, tx, ty, tz)) continue;
+    const double v = (double)St::dec(St::enc(d[i], b.enc[WCLS[i]]), b.dec[WCLS[i]]);
+    acc[0] += v;
+    if (CX[i]) acc[1] += CX[i] * v;
+    if (CY[i]) acc[2] += CY[i] * v;
+    if (CZ[i]) acc[3] += CZ[i] * v;
+  }
+}
+
+// Interior tile of a non-periodic box whose population groups (0..9 and
+// 10..18) each span less than 4 GiB: every load is one 32-bit offset add on
+// a per-thread node offset plus a scalar (uniform) group base.
+template <int S, int COLL, bool CHECK, bool GATHER, int BS>
+__device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, const Item& it,
+                                          const typename Store<S>::T* src,
+                                          typename Store<S>::T* dst, bool pre,
+                                          unsigned long long cmask, typename Store<S>::R rho0,
+                                          typename Store<S>::R omega, typename Store<S>::R omb,
+                                          typename Store<S>::R omg, double acc[4]) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
-  __shared__ double sred[4][WG / 64];
-  __shared__ int s_last;
+  constexpr unsigned SB = sizeof(T);
+  const unsigned nx = (unsigned)b.nx, ny = (unsigned)b.ny;
+  const unsigned rs = (unsigned)Q * nx;   // row-block stride (elements)
+  const unsigned ps = rs * ny;            // plane stride
+  const char* __restrict__ s0 = (const char*)src;
+  char* __restrict__ d0 = (char*)dst;
+  unsigned so[Q], doff[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int delta = pre ? 0 : CX[i] + CY[i] * (int)rs + CZ[i] * (int)ps;
+    so[i] = (unsigned)i * nx * SB - (unsigned)delta * SB;
+    doff[i] = (unsigned)i * nx * SB;
+  }
+  const float dc0 = b.dec[0], dc1 = b.dec[1], dc2 = b.dec[2];
+  const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
+  const int plane = it.ex * it.ey;
+#pragma unroll 1
+  for (int p = threadIdx.x; p < plane; p += BS) {
+    const int x = it.x0 + p % it.ex;
+    const int y = it.y0 + p / it.ex;
+    unsigned voff = (((unsigned)it.z0 * ny + (unsigned)y) * rs + (unsigned)x) * SB;
+#pragma unroll 1
+    for (int z = it.z0; z < it.z0 + it.ez; z++, voff += ps * SB) {
+      R d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const T v = *(const T*)(s0 + (voff + so[i]));
+        const float k = WCLS[i] == 0 ? dc0 : (WCLS[i] == 1 ? dc1 : dc2);
+        d[i] = St::dec(v, k);
+      }
+      R gx = 0, gy = 0, gz = 0;
+      if (GATHER) gather_force<R, false>(A, b, cmask, x, y, z, gx, gy, gz);
+      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const float k = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
+        *(T*)(d0 + (voff + doff[i])) = St::enc(d[i], k);
+      }
+      if (CHECK) check_acc<S, false>(b, x, y, z, d, acc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row items: each lane owns V consecutive nodes of one x-row (V * sizeof(T) =
+// 16 bytes: 8 FP16 or 4 FP32 values) and moves every population with one
+// aligned 16-byte load and one 16-byte store.  The pull's +-1 shift in x is an
+// element selection inside the lane's vector plus one value from the
+// neighbouring lane (rows never straddle a wavefront); shifts in y and z move
+// the whole row.  The lane holding x = 0 or x = nx-1 stores the boundary
+// equilibrium of that node (face -x or +x), so every store is a full vector.
+template <int S>
+struct VecT {
+  using T = typename Store<S>::T;
+  static constexpr int V = 16 / (int)sizeof(T);
+};
+
+template <int S>
+__device__ __forceinline__ typename Store<S>::T vget(const uint4& v, int e) {
+  using T = typename Store<S>::T;
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+  if constexpr (sizeof(T) == 2) {
+    const unsigned word = w[e >> 1];
+    const unsigned short h = (unsigned short)((e & 1) ? (word >> 16) : (word & 0xffffu));
+    return __builtin_bit_cast(T, h);
+  } else {
+    return __builtin_bit_cast(T, w[e]);
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void vset(uint4& v, int e, typename Store<S>::T val) {
+  using T = typename Store<S>::T;
+  unsigned* w = &v.x;
+  if constexpr (sizeof(T) == 2) {
+    const unsigned h = (unsigned)__builtin_bit_cast(unsigned short, val);
+    unsigned& word = w[e >> 1];
+    word = (e & 1) ? ((word & 0xffffu) | (h << 16)) : ((word & 0xffff0000u) | h);
+  } else {
+    w[e] = __builtin_bit_cast(unsigned, val);
+  }
+}
+
+// element e of population i's source vector, e in [-1, V]: -1 and V come from
+// the neighbouring lanes' vectors (left: its last element, right: its first)
+template <int S>
+__device__ __forceinline__ typename Store<S>::T vsrc(const uint4& v, unsigned left, unsigned right,
+                                                     int e) {
+  using T = typename Store<S>::T;
+  constexpr int V = VecT<S>::V;
+  if (e == -1) {
+    if constexpr (sizeof(T) == 2) return __builtin_bit_cast(T, (unsigned short)(left >> 16));
+    else return __builtin_bit_cast(T, left);
+  }
+  if (e == V) {
+    if constexpr (sizeof(T) == 2) return __builtin_bit_cast(T, (unsigned short)(right & 0xffffu));
+    else return __builtin_bit_cast(T, right);
+  }
+  return vget<S>(v, e);
+}
+
+template <int S, int COLL, bool CHECK, bool GATHER, bool PRE, int BS>
+__device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, const Item& it,
+                                          const typename Store<S>::T* src,
+                                          typename Store<S>::T* dst, long long step,
+                                          unsigned long long cmask, typename Store<S>::R rho0,
+                                          typename Store<S>::R omega, typename Store<S>::R omb,
+                                          typename Store<S>::R omg, double acc[4]) {
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  constexpr int V = VecT<S>::V;
+  constexpr unsigned SB = sizeof(T);
+  const unsigned nx = (unsigned)b.nx, ny = (unsigned)b.ny;
+  const unsigned rs = (unsigned)Q * nx;   // row-block stride (elements)
+  const size_t ps = (size_t)rs * ny;      // plane stride
+  // offsets inside a plane: population i of the row y - c_y (the plane z - c_z
+  // is chosen by base pointer)
+  unsigned so[Q], doff[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int dy = PRE ? 0 : CY[i];
+    so[i] = ((unsigned)i * nx - (unsigned)(dy * (int)rs)) * SB;
+    doff[i] = (unsigned)i * nx * SB;
+  }
+  const float dc0 = b.dec[0], dc1 = b.dec[1], dc2 = b.dec[2];
+  const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
+  const int L = (int)nx / V;              // lanes per row
+  const int rpw = 64 / L;                 // rows per wavefront
+  const int lane = (int)(threadIdx.x & 63);
+  const int wave = (int)(threadIdx.x >> 6);
+  const int r = lane / L, c = lane - (lane / L) * L;
+  const int y = it.y0 + wave * rpw + r;
+  const bool act = r < rpw && y < it.y0 + it.ey;
+  const int x0 = c * V;
+  const unsigned lane_l = (unsigned)(lane - 1) & 63u, lane_r = (unsigned)(lane + 1) & 63u;
+  const unsigned voff = ((unsigned)(act ? y : it.y0) * rs + (unsigned)x0) * SB;
+#pragma unroll 1
+  for (int z = it.z0; z < it.z0 + it.ez; z++) {
+    const char* __restrict__ pz = (const char*)(src + (size_t)z * ps);
+    const char* __restrict__ pm = (const char*)(src + (size_t)(z - 1) * ps);
+    const char* __restrict__ pp = (const char*)(src + (size_t)(z + 1) * ps);
+    char* __restrict__ dz = (char*)(dst + (size_t)z * ps);
+    uint4 raw[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      const char* base = (PRE || CZ[i] == 0) ? pz : (CZ[i] == 1 ? pm : pp);
+      raw[i] = act ? *(const uint4*)(base + (voff + so[i])) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    // neighbour-lane elements for the populations shifted in x
+    unsigned left[Q], right[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      left[i] = 0u;
+      right[i] = 0u;
+      if (!PRE && CX[i] == 1) left[i] = __shfl(raw[i].w, (int)lane_l, 64);
+      if (!PRE && CX[i] == -1) right[i] = __shfl(raw[i].x, (int)lane_r, 64);
+    }
+    uint4 out[Q];
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+      R d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const int e = PRE ? k : k - CX[i];
+        const float kd = WCLS[i] == 0 ? dc0 : (WCLS[i] == 1 ? dc1 : dc2);
+        d[i] = St::dec(vsrc<S>(raw[i], left[i], right[i], e), kd);
+      }
+      const int x = x0 + k;
+      R gx = 0, gy = 0, gz = 0;
+      if (GATHER) gather_force<R, false>(A, b, cmask, x, y, z, gx, gy, gz);
+      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+      if (CHECK && act && x >= 1 && x <= (int)nx - 2) check_acc<S, false>(b, x, y, z, d, acc);
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
+        vset<S>(out[i], k, St::enc(d[i], ke));
+      }
+    }
+    // x-face nodes of this row: boundary equilibrium at t_n (faces -x, +x)
+    if (act && (c == 0 || c == L - 1)) {
+#pragma unroll
+      for (int side = 0; side < 2; side++) {
+        if ((side == 0 && c != 0) || (side == 1 && c != L - 1)) continue;
+        const int q[3] = {side == 0 ? 0 : (int)nx - 1, y, z};
+        R u[3];
+        boundary_velocity<R>(b, side, q, step, u);
+        R eq[Q];
+        eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
+        if (CHECK) check_acc<S, false>(b, q[0], y, z, eq, acc);
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
+          vset<S>(out[i], side == 0 ? 0 : V - 1, St::enc(eq[i], ke));
+        }
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) *(uint4*)(dz + (voff + doff[i])) = out[i];
+    }
+  }
+}
+
+// Interior tile, general addressing (periodic axes wrap, any box size).
+template <int S, int COLL, bool PER, int BS>
+__device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, const Item& it,
+                                             const typename Store<S>::T* src,
+                                             typename Store<S>::T* dst, bool pre, bool check,
+                                             unsigned long long cmask, typename Store<S>::R rho0,
+                                             typename Store<S>::R omega, typename Store<S>::R omb,
+                                             typename Store<S>::R omg, double acc[4]) {
+  using St = Store<S>;
+  using R = typename St::R;
+  const int plane = it.ex * it.ey;
+#pragma unroll 1
+  for (int p = threadIdx.x; p < plane; p += BS) {
+    const int x = it.x0 + p % it.ex;
+    const int y = it.y0 + p / it.ex;
+#pragma unroll 1
+    for (int z = it.z0; z < it.z0 + it.ez; z++) {
+      R d[Q];
+      load_pre<S, PER>(src, b, x, y, z, pre, d);
+      R gx = 0, gy = 0, gz = 0;
+      if (cmask) gather_force<R, PER>(A, b, cmask, x, y, z, gx, gy, gz);
+      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+#pragma unroll
+      for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+      if (check) check_acc<S, PER>(b, x, y, z, d, acc);
+    }
+  }
+}
+
+// ----------------------------------------------------------- fused step
+
+template <int S, int COLL, bool PER, int BS = WG>
+__global__ __launch_bounds__(BS, (S == 0 ? 4 : 2)) void k_lb(LbArgs A) {
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  __shared__ double sred[4][BS / 64];
 
   const int tid = threadIdx.x;
   const bool skip =
@@ -390,7 +703,27 @@ __global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
     const int64_t nn = b.nn;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 
-    if (it.kind == ITEM_TILE) {
+    if (it.kind == ITEM_ROWS) {
+      unsigned long long cmask = 0;
+      for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
+        const int* bb = A.bbox + 6 * (b.chain_first + c);
+        const bool ov = bb[1] <= it.y0 + it.ey - 1 && bb[4] >= it.y0 && bb[2] <= it.z0 + it.ez - 1 &&
+                        bb[5] >= it.z0;
+        if (ov) cmask |= 1ull << c;
+      }
+      if constexpr (S != 0 && !PER) {
+#define LB_ROWS(CH, GA, PR) \
+  tile_rows<S, COLL, CH, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg, acc)
+        if (pre) {
+          if (cmask) { if (check) LB_ROWS(true, true, true); else LB_ROWS(false, true, true); }
+          else { if (check) LB_ROWS(true, false, true); else LB_ROWS(false, false, true); }
+        } else {
+          if (cmask) { if (check) LB_ROWS(true, true, false); else LB_ROWS(false, true, false); }
+          else { if (check) LB_ROWS(true, false, false); else LB_ROWS(false, false, false); }
+        }
+#undef LB_ROWS
+      }
+    } else if (it.kind == ITEM_TILE) {
       // chains whose stencil box overlaps this tile
       unsigned long long cmask = 0;
       for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
@@ -399,93 +732,36 @@ __global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
                         bb[4] >= it.y0 && bb[2] <= it.z0 + it.ez - 1 && bb[5] >= it.z0;
         if (ov) cmask |= 1ull << c;
       }
-      const int plane = it.ex * it.ey;
-#pragma unroll 1
-      for (int p = tid; p < plane; p += WG) {
-        // each thread marches one (x, y) column of the tile along z
-        const int x = it.x0 + p % it.ex;
-        const int y = it.y0 + p / it.ex;
-#pragma unroll 1
-        for (int z = it.z0; z < it.z0 + it.ez; z++) {
-          const int node = (z * b.ny + y) * b.nx + x;
-          R d[Q];
-          load_pre<S, PER>(src, b, x, y, z, pre, d);
-          // spread force: g(x) = - sum_j w_jx dP_j in fixed chain/bead order
-          R gx = 0, gy = 0, gz = 0;
-          if (cmask) {
-            const R* rd = (const R*)A.rec_d;
-            const R* rp = (const R*)A.rec_dp;
-            for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
-              if (!((cmask >> c) & 1ull)) continue;
-              const int gc = b.chain_first + c;
-              const int* bb = A.bbox + 6 * gc;
-              if (z < bb[2] || z > bb[5]) continue;
-              const ChainDesc& ch = A.chains[gc];
-              const bool inside = x >= bb[0] && x <= bb[3] && y >= bb[1] && y <= bb[4];
-              if (!inside) continue;
-              for (int jb = ch.first; jb < ch.first + ch.nb; jb++) {
-                const int4 bs = A.rec_base[jb];
-                int ox = x - bs.x, oy = y - bs.y, oz = z - bs.z;
-                if (PER) {
-                  if ((b.pmask & 1) && ox < 0) ox += b.nx;
-                  if ((b.pmask & 2) && oy < 0) oy += b.ny;
-                  if ((b.pmask & 4) && oz < 0) oz += b.nz;
-                }
-                if ((unsigned)ox > 1u || (unsigned)oy > 1u || (unsigned)oz > 1u) continue;
-                const R w = (ox ? rd[3 * jb] : (R)1 - rd[3 * jb]) *
-                            (oy ? rd[3 * jb + 1] : (R)1 - rd[3 * jb + 1]) *
-                            (oz ? rd[3 * jb + 2] : (R)1 - rd[3 * jb + 2]);
-                gx -= w * rp[3 * jb];
-                gy -= w * rp[3 * jb + 1];
-                gz -= w * rp[3 * jb + 2];
-              }
-            }
-          }
-          collide<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
-#pragma unroll
-          for (int i = 0; i < Q; i++) dst[i * nn + node] = St::enc(d[i], b.enc[WCLS[i]]);
-          if (check) {
-            // contribution of this node's stored populations to M, P at t_{n+1}
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-              int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
-              if (PER) {
-                if (b.pmask & 1) tx = wrapc(tx, b.nx);
-                if (b.pmask & 2) ty = wrapc(ty, b.ny);
-                if (b.pmask & 4) tz = wrapc(tz, b.nz);
-              }
-              if (!is_interior(b, tx, ty, tz)) continue;
-              const double v = (double)St::dec(St::enc(d[i], b.enc[WCLS[i]]), b.dec[WCLS[i]]);
-              acc[0] += v;
-              if (CX[i]) acc[1] += CX[i] * v;
-              if (CY[i]) acc[2] += CY[i] * v;
-              if (CZ[i]) acc[3] += CZ[i] * v;
-            }
-          }
+      if (!PER && b.fast) {
+        if (cmask) {
+          if (check) tile_fast<S, COLL, true, true, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg, acc);
+          else tile_fast<S, COLL, false, true, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg, acc);
+        } else {
+          if (check) tile_fast<S, COLL, true, false, BS>(A, b, it, src, dst, pre, 0, rho0, omega, omb, omg, acc);
+          else tile_fast<S, COLL, false, false, BS>(A, b, it, src, dst, pre, 0, rho0, omega, omb, omg, acc);
         }
+      } else {
+        tile_generic<S, COLL, PER, BS>(A, b, it, src, dst, pre, check, cmask, rho0, omega, omb, omg, acc);
       }
     } else {
       // boundary chunk: equilibrium at rho0 and u_b(t_n) for the populations
       // that stream into the interior
-      for (int k = it.x0 + tid; k < it.x0 + it.ex; k += WG) {
-        int f = 0, kk = k;
-        while (f < 5 && kk >= b.face_cnt[f]) {
-          kk -= b.face_cnt[f];
-          f++;
+      for (int k = it.x0 + tid; k < it.x0 + it.ex; k += BS) {
+        int r = 0, kk = k;
+        while (r < b.n_rect - 1 && kk >= b.rect_cnt[r]) {
+          kk -= b.rect_cnt[r];
+          r++;
         }
-        const int a = f >> 1;
-        const int au = (a == 0) ? 1 : 0;
-        const int av = (a == 2) ? 1 : 2;
-        const int lu = b.face_len[f][au];
+        const int f = b.rect_face[r];
+        const int lx = b.rect_len[r][0], ly = b.rect_len[r][1];
         int q[3];
-        q[a] = b.face_start[f][a];
-        q[au] = b.face_start[f][au] + kk % lu;
-        q[av] = b.face_start[f][av] + kk / lu;
+        q[0] = b.rect_start[r][0] + kk % lx;
+        q[1] = b.rect_start[r][1] + (kk / lx) % ly;
+        q[2] = b.rect_start[r][2] + kk / (lx * ly);
         R u[3];
         boundary_velocity<R>(b, f, q, step, u);
         R eq[Q];
         eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
-        const int node = (q[2] * b.ny + q[1]) * b.nx + q[0];
 #pragma unroll
         for (int i = 1; i < Q; i++) {
           int tx = q[0] + CX[i], ty = q[1] + CY[i], tz = q[2] + CZ[i];
@@ -496,7 +772,7 @@ __global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
           }
           if (!is_interior(b, tx, ty, tz)) continue;
           const T v = St::enc(eq[i], b.enc[WCLS[i]]);
-          dst[i * nn + node] = v;
+          dst[aidx(b, i, q[0], q[1], q[2])] = v;
           if (check) {
             const double dv = (double)St::dec(v, b.dec[WCLS[i]]);
             acc[0] += dv;
@@ -517,23 +793,23 @@ __global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
       __syncthreads();
       if (tid < 4) {
         double s = 0.0;
-        for (int w = 0; w < WG / 64; w++) s += sred[tid][w];
+        for (int w = 0; w < BS / 64; w++) s += sred[tid][w];
         A.partials[4 * ii + tid] = s;
       }
       __syncthreads();
     }
   }
 
-  // last workgroup: per-box fixed-order sums, finiteness check, step advance
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(&A.st->done, 1u);
-    s_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// One workgroup after the fused step: per-box fixed-order sums of the item
+// partials (on check steps), finiteness check, device step advance.  Runs as
+// its own launch so that the fused kernel needs no device-wide fences.
+__global__ __launch_bounds__(WG) void k_finalize(LbArgs A) {
+  const int tid = threadIdx.x;
+  if (A.st->err_key != ERR_NONE) return;
+  const long long step = A.st->step;
+  const bool check = A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0;
   __shared__ int s_bad;
   if (tid == 0) s_bad = 0x7fffffff;
   __syncthreads();
@@ -543,9 +819,7 @@ __global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
       for (int q = A.box_items_off[bx]; q < A.box_items_off[bx + 1]; q++) {
         const int item = A.box_items[q];
 #pragma unroll
-        for (int m = 0; m < 4; m++)
-          s[m] += __hip_atomic_load(&A.partials[4 * item + m], __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
+        for (int m = 0; m < 4; m++) s[m] += A.partials[4 * item + m];
       }
       const double M = A.rho0 * A.boxes[bx].interior + s[0];
       double* mm = A.mass_mom + 5 * bx;
@@ -556,16 +830,13 @@ __global__ __launch_bounds__(WG, 4) void k_lb(LbArgs A) {
       mm[4] = s[3];
       if (!(isfinite(M) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]))) atomicMin(&s_bad, bx);
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (tid == 0) {
-    A.st->done = 0;
-    if (s_bad != 0x7fffffff) {
-      atomicMin(&A.st->err_key, (s_bad << 4) | EC_UNSTABLE);
-    } else if (A.advance) {
+    if (s_bad != 0x7fffffff)
+      A.st->err_key = (s_bad << 4) | EC_UNSTABLE;
+    else if (A.advance)
       A.st->step = step + 1;
-    }
-    __threadfence();
   }
 }
 
@@ -603,7 +874,7 @@ __global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T*
       for (int i = 0; i < Q; i++) d[i] = (R)eq[i];
     }
 #pragma unroll
-    for (int i = 0; i < Q; i++) dst[i * nn + node] = St::enc(d[i], b.enc[WCLS[i]]);
+    for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
   }
 }
 
@@ -693,6 +964,23 @@ __global__ void k_read_beads(const ChainDesc* __restrict__ chains, int c0, int c
       }
     o += ch.nb;
   }
+}
+
+// stream copy with 16-byte accesses, four independent loads in flight per
+// thread (HBM ceiling probe); n is a multiple of 4 * WG * gridDim.x or the
+// tail is copied one vector at a time
+__global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                             size_t n) {
+  const size_t stride = (size_t)gridDim.x * WG;
+  size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 }  // namespace lbdev

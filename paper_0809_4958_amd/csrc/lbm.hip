@@ -13,6 +13,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -42,10 +43,13 @@ struct BoxHost {
   int64_t bc_t0 = 0;
   void* d_bc = nullptr;
   int ex = 0, ey = 0, ez = 0;  // tile shape
-  int face_cnt[6] = {0, 0, 0, 0, 0, 0};
-  int face_start[6][3] = {};
-  int face_len[6][3] = {};
+  int n_rect = 0;
+  int rect_face[MAX_RECT] = {};
+  int rect_cnt[MAX_RECT] = {};
+  int rect_start[MAX_RECT][3] = {};
+  int rect_len[MAX_RECT][3] = {};
   int nbnd = 0;
+  bool vec = false;  // interior rows as 16-byte vectors (ITEM_ROWS), x-face nodes included
 };
 
 struct ChainHost {
@@ -62,7 +66,7 @@ using ChainLaunch = void (*)(int, hipStream_t, const BoxDesc*, const ChainDesc*,
 
 template <int S, int C, bool P>
 void launch_lb(dim3 g, hipStream_t s, const LbArgs& a) {
-  hipLaunchKernelGGL((k_lb<S, C, P>), g, dim3(WG), 0, s, a);
+  hipLaunchKernelGGL((k_lb<S, C, P, WG>), g, dim3(WG), 0, s, a);
 }
 
 template <int S, bool P>
@@ -95,10 +99,12 @@ void launch_sites(bool per, int nblk, hipStream_t s, const BoxDesc& d, const voi
     hipLaunchKernelGGL((k_read_sites<S, false>), dim3(nblk), dim3(WG), 0, s, d, (const T*)src, xyz, n, out, pre, r0);
 }
 
+// coll: 0 BGK, 1 MRT, 2 MRT with ghost relaxation rate 1 (ghost moments not formed)
 template <int S>
 LbLaunch pick_lb(int coll, bool per) {
   if (coll == 0) return per ? launch_lb<S, 0, true> : launch_lb<S, 0, false>;
-  return per ? launch_lb<S, 1, true> : launch_lb<S, 1, false>;
+  if (coll == 1) return per ? launch_lb<S, 1, true> : launch_lb<S, 1, false>;
+  return per ? launch_lb<S, 2, true> : launch_lb<S, 2, false>;
 }
 
 size_t store_bytes(int s) { return s == LB_STORE_F64 ? 8 : (s == LB_STORE_F32 ? 4 : 2); }
@@ -311,6 +317,25 @@ lb_status build_tables(lb_ctx* ctx, int grid_override) {
       items.push_back(it);
       work.push_back(0.25 * it.ex);
     }
+    if (b.vec) {
+      const int V = 16 / (int)store_bytes(ctx->S);
+      const int rows = (WG / 64) * (64 / (b.dim.nx / V));  // rows per workgroup
+      for (int z = 0; z < b.iz; z += b.ez)
+        for (int y = 0; y < b.iy; y += rows) {
+          Item it{};
+          it.box = (int)bi;
+          it.kind = ITEM_ROWS;
+          it.x0 = 0;
+          it.y0 = 1 + y;
+          it.z0 = 1 + z;
+          it.ex = b.dim.nx;
+          it.ey = std::min(rows, b.iy - y);
+          it.ez = std::min(b.ez, b.iz - z);
+          items.push_back(it);
+          work.push_back((double)it.ex * it.ey * it.ez);
+        }
+      continue;
+    }
     for (int z = 0; z < b.iz; z += b.ez)
       for (int y = 0; y < b.iy; y += b.ey)
         for (int x = 0; x < b.ix; x += b.ex) {
@@ -421,18 +446,22 @@ lb_status upload_boxes(lb_ctx* ctx) {
     d.chain_first = cfirst[i];
     d.chain_count = ccount[i];
     d.nbnd = b.nbnd;
-    for (int f = 0; f < 6; f++) {
-      d.face_cnt[f] = b.face_cnt[f];
+    d.n_rect = b.n_rect;
+    for (int r = 0; r < MAX_RECT; r++) {
+      d.rect_face[r] = b.rect_face[r];
+      d.rect_cnt[r] = b.rect_cnt[r];
       for (int a = 0; a < 3; a++) {
-        d.face_start[f][a] = b.face_start[f][a];
-        d.face_len[f][a] = b.face_len[f][a];
+        d.rect_start[r][a] = b.rect_start[r][a];
+        d.rect_len[r][a] = b.rect_len[r][a];
       }
     }
+    d.vec = b.vec ? 1 : 0;
     for (int c = 0; c < 3; c++) {
       d.enc[c] = (float)(s2 / WD[c]);
       d.dec[c] = (float)(WD[c] / s2);
     }
     d.interior = (double)b.interior;
+    d.fast = (b.dim.periodic_mask == 0 && (double)Q * (double)b.nn * (double)store_bytes(ctx->S) < 4294967296.0) ? 1 : 0;
     ctx->h_boxes[i] = d;
   }
   HIPCHK(h2d(ctx, ctx->d_boxes, ctx->h_boxes.data(), ctx->h_boxes.size() * sizeof(BoxDesc)));
@@ -601,40 +630,65 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed) {
     e1 = next_event(ctx);
     (void)hipEventRecord(e1, s);
   }
-  ctx->lb_fn(dim3(ctx->grid), s, make_args(ctx, pre, 1, ctx->cfg.reduce_every));
+  const LbArgs a = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
+  ctx->lb_fn(dim3(ctx->grid), s, a);
   if (timed) {
     e2 = next_event(ctx);
     (void)hipEventRecord(e2, s);
   }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, s, a);
+}
+
+// Boundary nodes enumerated by boundary items, as rectangles.  Face priority
+// -x, +x, -y, +y, -z, +z: a face excludes the nodes of earlier (lower-axis)
+// faces.  For vector boxes the x-face nodes of interior rows (1 <= y <= ny-2,
+// 1 <= z <= nz-2) are written by the row items and left out here.
+void add_rect(BoxHost& b, int f, int x0, int lx, int y0, int ly, int z0, int lz) {
+  if (lx <= 0 || ly <= 0 || lz <= 0) return;
+  const int r = b.n_rect++;
+  b.rect_face[r] = f;
+  b.rect_start[r][0] = x0;
+  b.rect_start[r][1] = y0;
+  b.rect_start[r][2] = z0;
+  b.rect_len[r][0] = lx;
+  b.rect_len[r][1] = ly;
+  b.rect_len[r][2] = lz;
+  b.rect_cnt[r] = lx * ly * lz;
+  b.nbnd += lx * ly * lz;
 }
 
 void face_tables(BoxHost& b) {
   const int n3[3] = {b.dim.nx, b.dim.ny, b.dim.nz};
   const unsigned pm = b.dim.periodic_mask;
   b.nbnd = 0;
+  b.n_rect = 0;
   for (int f = 0; f < 6; f++) {
     const int a = f / 2;
-    if ((pm >> a) & 1u) {
-      b.face_cnt[f] = 0;
-      for (int k = 0; k < 3; k++) b.face_start[f][k] = 0, b.face_len[f][k] = 1;
-      continue;
-    }
-    int cnt = 1;
+    if ((pm >> a) & 1u) continue;
+    int st[3], ln[3];
     for (int k = 0; k < 3; k++) {
       if (k == a) {
-        b.face_start[f][k] = (f % 2) ? n3[k] - 1 : 0;
-        b.face_len[f][k] = 1;
+        st[k] = (f % 2) ? n3[k] - 1 : 0;
+        ln[k] = 1;
       } else if (k < a && !((pm >> k) & 1u)) {
-        b.face_start[f][k] = 1;
-        b.face_len[f][k] = n3[k] - 2;
+        st[k] = 1;
+        ln[k] = n3[k] - 2;
       } else {
-        b.face_start[f][k] = 0;
-        b.face_len[f][k] = n3[k];
+        st[k] = 0;
+        ln[k] = n3[k];
       }
-      cnt *= b.face_len[f][k];
     }
-    b.face_cnt[f] = cnt;
-    b.nbnd += cnt;
+    if (a == 0 && b.vec) {
+      // x face minus its interior rows: the z = 0 and z = nz-1 lines, and the
+      // y = 0 and y = ny-1 lines between them
+      const int x = st[0], ny = n3[1], nz = n3[2];
+      add_rect(b, f, x, 1, 0, ny, 0, 1);
+      add_rect(b, f, x, 1, 0, ny, nz - 1, 1);
+      add_rect(b, f, x, 1, 0, 1, 1, nz - 2);
+      add_rect(b, f, x, 1, ny - 1, 1, 1, nz - 2);
+    } else {
+      add_rect(b, f, st[0], ln[0], st[1], ln[1], st[2], ln[2]);
+    }
   }
 }
 
@@ -726,6 +780,12 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     b.off = off;
     off += nn * Q;
     if (pm) ctx->per = true;
+    {
+      const int V = 16 / (int)store_bytes(cfg->storage);
+      const double plane = (double)Q * n3[0] * n3[1] * (double)store_bytes(cfg->storage);
+      b.vec = cfg->storage != LB_STORE_F64 && pm == 0u && n3[0] % V == 0 && n3[0] / V <= 64 &&
+              3.0 * plane < 4294967296.0 && !getenv("LBM_NO_VEC");
+    }
     face_tables(b);
     default_tile(b);
     ctx->bx.push_back(b);
@@ -765,15 +825,17 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   DevState st{};
   st.step = 0;
   st.err_key = ERR_NONE;
-  st.done = 0;
   if (h2d(ctx, ctx->d_st, &st, sizeof(st)) != hipSuccess) {
     lb_free(ctx);
     return LB_ERR_HIP;
   }
-  switch (ctx->S) {
-    case 0: ctx->lb_fn = pick_lb<0>(ctx->coll, ctx->per); break;
-    case 1: ctx->lb_fn = pick_lb<1>(ctx->coll, ctx->per); break;
-    default: ctx->lb_fn = pick_lb<2>(ctx->coll, ctx->per); break;
+  {
+    const int kc = ctx->coll == LB_BGK ? 0 : (ctx->cfg.ghost_rate == 1.0 ? 2 : 1);
+    switch (ctx->S) {
+      case 0: ctx->lb_fn = pick_lb<0>(kc, ctx->per); break;
+      case 1: ctx->lb_fn = pick_lb<1>(kc, ctx->per); break;
+      default: ctx->lb_fn = pick_lb<2>(kc, ctx->per); break;
+    }
   }
   if (ctx->S == 0)
     ctx->chain_fn = ctx->per ? launch_chain<0, true> : launch_chain<0, false>;
@@ -1263,6 +1325,40 @@ lb_status lb_autotune(lb_ctx* ctx, int32_t trials) {
     }
   }
   return LB_OK;
+}
+
+lb_status lb_copy_probe(size_t bytes, int32_t iters, double* gbs) {
+  if (!gbs || iters < 1 || bytes < 16) return LB_ERR_ARG;
+  const size_t n = bytes / 16;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, n * 16) != hipSuccess) return LB_ERR_OOM;
+  if (hipMalloc(&b, n * 16) != hipSuccess) {
+    (void)hipFree(a);
+    return LB_ERR_OOM;
+  }
+  hipEvent_t e0, e1;
+  lb_status st = LB_OK;
+  if (hipMemset(a, 0, n * 16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    st = LB_ERR_HIP;
+  } else {
+    const int grid = 256 * 32;
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, nullptr, (const uint4*)a, (uint4*)b, n);
+    (void)hipEventRecord(e0, nullptr);
+    for (int k = 0; k < iters; k++)
+      hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, nullptr, (const uint4*)a, (uint4*)b, n);
+    (void)hipEventRecord(e1, nullptr);
+    float ms = 0;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      st = LB_ERR_HIP;
+    else
+      *gbs = 2.0 * (double)n * 16.0 * iters / (ms * 1e-3) / 1e9;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  (void)hipFree(a);
+  (void)hipFree(b);
+  return st;
 }
 
 const char* lb_describe(const lb_ctx* ctx) { return ctx ? ctx->desc.c_str() : ""; }

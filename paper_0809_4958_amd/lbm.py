@@ -59,7 +59,8 @@ class LbChain(ct.Structure):
 
 EXPORTS = ["lb_init", "lb_set_initial", "lb_set_boundary", "lb_couple_chain", "lb_step",
            "lb_read_fields", "lb_read_sites", "lb_write_state", "lb_sync", "lb_autotune",
-           "lb_set_timing", "lb_get_timing", "lb_describe", "lb_last_error", "lb_free"]
+           "lb_set_timing", "lb_get_timing", "lb_describe", "lb_last_error", "lb_free",
+           "lb_copy_probe"]
 
 _lib = None
 
@@ -92,10 +93,21 @@ def load(path: str = LIB):
     lib.lb_last_error.restype = ct.c_char_p
     lib.lb_free.argtypes = [vp]
     lib.lb_free.restype = None
+    lib.lb_copy_probe.argtypes = [ct.c_size_t, ct.c_int32, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ct.c_int
     _lib = lib
     return lib
+
+
+def copy_probe(nbytes=1 << 30, iters=20) -> float:
+    """Measured HBM copy bandwidth (read + write) in GB/s."""
+    lib = load()
+    out = ct.c_double()
+    st = lib.lb_copy_probe(int(nbytes), int(iters), ct.byref(out))
+    if st != OK:
+        raise LBError(st, "lb_copy_probe failed")
+    return out.value
 
 
 class LBError(RuntimeError):
