@@ -79,7 +79,7 @@ __host__ __device__ constexpr bool basis_orthogonal() {
 }
 static_assert(basis_orthogonal(), "MRT basis is not weighted-orthogonal");
 
-enum : int { ITEM_TILE = 0, ITEM_BOUNDARY = 1, ITEM_ROWS = 2 };
+enum : int { ITEM_TILE = 0, ITEM_BOUNDARY = 1, ITEM_ROWS = 2, ITEM_FACE_ROWS = 3 };
 constexpr int MAX_RECT = 12;
 
 struct BoxDesc {
@@ -101,7 +101,7 @@ struct BoxDesc {
   float enc[3];         // FP16 encode factor per weight class: 2^s / w
   double interior;      // number of interior nodes
   int fast;             // non-periodic and 19*nn*sizeof(T) < 2^32 (32-bit offsets)
-  int vec;              // rows handled as 16-byte vectors (ITEM_ROWS) incl. the x-face nodes
+  int vec;              // interior rows handled as lane vectors (ITEM_ROWS) incl. the x-face nodes
 };
 
 struct Item {

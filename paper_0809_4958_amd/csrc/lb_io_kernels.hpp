@@ -1,0 +1,194 @@
+// lb_io_kernels.hpp -- gfx950 kernels around the fused step: the per-step
+// finalisation, state upload and readout, and the stream-copy probe.
+//
+//   k_finalize  one workgroup after k_lb: reduces the item partials in a fixed
+//               order per box, checks finiteness, advances the step counter.
+//   k_set_pre / k_read / k_read_sites / k_read_beads   state upload and readout.
+//   k_copy      16-byte stream copy (HBM ceiling probe).
+#pragma once
+#include "lb_kernels.hpp"
+
+namespace lbdev {
+
+// One workgroup after the fused step: per-box fixed-order sums of the item
+// partials (on check steps), finiteness check, device step advance.  Runs as
+// its own launch so that the fused kernel needs no device-wide fences.
+__global__ __launch_bounds__(WG) void k_finalize(LbArgs A) {
+  const int tid = threadIdx.x;
+  if (A.st->err_key != ERR_NONE) return;
+  const long long step = A.st->step;
+  const bool check = A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0;
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0x7fffffff;
+  __syncthreads();
+  if (check) {
+    for (int bx = tid; bx < A.n_boxes; bx += WG) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int q = A.box_items_off[bx]; q < A.box_items_off[bx + 1]; q++) {
+        const int item = A.box_items[q];
+#pragma unroll
+        for (int m = 0; m < 4; m++) s[m] += A.partials[4 * item + m];
+      }
+      const double M = A.rho0 * A.boxes[bx].interior + s[0];
+      double* mm = A.mass_mom + 5 * bx;
+      mm[0] = (double)(step + 1);
+      mm[1] = M;
+      mm[2] = s[1];
+      mm[3] = s[2];
+      mm[4] = s[3];
+      if (!(isfinite(M) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]))) atomicMin(&s_bad, bx);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (s_bad != 0x7fffffff)
+      A.st->err_key = (s_bad << 4) | EC_UNSTABLE;
+    else if (A.advance)
+      A.st->step = step + 1;
+  }
+}
+
+// ------------------------------------------------------- state upload
+// pre-collision state of one box from FP64 populations [19][nn] (mode 0), from
+// the equilibrium of a velocity field u[nn][3] (mode 1), rest (mode 2), or FP64
+// deviations f_i - w_i rho0 [19][nn] (mode 3)
+template <int S>
+__global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T* __restrict__ dst,
+                                                const double* __restrict__ in, int mode, double rho0) {
+  using St = Store<S>;
+  using R = typename St::R;
+  const int64_t nn = b.nn;
+  for (int64_t node = (int64_t)blockIdx.x * WG + threadIdx.x; node < nn;
+       node += (int64_t)gridDim.x * WG) {
+    const int x = (int)(node % b.nx);
+    const int y = (int)((node / b.nx) % b.ny);
+    const int z = (int)(node / ((int64_t)b.nx * b.ny));
+    R d[Q];
+    if (!is_interior(b, x, y, z) || mode == 2) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = 0;
+    } else if (mode == 0) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = (R)(in[i * nn + node] - WD[WCLS[i]] * rho0);
+    } else if (mode == 3) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = (R)in[i * nn + node];
+    } else {
+      // deviation of f_eq(rho0, u): computed in FP64 then rounded once
+      double ud[3] = {in[3 * node], in[3 * node + 1], in[3 * node + 2]};
+      double eq[Q];
+      eq_dev<double>(0.0, rho0, ud[0], ud[1], ud[2], eq);
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] = (R)eq[i];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+  }
+}
+
+// ------------------------------------------------------------ readout
+// what: 0 populations [19][nn], 1 rho [nn], 2 u [nn][3], 3 deviations [19][nn]
+template <int S, bool PER>
+__global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>::T* __restrict__ src,
+                                             double* __restrict__ out, int what, int pre, double rho0) {
+  using R = typename Store<S>::R;
+  const int64_t nn = b.nn;
+  for (int64_t node = (int64_t)blockIdx.x * WG + threadIdx.x; node < nn;
+       node += (int64_t)gridDim.x * WG) {
+    const int x = (int)(node % b.nx);
+    const int y = (int)((node / b.nx) % b.ny);
+    const int z = (int)(node / ((int64_t)b.nx * b.ny));
+    double f[Q];
+    if (is_interior(b, x, y, z)) {
+      R d[Q];
+      load_pre<S, PER>(src, b, x, y, z, pre != 0, d);
+#pragma unroll
+      for (int i = 0; i < Q; i++) f[i] = WD[WCLS[i]] * rho0 + (double)d[i];
+      if (what == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = f[i];
+      } else if (what == 3) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = (double)d[i];
+      } else {
+        double drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          drho += (double)d[i];
+          jx += CX[i] * (double)d[i];
+          jy += CY[i] * (double)d[i];
+          jz += CZ[i] * (double)d[i];
+        }
+        const double rho = rho0 + drho;
+        if (what == 1) {
+          out[node] = rho;
+        } else {
+          out[3 * node] = jx / rho;
+          out[3 * node + 1] = jy / rho;
+          out[3 * node + 2] = jz / rho;
+        }
+      }
+    } else {
+      if (what == 0) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = WD[WCLS[i]] * rho0;
+      } else if (what == 3) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i * nn + node] = 0.0;
+      } else if (what == 1) {
+        out[node] = rho0;
+      } else {
+        out[3 * node] = out[3 * node + 1] = out[3 * node + 2] = 0.0;
+      }
+    }
+  }
+}
+
+template <int S, bool PER>
+__global__ __launch_bounds__(WG) void k_read_sites(BoxDesc b, const typename Store<S>::T* __restrict__ src,
+                                                   const int* __restrict__ xyz, int n,
+                                                   double* __restrict__ out, int pre, double rho0) {
+  using R = typename Store<S>::R;
+  const int k = blockIdx.x * WG + threadIdx.x;
+  if (k >= n) return;
+  R d[Q];
+  load_pre<S, PER>(src, b, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2], pre != 0, d);
+#pragma unroll
+  for (int i = 0; i < Q; i++) out[Q * k + i] = WD[WCLS[i]] * rho0 + (double)d[i];
+}
+
+// bead positions/velocities of one parity buffer back to absolute FP64 coordinates
+template <typename R>
+__global__ void k_read_beads(const ChainDesc* __restrict__ chains, int c0, int c1,
+                             const R* __restrict__ buf, double* __restrict__ out, int add_anchor) {
+  int o = 0;
+  for (int c = c0; c < c1; c++) {
+    const ChainDesc ch = chains[c];
+    for (int j = threadIdx.x; j < ch.nb; j += blockDim.x)
+      for (int a = 0; a < 3; a++) {
+        double v = (double)buf[3 * (ch.first + j) + a];
+        if (add_anchor) v = (double)ch.ai[a] + (ch.af[a] + v);
+        out[3 * (o + j) + a] = v;
+      }
+    o += ch.nb;
+  }
+}
+
+// stream copy with 16-byte accesses, four independent loads in flight per
+// thread (HBM ceiling probe); n is a multiple of 4 * WG * gridDim.x or the
+// tail is copied one vector at a time
+__global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                             size_t n) {
+  const size_t stride = (size_t)gridDim.x * WG;
+  size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace lbdev

@@ -12,9 +12,7 @@
 //             equilibrium populations that point into the interior.  On check
 //             steps every item writes FP64 partial sums of mass and momentum
 //             at t_{n+1}.
-//   k_finalize one workgroup after k_lb: reduces the partials in a fixed
-//             order per box, checks finiteness, advances the step counter.
-//   k_set_pre / k_read / k_read_sites   state upload and readout.
+//             The per-box sums are formed by k_finalize (lb_io_kernels.hpp).
 #pragma once
 #include "lb_device.hpp"
 
@@ -23,6 +21,19 @@ namespace lbdev {
 constexpr int WG = 256;
 constexpr int MAX_SLOTS = 4;   // tile plane positions per thread (ex*ey <= 1024)
 constexpr int MAX_BOX_CHAINS = 64;
+// 32-bit words per lane in row items (2: 8-byte vectors, 4 FP16 or 2 FP32
+// nodes per lane) and the minimum resident waves per SIMD of the FP32/FP16
+// step kernel; both are build-time choices
+#ifndef LB_ROW_WORDS_F16
+#define LB_ROW_WORDS_F16 2
+#endif
+#ifndef LB_ROW_WORDS_F32
+#define LB_ROW_WORDS_F32 2
+#endif
+#ifndef LB_MIN_WAVES
+#define LB_MIN_WAVES 2
+#endif
+__host__ __device__ constexpr int row_words(int s) { return s == 2 ? LB_ROW_WORDS_F16 : LB_ROW_WORDS_F32; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -483,36 +494,94 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
 }
 
 // ---------------------------------------------------------------------------
-// Row items: each lane owns V consecutive nodes of one x-row (V * sizeof(T) =
-// 16 bytes: 8 FP16 or 4 FP32 values) and moves every population with one
-// aligned 16-byte load and one 16-byte store.  The pull's +-1 shift in x is an
-// element selection inside the lane's vector plus one value from the
-// neighbouring lane (rows never straddle a wavefront); shifts in y and z move
-// the whole row.  The lane holding x = 0 or x = nx-1 stores the boundary
+// Row items: each lane owns V consecutive nodes of one x-row, held as W 32-bit
+// words (V = 2W FP16 or W FP32 values), and moves every population with one
+// aligned W-word load and one W-word store.  The interior rows (y, z) of a box
+// (1 <= y <= ny-2, 1 <= z <= nz-2), each cut into L = nx / V lane groups, are
+// numbered consecutively, and a workgroup walks BS consecutive groups per
+// iteration, so rows may straddle wavefronts and every lane is busy for any
+// nx divisible by V.  The pull's +-1 shift in x is an element selection
+// inside the lane's vector plus one element of the neighbouring group: a lane
+// shuffle inside the wavefront, or a direct load for the first and last lane
+// of a wavefront.  The groups holding x = 0 or x = nx-1 store the boundary
 // equilibrium of that node (face -x or +x), so every store is a full vector.
-template <int S>
-struct VecT {
+template <int S, int W>
+struct RowVec {
   using T = typename Store<S>::T;
-  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int EPW = 4 / (int)sizeof(T);  // elements per 32-bit word
+  static constexpr int V = W * EPW;               // nodes per lane
 };
 
-template <int S>
-__device__ __forceinline__ typename Store<S>::T vget(const uint4& v, int e) {
-  using T = typename Store<S>::T;
-  const unsigned w[4] = {v.x, v.y, v.z, v.w};
-  if constexpr (sizeof(T) == 2) {
-    const unsigned word = w[e >> 1];
-    const unsigned short h = (unsigned short)((e & 1) ? (word >> 16) : (word & 0xffffu));
-    return __builtin_bit_cast(T, h);
+// Buffer resource over [base, base + bytes) (raw, stride 0; gfx9 word 3):
+// a lane addresses it with one 32-bit offset, a population with a scalar
+// offset, and accesses past the end read zero / are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, long long bytes) {
+  const int n = bytes >= 0xffffffffLL ? (int)0xffffffffu : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
+}
+
+template <int W>
+__device__ __forceinline__ void vload(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff,
+                                      unsigned (&w)[W]) {
+  if constexpr (W == 1) {
+    w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0);
+  } else if constexpr (W == 2) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0);
+    w[0] = v[0];
+    w[1] = v[1];
   } else {
-    return __builtin_bit_cast(T, w[e]);
+    static_assert(W == 4, "row vectors are 1, 2 or 4 words");
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, 0);
+    w[0] = v[0];
+    w[1] = v[1];
+    w[2] = v[2];
+    w[3] = v[3];
   }
 }
 
-template <int S>
-__device__ __forceinline__ void vset(uint4& v, int e, typename Store<S>::T val) {
+template <int W>
+__device__ __forceinline__ void vstore(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff,
+                                       const unsigned (&w)[W]) {
+  if constexpr (W == 1) {
+    __builtin_amdgcn_raw_buffer_store_b32(w[0], r, (int)voff, soff, 0);
+  } else if constexpr (W == 2) {
+    __attribute__((ext_vector_type(2))) unsigned v;
+    v[0] = w[0];
+    v[1] = w[1];
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, soff, 0);
+  } else {
+    __attribute__((ext_vector_type(4))) unsigned v;
+    v[0] = w[0];
+    v[1] = w[1];
+    v[2] = w[2];
+    v[3] = w[3];
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, soff, 0);
+  }
+}
+
+// element e of a lane's words, e in [-1, V]: -1 is the left neighbour's last
+// element (held in the high bits of `left`), V the right neighbour's first
+// (low bits of `right`)
+template <int S, int W>
+__device__ __forceinline__ typename Store<S>::T velem(const unsigned (&w)[W], unsigned left,
+                                                      unsigned right, int e) {
   using T = typename Store<S>::T;
-  unsigned* w = &v.x;
+  constexpr int V = RowVec<S, W>::V;
+  if constexpr (sizeof(T) == 2) {
+    unsigned short h;
+    if (e == -1) h = (unsigned short)(left >> 16);
+    else if (e == V) h = (unsigned short)(right & 0xffffu);
+    else h = (unsigned short)((e & 1) ? (w[e >> 1] >> 16) : (w[e >> 1] & 0xffffu));
+    return __builtin_bit_cast(T, h);
+  } else {
+    const unsigned u = e == -1 ? left : (e == V ? right : w[e]);
+    return __builtin_bit_cast(T, u);
+  }
+}
+
+template <int S, int W>
+__device__ __forceinline__ void vput(unsigned (&w)[W], int e, typename Store<S>::T val) {
+  using T = typename Store<S>::T;
   if constexpr (sizeof(T) == 2) {
     const unsigned h = (unsigned)__builtin_bit_cast(unsigned short, val);
     unsigned& word = w[e >> 1];
@@ -522,25 +591,7 @@ __device__ __forceinline__ void vset(uint4& v, int e, typename Store<S>::T val) 
   }
 }
 
-// element e of population i's source vector, e in [-1, V]: -1 and V come from
-// the neighbouring lanes' vectors (left: its last element, right: its first)
-template <int S>
-__device__ __forceinline__ typename Store<S>::T vsrc(const uint4& v, unsigned left, unsigned right,
-                                                     int e) {
-  using T = typename Store<S>::T;
-  constexpr int V = VecT<S>::V;
-  if (e == -1) {
-    if constexpr (sizeof(T) == 2) return __builtin_bit_cast(T, (unsigned short)(left >> 16));
-    else return __builtin_bit_cast(T, left);
-  }
-  if (e == V) {
-    if constexpr (sizeof(T) == 2) return __builtin_bit_cast(T, (unsigned short)(right & 0xffffu));
-    else return __builtin_bit_cast(T, right);
-  }
-  return vget<S>(v, e);
-}
-
-template <int S, int COLL, bool CHECK, bool GATHER, bool PRE, int BS>
+template <int S, int W, int COLL, bool CHECK, bool GATHER, bool PRE, int BS>
 __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, const Item& it,
                                           const typename Store<S>::T* src,
                                           typename Store<S>::T* dst, long long step,
@@ -550,54 +601,116 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
-  constexpr int V = VecT<S>::V;
-  constexpr unsigned SB = sizeof(T);
-  const unsigned nx = (unsigned)b.nx, ny = (unsigned)b.ny;
-  const unsigned rs = (unsigned)Q * nx;   // row-block stride (elements)
-  const size_t ps = (size_t)rs * ny;      // plane stride
-  // offsets inside a plane: population i of the row y - c_y (the plane z - c_z
-  // is chosen by base pointer)
-  unsigned so[Q], doff[Q];
-#pragma unroll
-  for (int i = 0; i < Q; i++) {
-    const int dy = PRE ? 0 : CY[i];
-    so[i] = ((unsigned)i * nx - (unsigned)(dy * (int)rs)) * SB;
-    doff[i] = (unsigned)i * nx * SB;
-  }
+  constexpr int V = RowVec<S, W>::V;
+  constexpr int SB = (int)sizeof(T);
+  const int nx = b.nx, ny = b.ny, nyi = b.ny - 2;
+  const int L = nx / V;                            // lane groups per row
+  const int nxb = nx * SB;                         // bytes per population row
+  const int rsb = Q * nxb;                         // bytes per row block (19 rows)
+  const long long psb = (long long)rsb * ny;       // bytes per plane
+  const long long box_bytes = psb * b.nz;
+  const int g_last = L * nyi * (b.nz - 2) - 1;     // last group of the box
+  const int q_end = it.x0 + it.ex;
   const float dc0 = b.dec[0], dc1 = b.dec[1], dc2 = b.dec[2];
   const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
-  const int L = (int)nx / V;              // lanes per row
-  const int rpw = 64 / L;                 // rows per wavefront
   const int lane = (int)(threadIdx.x & 63);
-  const int wave = (int)(threadIdx.x >> 6);
-  const int r = lane / L, c = lane - (lane / L) * L;
-  const int y = it.y0 + wave * rpw + r;
-  const bool act = r < rpw && y < it.y0 + it.ey;
-  const int x0 = c * V;
   const unsigned lane_l = (unsigned)(lane - 1) & 63u, lane_r = (unsigned)(lane + 1) & 63u;
-  const unsigned voff = ((unsigned)(act ? y : it.y0) * rs + (unsigned)x0) * SB;
+  // population i of the node at lane offset v sits at v + soff(i) from the
+  // iteration's base plane (one plane below its first row): offsets >= 0
+  const int ps = (int)psb;
 #pragma unroll 1
-  for (int z = it.z0; z < it.z0 + it.ez; z++) {
-    const char* __restrict__ pz = (const char*)(src + (size_t)z * ps);
-    const char* __restrict__ pm = (const char*)(src + (size_t)(z - 1) * ps);
-    const char* __restrict__ pp = (const char*)(src + (size_t)(z + 1) * ps);
-    char* __restrict__ dz = (char*)(dst + (size_t)z * ps);
-    uint4 raw[Q];
+  for (int qb = it.x0; qb < q_end; qb += BS) {
+    const int zf = 1 + (qb / L) / nyi;             // first plane of this iteration
+    const long long base = (long long)(zf - 1) * psb;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc((const char*)src + base, box_bytes - base);
+    const __amdgpu_buffer_rsrc_t rdst = make_rsrc((const char*)dst + base, box_bytes - base);
+    const int q = qb + (int)threadIdx.x;
+    const bool act = q < q_end;
+    // groups past the item still load real data (their own group, or the last
+    // group of the box): the last active lane's right neighbour may be one
+    const int qq = q < g_last ? q : g_last;
+    const int row = qq / L;
+    const int c = qq - row * L;
+    const int zi = row / nyi;
+    const int y = 1 + row - zi * nyi, z = 1 + zi;
+    const int x0 = c * V;
+    const unsigned voff = (unsigned)((z - zf) * ps + (y - 1) * rsb + x0 * SB);
+    unsigned raw[Q][W];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      const char* base = (PRE || CZ[i] == 0) ? pz : (CZ[i] == 1 ? pm : pp);
-      raw[i] = act ? *(const uint4*)(base + (voff + so[i])) : make_uint4(0u, 0u, 0u, 0u);
+      const int so = i * nxb + (PRE ? ps + rsb : (1 - CZ[i]) * ps + (1 - CY[i]) * rsb);
+      vload<W>(rsrc, voff, so, raw[i]);
     }
-    // neighbour-lane elements for the populations shifted in x
+    // neighbour elements of the populations shifted in x
     unsigned left[Q], right[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
       left[i] = 0u;
       right[i] = 0u;
-      if (!PRE && CX[i] == 1) left[i] = __shfl(raw[i].w, (int)lane_l, 64);
-      if (!PRE && CX[i] == -1) right[i] = __shfl(raw[i].x, (int)lane_r, 64);
+      if (!PRE && CX[i] == 1) left[i] = __shfl(raw[i][W - 1], (int)lane_l, 64);
+      if (!PRE && CX[i] == -1) right[i] = __shfl(raw[i][0], (int)lane_r, 64);
     }
-    uint4 out[Q];
+    if (!PRE) {
+      // first / last lane of the wavefront: the neighbour group sits in
+      // another wavefront; load its element directly (in bounds: c > 0 means
+      // x0 - 1 >= 0, c < L - 1 means x0 + V <= nx - 1)
+      if (lane == 0 && c != 0) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          if (CX[i] != 1) continue;
+          const int so = i * nxb + (1 - CZ[i]) * ps + (1 - CY[i]) * rsb - SB;
+          if constexpr (SB == 2)
+            left[i] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rsrc, (int)voff, so, 0) << 16;
+          else
+            left[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, so, 0);
+        }
+      }
+      if (lane == 63 && c != L - 1) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          if (CX[i] != -1) continue;
+          const int so = i * nxb + (1 - CZ[i]) * ps + (1 - CY[i]) * rsb + V * SB;
+          if constexpr (SB == 2)
+            right[i] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rsrc, (int)voff, so, 0);
+          else
+            right[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, so, 0);
+        }
+      }
+    }
+    // spread force of the lane's V nodes: chains whose stencil box holds the
+    // row, beads in fixed order
+    R g[GATHER ? V : 1][3];
+#pragma unroll
+    for (int k = 0; k < (GATHER ? V : 1); k++) g[k][0] = g[k][1] = g[k][2] = (R)0;
+    if (GATHER && act) {
+      const R* rd = (const R*)A.rec_d;
+      const R* rp = (const R*)A.rec_dp;
+      for (int ci = 0; ci < b.chain_count && ci < MAX_BOX_CHAINS; ci++) {
+        if (!((cmask >> ci) & 1ull)) continue;
+        const int gc = b.chain_first + ci;
+        const int* bb = A.bbox + 6 * gc;
+        if (z < bb[2] || z > bb[5] || y < bb[1] || y > bb[4] || x0 + V - 1 < bb[0] || x0 > bb[3])
+          continue;
+        const ChainDesc& ch = A.chains[gc];
+        for (int jb = ch.first; jb < ch.first + ch.nb; jb++) {
+          const int4 bs = A.rec_base[jb];
+          const int oy = y - bs.y, oz = z - bs.z;
+          if ((unsigned)oy > 1u || (unsigned)oz > 1u) continue;
+          const R dx = rd[3 * jb], dy = rd[3 * jb + 1], dz = rd[3 * jb + 2];
+          const R px = rp[3 * jb], py = rp[3 * jb + 1], pz = rp[3 * jb + 2];
+#pragma unroll
+          for (int k = 0; k < V; k++) {
+            const int ox = x0 + k - bs.x;
+            if ((unsigned)ox > 1u) continue;
+            const R w = (ox ? dx : (R)1 - dx) * (oy ? dy : (R)1 - dy) * (oz ? dz : (R)1 - dz);
+            g[k][0] -= w * px;
+            g[k][1] -= w * py;
+            g[k][2] -= w * pz;
+          }
+        }
+      }
+    }
+    unsigned out[Q][W];
 #pragma unroll
     for (int k = 0; k < V; k++) {
       R d[Q];
@@ -605,17 +718,16 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
       for (int i = 0; i < Q; i++) {
         const int e = PRE ? k : k - CX[i];
         const float kd = WCLS[i] == 0 ? dc0 : (WCLS[i] == 1 ? dc1 : dc2);
-        d[i] = St::dec(vsrc<S>(raw[i], left[i], right[i], e), kd);
+        d[i] = St::dec(velem<S, W>(raw[i], left[i], right[i], e), kd);
       }
       const int x = x0 + k;
-      R gx = 0, gy = 0, gz = 0;
-      if (GATHER) gather_force<R, false>(A, b, cmask, x, y, z, gx, gy, gz);
-      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
-      if (CHECK && act && x >= 1 && x <= (int)nx - 2) check_acc<S, false>(b, x, y, z, d, acc);
+      collide_any<R, COLL>(d, GATHER ? g[k][0] : (R)0, GATHER ? g[k][1] : (R)0,
+                           GATHER ? g[k][2] : (R)0, rho0, omega, omb, omg);
+      if (CHECK && act && x >= 1 && x <= nx - 2) check_acc<S, false>(b, x, y, z, d, acc);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-        vset<S>(out[i], k, St::enc(d[i], ke));
+        vput<S, W>(out[i], k, St::enc(d[i], ke));
       }
     }
     // x-face nodes of this row: boundary equilibrium at t_n (faces -x, +x)
@@ -623,22 +735,87 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
 #pragma unroll
       for (int side = 0; side < 2; side++) {
         if ((side == 0 && c != 0) || (side == 1 && c != L - 1)) continue;
-        const int q[3] = {side == 0 ? 0 : (int)nx - 1, y, z};
+        const int qn[3] = {side == 0 ? 0 : nx - 1, y, z};
         R u[3];
-        boundary_velocity<R>(b, side, q, step, u);
+        boundary_velocity<R>(b, side, qn, step, u);
         R eq[Q];
         eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
-        if (CHECK) check_acc<S, false>(b, q[0], y, z, eq, acc);
+        if (CHECK) check_acc<S, false>(b, qn[0], y, z, eq, acc);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-          vset<S>(out[i], side == 0 ? 0 : V - 1, St::enc(eq[i], ke));
+          vput<S, W>(out[i], side == 0 ? 0 : V - 1, St::enc(eq[i], ke));
         }
       }
     }
     if (act) {
 #pragma unroll
-      for (int i = 0; i < Q; i++) *(uint4*)(dz + (voff + doff[i])) = out[i];
+      for (int i = 0; i < Q; i++) vstore<W>(rdst, voff, i * nxb + ps + rsb, out[i]);
+    }
+  }
+}
+
+// Face rows of a row box: the rows y = 0, y = ny-1 (1 <= z <= nz-2) and all
+// rows of the planes z = 0, z = nz-1, cut into the same lane groups, numbered
+// plane z = 0 (rows y = 0..ny-1), plane z = nz-1, then for each interior z its
+// rows y = 0 and y = ny-1.  Every node stores the full boundary equilibrium at
+// t_n with the face of lowest index it lies on (-x, +x, -y, +y, -z, +z), one
+// W-word vector per population; only the populations pointing into the
+// interior are ever read.
+template <int S, int W, bool CHECK, int BS>
+__device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
+                                          typename Store<S>::T* dst, long long step,
+                                          typename Store<S>::R rho0, double acc[4]) {
+  using St = Store<S>;
+  using R = typename St::R;
+  constexpr int V = RowVec<S, W>::V;
+  constexpr int SB = (int)sizeof(typename St::T);
+  const int nx = b.nx, ny = b.ny, nz = b.nz;
+  const int L = nx / V;
+  const long long nxb = (long long)nx * SB, rsb = Q * nxb, psb = rsb * ny;
+  const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
+  const int q_end = it.x0 + it.ex;
+#pragma unroll 1
+  for (int q = it.x0 + (int)threadIdx.x; q < q_end; q += BS) {
+    const int fr = q / L;
+    const int c = q - fr * L;
+    int y, z;
+    if (fr < ny) {
+      y = fr;
+      z = 0;
+    } else if (fr < 2 * ny) {
+      y = fr - ny;
+      z = nz - 1;
+    } else {
+      const int k = fr - 2 * ny;
+      z = 1 + (k >> 1);
+      y = (k & 1) ? ny - 1 : 0;
+    }
+    const int x0 = c * V;
+    unsigned out[Q][W];
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+      const int x = x0 + k;
+      const int f = x == 0 ? 0 : (x == nx - 1 ? 1 : (y == 0 ? 2 : (y == ny - 1 ? 3 : (z == 0 ? 4 : 5))));
+      const int qn[3] = {x, y, z};
+      R u[3];
+      boundary_velocity<R>(b, f, qn, step, u);
+      R eq[Q];
+      eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
+      if (CHECK) check_acc<S, false>(b, x, y, z, eq, acc);
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
+        vput<S, W>(out[i], k, St::enc(eq[i], ke));
+      }
+    }
+    char* row = (char*)dst + (long long)z * psb + (long long)y * rsb + (long long)x0 * SB;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      char* p = row + i * nxb;
+      if constexpr (W == 1) *(unsigned*)p = out[i][0];
+      else if constexpr (W == 2) *(uint2*)p = make_uint2(out[i][0], out[i][1]);
+      else *(uint4*)p = make_uint4(out[i][0], out[i][1], out[i][2], out[i][3]);
     }
   }
 }
@@ -675,7 +852,7 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
 // ----------------------------------------------------------- fused step
 
 template <int S, int COLL, bool PER, int BS = WG>
-__global__ __launch_bounds__(BS, (S == 0 ? 4 : 2)) void k_lb(LbArgs A) {
+__global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -713,7 +890,7 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : 2)) void k_lb(LbArgs A) {
       }
       if constexpr (S != 0 && !PER) {
 #define LB_ROWS(CH, GA, PR) \
-  tile_rows<S, COLL, CH, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg, acc)
+  tile_rows<S, row_words(S), COLL, CH, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg, acc)
         if (pre) {
           if (cmask) { if (check) LB_ROWS(true, true, true); else LB_ROWS(false, true, true); }
           else { if (check) LB_ROWS(true, false, true); else LB_ROWS(false, false, true); }
@@ -722,6 +899,11 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : 2)) void k_lb(LbArgs A) {
           else { if (check) LB_ROWS(true, false, false); else LB_ROWS(false, false, false); }
         }
 #undef LB_ROWS
+      }
+    } else if (it.kind == ITEM_FACE_ROWS) {
+      if constexpr (S != 0 && !PER) {
+        if (check) face_rows<S, row_words(S), true, BS>(b, it, dst, step, rho0, acc);
+        else face_rows<S, row_words(S), false, BS>(b, it, dst, step, rho0, acc);
       }
     } else if (it.kind == ITEM_TILE) {
       // chains whose stencil box overlaps this tile
@@ -800,187 +982,6 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : 2)) void k_lb(LbArgs A) {
     }
   }
 
-}
-
-// One workgroup after the fused step: per-box fixed-order sums of the item
-// partials (on check steps), finiteness check, device step advance.  Runs as
-// its own launch so that the fused kernel needs no device-wide fences.
-__global__ __launch_bounds__(WG) void k_finalize(LbArgs A) {
-  const int tid = threadIdx.x;
-  if (A.st->err_key != ERR_NONE) return;
-  const long long step = A.st->step;
-  const bool check = A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0;
-  __shared__ int s_bad;
-  if (tid == 0) s_bad = 0x7fffffff;
-  __syncthreads();
-  if (check) {
-    for (int bx = tid; bx < A.n_boxes; bx += WG) {
-      double s[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int q = A.box_items_off[bx]; q < A.box_items_off[bx + 1]; q++) {
-        const int item = A.box_items[q];
-#pragma unroll
-        for (int m = 0; m < 4; m++) s[m] += A.partials[4 * item + m];
-      }
-      const double M = A.rho0 * A.boxes[bx].interior + s[0];
-      double* mm = A.mass_mom + 5 * bx;
-      mm[0] = (double)(step + 1);
-      mm[1] = M;
-      mm[2] = s[1];
-      mm[3] = s[2];
-      mm[4] = s[3];
-      if (!(isfinite(M) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]))) atomicMin(&s_bad, bx);
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    if (s_bad != 0x7fffffff)
-      A.st->err_key = (s_bad << 4) | EC_UNSTABLE;
-    else if (A.advance)
-      A.st->step = step + 1;
-  }
-}
-
-// ------------------------------------------------------- state upload
-// pre-collision state of one box from FP64 populations [19][nn] (mode 0), from
-// the equilibrium of a velocity field u[nn][3] (mode 1), rest (mode 2), or FP64
-// deviations f_i - w_i rho0 [19][nn] (mode 3)
-template <int S>
-__global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T* __restrict__ dst,
-                                                const double* __restrict__ in, int mode, double rho0) {
-  using St = Store<S>;
-  using R = typename St::R;
-  const int64_t nn = b.nn;
-  for (int64_t node = (int64_t)blockIdx.x * WG + threadIdx.x; node < nn;
-       node += (int64_t)gridDim.x * WG) {
-    const int x = (int)(node % b.nx);
-    const int y = (int)((node / b.nx) % b.ny);
-    const int z = (int)(node / ((int64_t)b.nx * b.ny));
-    R d[Q];
-    if (!is_interior(b, x, y, z) || mode == 2) {
-#pragma unroll
-      for (int i = 0; i < Q; i++) d[i] = 0;
-    } else if (mode == 0) {
-#pragma unroll
-      for (int i = 0; i < Q; i++) d[i] = (R)(in[i * nn + node] - WD[WCLS[i]] * rho0);
-    } else if (mode == 3) {
-#pragma unroll
-      for (int i = 0; i < Q; i++) d[i] = (R)in[i * nn + node];
-    } else {
-      // deviation of f_eq(rho0, u): computed in FP64 then rounded once
-      double ud[3] = {in[3 * node], in[3 * node + 1], in[3 * node + 2]};
-      double eq[Q];
-      eq_dev<double>(0.0, rho0, ud[0], ud[1], ud[2], eq);
-#pragma unroll
-      for (int i = 0; i < Q; i++) d[i] = (R)eq[i];
-    }
-#pragma unroll
-    for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
-  }
-}
-
-// ------------------------------------------------------------ readout
-// what: 0 populations [19][nn], 1 rho [nn], 2 u [nn][3], 3 deviations [19][nn]
-template <int S, bool PER>
-__global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>::T* __restrict__ src,
-                                             double* __restrict__ out, int what, int pre, double rho0) {
-  using R = typename Store<S>::R;
-  const int64_t nn = b.nn;
-  for (int64_t node = (int64_t)blockIdx.x * WG + threadIdx.x; node < nn;
-       node += (int64_t)gridDim.x * WG) {
-    const int x = (int)(node % b.nx);
-    const int y = (int)((node / b.nx) % b.ny);
-    const int z = (int)(node / ((int64_t)b.nx * b.ny));
-    double f[Q];
-    if (is_interior(b, x, y, z)) {
-      R d[Q];
-      load_pre<S, PER>(src, b, x, y, z, pre != 0, d);
-#pragma unroll
-      for (int i = 0; i < Q; i++) f[i] = WD[WCLS[i]] * rho0 + (double)d[i];
-      if (what == 0) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) out[i * nn + node] = f[i];
-      } else if (what == 3) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) out[i * nn + node] = (double)d[i];
-      } else {
-        double drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-          drho += (double)d[i];
-          jx += CX[i] * (double)d[i];
-          jy += CY[i] * (double)d[i];
-          jz += CZ[i] * (double)d[i];
-        }
-        const double rho = rho0 + drho;
-        if (what == 1) {
-          out[node] = rho;
-        } else {
-          out[3 * node] = jx / rho;
-          out[3 * node + 1] = jy / rho;
-          out[3 * node + 2] = jz / rho;
-        }
-      }
-    } else {
-      if (what == 0) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) out[i * nn + node] = WD[WCLS[i]] * rho0;
-      } else if (what == 3) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) out[i * nn + node] = 0.0;
-      } else if (what == 1) {
-        out[node] = rho0;
-      } else {
-        out[3 * node] = out[3 * node + 1] = out[3 * node + 2] = 0.0;
-      }
-    }
-  }
-}
-
-template <int S, bool PER>
-__global__ __launch_bounds__(WG) void k_read_sites(BoxDesc b, const typename Store<S>::T* __restrict__ src,
-                                                   const int* __restrict__ xyz, int n,
-                                                   double* __restrict__ out, int pre, double rho0) {
-  using R = typename Store<S>::R;
-  const int k = blockIdx.x * WG + threadIdx.x;
-  if (k >= n) return;
-  R d[Q];
-  load_pre<S, PER>(src, b, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2], pre != 0, d);
-#pragma unroll
-  for (int i = 0; i < Q; i++) out[Q * k + i] = WD[WCLS[i]] * rho0 + (double)d[i];
-}
-
-// bead positions/velocities of one parity buffer back to absolute FP64 coordinates
-template <typename R>
-__global__ void k_read_beads(const ChainDesc* __restrict__ chains, int c0, int c1,
-                             const R* __restrict__ buf, double* __restrict__ out, int add_anchor) {
-  int o = 0;
-  for (int c = c0; c < c1; c++) {
-    const ChainDesc ch = chains[c];
-    for (int j = threadIdx.x; j < ch.nb; j += blockDim.x)
-      for (int a = 0; a < 3; a++) {
-        double v = (double)buf[3 * (ch.first + j) + a];
-        if (add_anchor) v = (double)ch.ai[a] + (ch.af[a] + v);
-        out[3 * (o + j) + a] = v;
-      }
-    o += ch.nb;
-  }
-}
-
-// stream copy with 16-byte accesses, four independent loads in flight per
-// thread (HBM ceiling probe); n is a multiple of 4 * WG * gridDim.x or the
-// tail is copied one vector at a time
-__global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
-                                             size_t n) {
-  const size_t stride = (size_t)gridDim.x * WG;
-  size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
-  }
-  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 }  // namespace lbdev

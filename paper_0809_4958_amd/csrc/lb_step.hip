@@ -1,0 +1,47 @@
+// lb_step.hip -- instantiation of the step kernels for one storage type LB_S
+// and one collision operator LB_C (both given on the compiler command line).
+#include <hip/hip_runtime.h>
+
+#include "lb_kernels.hpp"
+#include "lb_launch.hpp"
+
+#if !defined(LB_S) || !defined(LB_C)
+#error "compile with -DLB_S=<0|1|2> -DLB_C=<0|1|2>"
+#endif
+
+namespace lbhost {
+
+using namespace lbdev;
+
+template <int S, int C, bool P>
+void launch_lb(dim3 g, hipStream_t s, const LbArgs& a) {
+  hipLaunchKernelGGL((k_lb<S, C, P, WG>), g, dim3(WG), 0, s, a);
+}
+
+template <int S, int C>
+LbLaunch pick_lb(bool periodic) {
+  return periodic ? launch_lb<S, C, true> : launch_lb<S, C, false>;
+}
+
+template LbLaunch pick_lb<LB_S, LB_C>(bool);
+
+#if LB_C == 0
+template <int S, bool P>
+void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc* chains,
+                  const void* a0, const void* a1, void* pos, void* vel, int total, int4* rb,
+                  void* rd, void* rp, int* bbox, DevState* st, double rho0, int pre) {
+  using T = typename Store<S>::T;
+  using R = typename Store<S>::R;
+  hipLaunchKernelGGL((k_chain<S, P>), dim3(nch), dim3(WG), 0, s, boxes, chains, (const T*)a0,
+                     (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox, st, rho0, pre);
+}
+
+template <int S>
+ChainLaunch pick_chain(bool periodic) {
+  return periodic ? launch_chain<S, true> : launch_chain<S, false>;
+}
+
+template ChainLaunch pick_chain<LB_S>(bool);
+#endif
+
+}  // namespace lbhost

@@ -23,7 +23,8 @@
 #include <vector>
 
 #include "lbm.h"
-#include "lb_kernels.hpp"
+#include "lb_io_kernels.hpp"
+#include "lb_launch.hpp"
 
 using namespace lbdev;
 
@@ -59,25 +60,8 @@ struct ChainHost {
   bool pos_is_rel = false;  // pos holds positions minus the anchor (exact restore)
 };
 
-using LbLaunch = void (*)(dim3, hipStream_t, const LbArgs&);
-using ChainLaunch = void (*)(int, hipStream_t, const BoxDesc*, const ChainDesc*, const void*,
-                             const void*, void*, void*, int, int4*, void*, void*, int*, DevState*,
-                             double, int);
-
-template <int S, int C, bool P>
-void launch_lb(dim3 g, hipStream_t s, const LbArgs& a) {
-  hipLaunchKernelGGL((k_lb<S, C, P, WG>), g, dim3(WG), 0, s, a);
-}
-
-template <int S, bool P>
-void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc* chains,
-                  const void* a0, const void* a1, void* pos, void* vel, int total, int4* rb,
-                  void* rd, void* rp, int* bbox, DevState* st, double rho0, int pre) {
-  using T = typename Store<S>::T;
-  using R = typename Store<S>::R;
-  hipLaunchKernelGGL((k_chain<S, P>), dim3(nch), dim3(WG), 0, s, boxes, chains, (const T*)a0,
-                     (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox, st, rho0, pre);
-}
+using lbhost::ChainLaunch;
+using lbhost::LbLaunch;
 
 template <int S>
 void launch_read(bool per, int nblk, hipStream_t s, const BoxDesc& d, const void* src, double* out,
@@ -102,13 +86,15 @@ void launch_sites(bool per, int nblk, hipStream_t s, const BoxDesc& d, const voi
 // coll: 0 BGK, 1 MRT, 2 MRT with ghost relaxation rate 1 (ghost moments not formed)
 template <int S>
 LbLaunch pick_lb(int coll, bool per) {
-  if (coll == 0) return per ? launch_lb<S, 0, true> : launch_lb<S, 0, false>;
-  if (coll == 1) return per ? launch_lb<S, 1, true> : launch_lb<S, 1, false>;
-  return per ? launch_lb<S, 2, true> : launch_lb<S, 2, false>;
+  if (coll == 0) return lbhost::pick_lb<S, 0>(per);
+  if (coll == 1) return lbhost::pick_lb<S, 1>(per);
+  return lbhost::pick_lb<S, 2>(per);
 }
 
 size_t store_bytes(int s) { return s == LB_STORE_F64 ? 8 : (s == LB_STORE_F32 ? 4 : 2); }
 size_t real_bytes(int s) { return s == LB_STORE_F64 ? 8 : 4; }
+// nodes per lane of the row items
+int row_nodes(int s) { return row_words(s) * 4 / (int)store_bytes(s); }
 
 }  // namespace
 
@@ -318,22 +304,42 @@ lb_status build_tables(lb_ctx* ctx, int grid_override) {
       work.push_back(0.25 * it.ex);
     }
     if (b.vec) {
-      const int V = 16 / (int)store_bytes(ctx->S);
-      const int rows = (WG / 64) * (64 / (b.dim.nx / V));  // rows per workgroup
-      for (int z = 0; z < b.iz; z += b.ez)
-        for (int y = 0; y < b.iy; y += rows) {
-          Item it{};
-          it.box = (int)bi;
-          it.kind = ITEM_ROWS;
-          it.x0 = 0;
-          it.y0 = 1 + y;
-          it.z0 = 1 + z;
-          it.ex = b.dim.nx;
-          it.ey = std::min(rows, b.iy - y);
-          it.ez = std::min(b.ez, b.iz - z);
-          items.push_back(it);
-          work.push_back((double)it.ex * it.ey * it.ez);
-        }
+      // interior rows cut into lane groups of V nodes, numbered row by row
+      // (y fastest, then z); an item is b.ez workgroup iterations of WG groups
+      const int V = row_nodes(ctx->S);
+      const int L = b.dim.nx / V, nyi = b.dim.ny - 2;
+      const int64_t groups = (int64_t)L * nyi * (b.dim.nz - 2);
+      const int64_t per = (int64_t)WG * std::max(1, b.ez);
+      for (int64_t g0 = 0; g0 < groups; g0 += per) {
+        const int64_t g1 = std::min(groups, g0 + per);
+        const int r0 = (int)(g0 / L), r1 = (int)((g1 - 1) / L);
+        const int z0 = r0 / nyi, z1 = r1 / nyi;
+        Item it{};
+        it.box = (int)bi;
+        it.kind = ITEM_ROWS;
+        it.x0 = (int)g0;
+        it.ex = (int)(g1 - g0);
+        // bounding box of the item's rows (chain overlap test)
+        it.z0 = 1 + z0;
+        it.ez = z1 - z0 + 1;
+        it.y0 = z0 == z1 ? 1 + (r0 - z0 * nyi) : 1;
+        it.ey = z0 == z1 ? r1 - r0 + 1 : nyi;
+        items.push_back(it);
+        work.push_back((double)it.ex * V);
+      }
+      // face rows: planes z = 0 and nz-1, then rows y = 0 and ny-1 of each
+      // interior plane
+      const int64_t fgroups = (int64_t)L * (2 * b.dim.ny + 2 * (b.dim.nz - 2));
+      const int64_t fper = (int64_t)WG * 4;
+      for (int64_t g0 = 0; g0 < fgroups; g0 += fper) {
+        Item it{};
+        it.box = (int)bi;
+        it.kind = ITEM_FACE_ROWS;
+        it.x0 = (int)g0;
+        it.ex = (int)std::min(fper, fgroups - g0);
+        items.push_back(it);
+        work.push_back(0.5 * it.ex * V);
+      }
       continue;
     }
     for (int z = 0; z < b.iz; z += b.ez)
@@ -641,8 +647,8 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed) {
 
 // Boundary nodes enumerated by boundary items, as rectangles.  Face priority
 // -x, +x, -y, +y, -z, +z: a face excludes the nodes of earlier (lower-axis)
-// faces.  For vector boxes the x-face nodes of interior rows (1 <= y <= ny-2,
-// 1 <= z <= nz-2) are written by the row items and left out here.
+// faces.  Row boxes have none: their x-face nodes are written by the interior
+// row items and every other boundary node by the face-row items.
 void add_rect(BoxHost& b, int f, int x0, int lx, int y0, int ly, int z0, int lz) {
   if (lx <= 0 || ly <= 0 || lz <= 0) return;
   const int r = b.n_rect++;
@@ -662,6 +668,7 @@ void face_tables(BoxHost& b) {
   const unsigned pm = b.dim.periodic_mask;
   b.nbnd = 0;
   b.n_rect = 0;
+  if (b.vec) return;
   for (int f = 0; f < 6; f++) {
     const int a = f / 2;
     if ((pm >> a) & 1u) continue;
@@ -678,17 +685,7 @@ void face_tables(BoxHost& b) {
         ln[k] = n3[k];
       }
     }
-    if (a == 0 && b.vec) {
-      // x face minus its interior rows: the z = 0 and z = nz-1 lines, and the
-      // y = 0 and y = ny-1 lines between them
-      const int x = st[0], ny = n3[1], nz = n3[2];
-      add_rect(b, f, x, 1, 0, ny, 0, 1);
-      add_rect(b, f, x, 1, 0, ny, nz - 1, 1);
-      add_rect(b, f, x, 1, 0, 1, 1, nz - 2);
-      add_rect(b, f, x, 1, ny - 1, 1, 1, nz - 2);
-    } else {
-      add_rect(b, f, st[0], ln[0], st[1], ln[1], st[2], ln[2]);
-    }
+    add_rect(b, f, st[0], ln[0], st[1], ln[1], st[2], ln[2]);
   }
 }
 
@@ -781,10 +778,13 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     off += nn * Q;
     if (pm) ctx->per = true;
     {
-      const int V = 16 / (int)store_bytes(cfg->storage);
+      const int V = row_nodes(cfg->storage);
+      const double groups = (double)(n3[0] / V) * (n3[1] - 2) * (n3[2] - 2);
+      // 32-bit buffer offsets: the planes one workgroup iteration touches
       const double plane = (double)Q * n3[0] * n3[1] * (double)store_bytes(cfg->storage);
-      b.vec = cfg->storage != LB_STORE_F64 && pm == 0u && n3[0] % V == 0 && n3[0] / V <= 64 &&
-              3.0 * plane < 4294967296.0 && !getenv("LBM_NO_VEC");
+      const double span = (WG / ((double)(n3[0] / V) * (n3[1] - 2)) + 4.0) * plane;
+      b.vec = cfg->storage != LB_STORE_F64 && pm == 0u && n3[0] % V == 0 && n3[0] >= 2 * V &&
+              groups < 2.0e9 && span < 2147483648.0 && !getenv("LBM_NO_VEC");
     }
     face_tables(b);
     default_tile(b);
@@ -838,11 +838,11 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     }
   }
   if (ctx->S == 0)
-    ctx->chain_fn = ctx->per ? launch_chain<0, true> : launch_chain<0, false>;
+    ctx->chain_fn = lbhost::pick_chain<0>(ctx->per);
   else if (ctx->S == 1)
-    ctx->chain_fn = ctx->per ? launch_chain<1, true> : launch_chain<1, false>;
+    ctx->chain_fn = lbhost::pick_chain<1>(ctx->per);
   else
-    ctx->chain_fn = ctx->per ? launch_chain<2, true> : launch_chain<2, false>;
+    ctx->chain_fn = lbhost::pick_chain<2>(ctx->per);
   load_tune_cache(ctx);
   if (upload_boxes(ctx) != LB_OK) {
     lb_free(ctx);
@@ -1271,8 +1271,12 @@ lb_status lb_autotune(lb_ctx* ctx, int32_t trials) {
     BoxHost& ref = ctx->bx[kv.second[0]];
     std::vector<std::array<int, 3>> cands;
     std::vector<int> exs;
-    for (int ex : {ref.ix, 32, 64, 128, 256})
-      if (ex >= 1 && ex <= ref.ix && std::find(exs.begin(), exs.end(), ex) == exs.end()) exs.push_back(ex);
+    if (ref.vec)  // row boxes: only the workgroup iterations per item (ez) matter
+      for (int ez : {2, 4, 8, 16, 32, 64}) cands.push_back({ref.ex, ref.ey, ez});
+    if (!ref.vec)
+      for (int ex : {ref.ix, 32, 64, 128, 256})
+        if (ex >= 1 && ex <= ref.ix && std::find(exs.begin(), exs.end(), ex) == exs.end())
+          exs.push_back(ex);
     for (int ex : exs)
       for (int pl : {256, 512, 1024}) {
         int ey = std::max(1, std::min(ref.iy, pl / ex));
