@@ -6,15 +6,18 @@ sub-boxes with edge lengths drawn from {32, 48, 64, 96}, each driven by its own
 kinematic-simulation tracer boundary history (sampled faces, 17x17 corner-aligned
 grid every 20 steps), each with one 32-bead FENE chain, D3Q19 MRT tau = 0.6,
 FP32 compute with FP16-deviation population storage, all boxes advanced by one
-fused launch per step.  A step is one pass of the whole path: chain kernel
-(interpolation, MD substeps, spreading records) + fused collide/stream over
-every box + boundary faces.
+fused launch per step, steps replayed from captured HIP graphs.  A step is one
+pass of the whole path: chain kernel (interpolation, MD substeps, spreading
+records) + fused collide/stream over every box and boundary face + the
+mass/momentum finalisation.
 
-Prints one JSON line: MLUPS over interior nodes, the HBM roofline fraction of
-the fused kernel (HIP events on its stream), the same 256 boxes run one by
-one as plain FP32 single-box contexts for the gain, the FP16 error against the
-FP64 oracle on one box of the batch, and the oracle's own throughput on the
-host cores.
+Prints one JSON line: MLUPS over interior nodes; the HBM roofline of the fused
+kernel (its average duration from HIP events recorded inside the replayed
+graphs, the measured copy ceiling, and the HBM traffic of the committed
+counter run when it was taken on the current kernel sources); the same boxes
+run one by one as plain FP32 single-box contexts for the gain; and the oracle
+leg: the FP64 oracle's own throughput on the host cores and the FP16 velocity
+error of one box of the batch against it.
 """
 import argparse
 import json
@@ -34,13 +37,16 @@ METRIC = "MLUPS & % HBM roofline; batched FP16-store vs plain FP32 at ≤1e-3 re
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=2000)
-    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--steps", type=int, default=5000)
+    p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--boxes", type=int, default=256)
     p.add_argument("--storage", default="f16", choices=["f16", "f32"])
+    p.add_argument("--graph-steps", type=int, default=100,
+                   help="steps per captured HIP graph (0: plain stream launches)")
     p.add_argument("--no-baselines", action="store_true",
-                   help="skip the plain-FP32 single-box, oracle-error and CPU legs")
+                   help="skip the plain-FP32 single-box and oracle legs")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-mib", type=int, default=1024, help="copy-probe size (0: skip)")
     p.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     return p.parse_args()
 
@@ -71,10 +77,10 @@ def bead_mass(n_beads):
     return 0.5 / n_beads
 
 
-def make_ctx(lbm, boxes, storage, tau, reduce_every=0, stream=None):
+def make_ctx(lbm, boxes, storage, tau, reduce_every=0, stream=None, graph_steps=0):
     ctx = lbm.Context([(b["n"],) * 3 for b in boxes], collision=lbm.MRT, tau=tau, tau_bulk=tau,
                       ghost_rate=1.0, storage=storage, reduce_every=reduce_every, stream=stream,
-                      torch_alloc=True)
+                      torch_alloc=True, graph_steps=graph_steps)
     for k, b in enumerate(boxes):
         ctx.set_initial(k, b["u0"])
         ctx.set_boundary(k, lbm.BC_SAMPLED, b["faces"], t0=0, dt=20, res=b["faces"].shape[2])
@@ -82,6 +88,45 @@ def make_ctx(lbm, boxes, storage, tau, reduce_every=0, stream=None):
                          mass=bead_mass(len(b["pos"])), fene_k=1.0, fene_r0=2.0,
                          anchor=b["anchor"])
     return ctx
+
+
+def traffic_file(storage, n_boxes):
+    return os.path.join(ROOT, "profiles", f"k_lb_batch{n_boxes}_{storage}_hbm_traffic.txt")
+
+
+def committed_traffic(storage, n_boxes):
+    """HBM bytes per k_lb launch from the committed counter summary, or None
+    when it is missing or was taken on other kernel sources."""
+    path = traffic_file(storage, n_boxes)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    from paper_0809_4958_amd.prof_summary import kernel_source_hash
+    if vals.get("kernel_sources_sha1") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(ctx, steps, torch):
+    """Exactly `steps` steps with per-step HIP events; returns (seconds, timing)."""
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    return elapsed, tm
 
 
 def main():
@@ -100,32 +145,28 @@ def main():
     t_in = time.time()
     boxes = batch_inputs(args.boxes, total_steps, tau)
     t_in = time.time() - t_in
+    print(json.dumps({"progress": "inputs ready", "seconds": round(t_in, 1)}), file=sys.stderr,
+          flush=True)
     interior = float(sum((b["n"] - 2) ** 3 for b in boxes))
     storage = lbm.STORE_F16DEV if args.storage == "f16" else lbm.STORE_F32
-    bytes_per_pop = 2 if storage == lbm.STORE_F16DEV else 4
     stream = torch.cuda.current_stream().cuda_stream
-    ctx = make_ctx(lbm, boxes, storage, tau, reduce_every=100, stream=stream)
+    copy_gbs = lbm.copy_probe(args.copy_mib << 20, 20) if args.copy_mib > 0 else None
+    ctx = make_ctx(lbm, boxes, storage, tau, reduce_every=100, stream=stream,
+                   graph_steps=args.graph_steps)
     if args.tune:
         ctx.autotune(3)
-    # warmup
     ctx.step(args.warmup)
     ctx.sync()
     torch.cuda.synchronize()
-    # timed region: exactly K steps, per-launch HIP events on the context stream
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(args.steps)
-    ctx.sync()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    tm = ctx.timing()
-    ctx.set_timing(False)
+    # timed region: exactly K steps; HIP events inside the replayed graphs
+    elapsed, tm = time_steps(ctx, args.steps, torch)
     ms_step = elapsed * 1e3 / args.steps
     mlups = interior * args.steps / elapsed / 1e6
     lb_ms = tm[1]
     alg_bytes = tm[3]
     achieved = alg_bytes / (lb_ms * 1e-3) / 1e9
+    traffic = committed_traffic(args.storage, args.boxes)
+    from paper_0809_4958_amd.prof_summary import kernel_source_hash
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -141,11 +182,13 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"batched: {args.boxes} KS tracer boxes with edges from {{32,48,64,96}}, "
-                         f"D3Q19 MRT tau=0.6, FP32 compute / {'FP16-deviation' if bytes_per_pop == 2 else 'FP32'} "
-                         "storage, sampled 17x17 faces every 20 steps, one 32-bead FENE chain per box"),
+                         f"D3Q19 MRT tau=0.6, FP32 compute / "
+                         f"{'FP16-deviation' if args.storage == 'f16' else 'FP32'} storage, "
+                         "sampled 17x17 faces every 20 steps, one 32-bead FENE chain per box"),
             "boxes": args.boxes,
             "interior_nodes": int(interior),
             "storage": args.storage,
+            "graph_steps": args.graph_steps,
             "launch": ctx.describe(),
         },
         "roofline": {
@@ -154,85 +197,102 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "k_lb (fused collide-stream + boundary faces + spreading gather)",
             "kernel_ms": round(lb_ms, 4),
             "chain_kernel_ms": round(tm[2], 4),
             "algorithmic_bytes_per_launch": alg_bytes,
+            "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+            "kernel_sources_sha1": kernel_source_hash(),
         },
         "input_generation_s": round(t_in, 1),
     }
-    print(json.dumps({"progress": "timed region done", "mlups": out["value"]}), file=sys.stderr,
-          flush=True)
+    ctx.close()
+    print(json.dumps({"progress": "timed region done", "mlups": out["value"],
+                      "k_lb_ms": round(lb_ms, 4)}), file=sys.stderr, flush=True)
 
     if not args.no_baselines:
-        # plain FP32, one single-box context per box size, timed per box-step
+        # plain FP32: one single-box context per box size (graph-replayed too),
+        # timed per box-step; the batch's time is the sum over its boxes
         sizes = sorted({b["n"] for b in boxes})
         per_size_ms = {}
         for n in sizes:
             b = next(bb for bb in boxes if bb["n"] == n)
-            single = make_ctx(lbm, [b], lbm.STORE_F32, tau, reduce_every=100, stream=stream)
-            k = 200
+            single = make_ctx(lbm, [b], lbm.STORE_F32, tau, reduce_every=100, stream=stream,
+                              graph_steps=args.graph_steps)
             single.step(20)
             single.sync()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            single.step(k)
-            single.sync()
-            torch.cuda.synchronize()
-            per_size_ms[n] = (time.perf_counter() - t1) * 1e3 / k
+            k = min(400, total_steps - 20)
+            t, _ = time_steps(single, k, torch)
+            per_size_ms[n] = t * 1e3 / k
             single.close()
         plain_ms = sum(per_size_ms[b["n"]] for b in boxes)
         plain_mlups = interior / (plain_ms * 1e-3) / 1e6
         out["plain_fp32_single_box"] = {"mlups": round(plain_mlups, 1),
                                         "ms_per_step_all_boxes": round(plain_ms, 3),
-                                        "ms_per_box_step": {str(k): round(v, 4) for k, v in per_size_ms.items()}}
+                                        "ms_per_box_step": {str(k): round(v, 4)
+                                                            for k, v in per_size_ms.items()}}
         out["gain_vs_plain_fp32"] = round(mlups / plain_mlups, 2)
-        # FP16 error vs the FP64 oracle on the first 32^3 box of the batch
-        import oracle
-        k32 = next(i for i, b in enumerate(boxes) if b["n"] == 32)
-        b = boxes[k32]
-        ob = oracle.OracleBox((32, 32, 32), collision=oracle.MRT, tau=tau, tau_bulk=tau, ghost_rate=1.0)
-        ob.set_initial(b["u0"])
-        ob.set_boundary(oracle.BC_SAMPLED, b["faces"].astype(np.float64), t0=0, dt=20, res=17)
-        ob.add_chain(b["pos"], None, substeps=10, fix_com=True, zeta=5.0, mass=bead_mass(32),
-                     fene_k=1.0, fene_r0=2.0, anchor=b["anchor"])
-        t1 = time.perf_counter()
-        st = ob.step(total_steps)
-        t_or = time.perf_counter() - t1
-        _, uo = ob.rho_u()
-        ug = ctx.read(k32, lbm.F_U)
-        m = ob.interior_mask()
-        err = float(np.linalg.norm(ug[m] - uo[m]) / np.linalg.norm(uo[m]))
-        out["rel_err_u_vs_fp64_oracle"] = {"value": err, "box": k32, "edge": 32,
-                                           "steps": total_steps, "oracle_status": int(st)}
-        # CPU baseline: the oracle on a bounded sample of the same workload
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        sample = [next(i for i, bb in enumerate(boxes) if bb["n"] == n) for n in sizes]
-        lups = 0.0
-        t1 = time.perf_counter()
-        for i in sample:
-            bb = boxes[i]
-            n = bb["n"]
-            o2 = oracle.OracleBox((n, n, n), collision=oracle.MRT, tau=tau, tau_bulk=tau)
-            o2.set_initial(bb["u0"])
-            o2.set_boundary(oracle.BC_SAMPLED, bb["faces"].astype(np.float64), t0=0, dt=20, res=17)
-            o2.add_chain(bb["pos"], None, mass=bead_mass(32), anchor=bb["anchor"])
-            k = 0
-            ts = time.perf_counter()
-            while time.perf_counter() - ts < args.cpu_seconds / len(sample) and k + 5 <= total_steps:
-                if o2.step(5) != 0:
-                    raise RuntimeError("oracle stopped with status %d" % o2.error()[0])
-                k += 5
-            lups += (n - 2) ** 3 * k
-        t_cpu = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": round(lups / t_cpu / 1e6, 2), "unit": "MLUPS",
-                               "cores": threads, "kind": "oracle",
-                               "sample": (f"FP64 oracle, one box of each edge {sizes} from the batch, "
-                                          f"MRT + chain, about {args.cpu_seconds:.0f} s of stepping "
-                                          f"({lups:.3g} lattice updates)"),
-                               "oracle_full_run_32_s": round(t_or, 2)}
+        print(json.dumps({"progress": "plain FP32 leg done"}), file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_leg(args, lbm, boxes, tau, storage, total_steps, stream,
+                                               torch)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_leg(args, lbm, boxes, tau, storage, total_steps, stream, torch):
+    """The FP64 oracle on the host cores: its throughput on a bounded sample of
+    the workload, and the error of the GPU path's velocity on one 32^3 box of
+    the batch after the whole run against it."""
+    import oracle
+    sizes = sorted({b["n"] for b in boxes})
+    sample = [next(i for i, bb in enumerate(boxes) if bb["n"] == n) for n in sizes]
+    lups = 0.0
+    t1 = time.perf_counter()
+    for i in sample:
+        bb = boxes[i]
+        n = bb["n"]
+        o2 = oracle.OracleBox((n, n, n), collision=oracle.MRT, tau=tau, tau_bulk=tau)
+        o2.set_initial(bb["u0"])
+        o2.set_boundary(oracle.BC_SAMPLED, bb["faces"].astype(np.float64), t0=0, dt=20, res=17)
+        o2.add_chain(bb["pos"], None, mass=bead_mass(32), anchor=bb["anchor"])
+        k = 0
+        ts = time.perf_counter()
+        while time.perf_counter() - ts < args.cpu_seconds / len(sample) and k + 5 <= total_steps:
+            if o2.step(5) != 0:
+                raise RuntimeError("oracle stopped with status %d" % o2.error()[0])
+            k += 5
+        lups += (n - 2) ** 3 * k
+    t_cpu = time.perf_counter() - t1
+    res = {"value": round(lups / t_cpu / 1e6, 2), "unit": "MLUPS",
+           "cores": oracle.threads(), "kind": "oracle",
+           "sample": (f"FP64 oracle, one box of each edge {sizes} from the batch, MRT + chain, "
+                      f"about {args.cpu_seconds:.0f} s of stepping ({lups:.3g} lattice updates)")}
+    # accuracy: the first 32^3 box of the batch, alone in a context of the
+    # benchmarked storage (batched and single contexts are bitwise identical),
+    # against the oracle over the whole run
+    k32 = next(i for i, b in enumerate(boxes) if b["n"] == 32)
+    b = boxes[k32]
+    ob = oracle.OracleBox((32, 32, 32), collision=oracle.MRT, tau=tau, tau_bulk=tau, ghost_rate=1.0)
+    ob.set_initial(b["u0"])
+    ob.set_boundary(oracle.BC_SAMPLED, b["faces"].astype(np.float64), t0=0, dt=20, res=17)
+    ob.add_chain(b["pos"], None, substeps=10, fix_com=True, zeta=5.0, mass=bead_mass(32),
+                 fene_k=1.0, fene_r0=2.0, anchor=b["anchor"])
+    t2 = time.perf_counter()
+    st = ob.step(total_steps)
+    t_or = time.perf_counter() - t2
+    g = make_ctx(lbm, [b], storage, tau, reduce_every=100, stream=stream)
+    g.step(total_steps)
+    g.sync()
+    torch.cuda.synchronize()
+    _, uo = ob.rho_u()
+    ug = g.read(0, lbm.F_U)
+    g.close()
+    m = ob.interior_mask()
+    err = float(np.linalg.norm(ug[m] - uo[m]) / np.linalg.norm(uo[m]))
+    res["rel_err_u_vs_oracle"] = {"value": err, "storage": args.storage, "box": k32, "edge": 32,
+                                  "steps": total_steps, "oracle_status": int(st),
+                                  "oracle_seconds": round(t_or, 2)}
+    return res
 
 
 if __name__ == "__main__":

@@ -5,6 +5,6 @@ import this package.  It shares no code with the GPU library: its C source
 (``lb_oracle.c``) is compiled with gcc by :func:`build` and bound here with
 ctypes.
 """
-from .oracle import (OracleBox, build, lattice, mrt_basis, equilibrium, collide,  # noqa: F401
+from .oracle import (OracleBox, build, threads, lattice, mrt_basis, equilibrium, collide,  # noqa: F401
                      chain_md, BGK, MRT, BC_AFFINE, BC_SAMPLED, OK, ERR_ARG, ERR_FENE,
                      ERR_BEAD_OUT, ERR_UNSTABLE, ERR_STATE)

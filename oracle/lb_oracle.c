@@ -23,6 +23,9 @@
 #include "lb_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -80,6 +83,14 @@ static void init_tables(void) {
     B[k] = s;
   }
   tables_ready = 1;
+}
+
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 void or_lattice(int c[OR_Q][3], double w[OR_Q]) {

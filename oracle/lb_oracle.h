@@ -47,6 +47,8 @@ typedef struct or_box or_box;
 
 /* lattice tables: c[19][3] and w[19] */
 void or_lattice(int c[OR_Q][3], double w[OR_Q]);
+/* number of OpenMP threads a step uses (the oracle's host cores) */
+int or_threads(void);
 /* weighted-orthogonal MRT basis: e[k][i] = e_k(c_i), norms b[k] = sum_i w_i e_k(c_i)^2 */
 void or_mrt_basis(double e[OR_Q][OR_Q], double b[OR_Q]);
 /* node-level primitives */

@@ -71,6 +71,7 @@ def _load():
         lib.or_read_mass_mom.argtypes = [ct.c_void_p, ct.c_void_p]
         lib.or_read_last_force.argtypes = [ct.c_void_p, ct.c_void_p]
         lib.or_lattice.argtypes = [ct.c_void_p, ct.c_void_p]
+        lib.or_threads.restype = ct.c_int
         lib.or_mrt_basis.argtypes = [ct.c_void_p, ct.c_void_p]
         lib.or_equilibrium.argtypes = [ct.c_double, ct.c_void_p, ct.c_void_p]
         lib.or_collide.argtypes = [ct.POINTER(_Params), ct.c_void_p, ct.c_void_p, ct.c_void_p]
@@ -90,6 +91,11 @@ def _f64(a, shape=None) -> np.ndarray:
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's steps use."""
+    return int(_load().or_threads())
 
 
 def lattice():

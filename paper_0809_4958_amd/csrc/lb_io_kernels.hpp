@@ -5,6 +5,7 @@
 //               order per box, checks finiteness, advances the step counter.
 //   k_set_pre / k_read / k_read_sites / k_read_beads   state upload and readout.
 //   k_copy      16-byte stream copy (HBM ceiling probe).
+//   k_stamp     device wall-clock timestamp (timing inside captured graphs).
 #pragma once
 #include "lb_kernels.hpp"
 
@@ -189,6 +190,12 @@ __global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src, uint
     dst[i + 3 * stride] = d;
   }
   for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// one constant-rate device timestamp (hipDeviceAttributeWallClockRate kHz),
+// stored with a vector store
+__global__ void k_stamp(long long* slot) {
+  if (threadIdx.x == 0) *slot = wall_clock64();
 }
 
 }  // namespace lbdev

@@ -137,13 +137,24 @@ struct lb_ctx {
   lb_status latched = LB_OK;
   hipGraphExec_t gexec = nullptr;
   int gsteps = 0;
+  // timed graphs: two instances with their own event-record nodes, replayed
+  // alternately so the host reads one chunk's events while the next runs
+  hipGraphExec_t gexec_t[2] = {nullptr, nullptr};
+  long long* d_stamps = nullptr;     // [2][3 * gsteps_t] device timestamps
+  long long* h_stamps = nullptr;     // pinned copy
+  hipEvent_t stamp_ev[2] = {nullptr, nullptr};
+  double clock_khz = 0;
+  int gsteps_t = 0;
   LbLaunch lb_fn = nullptr;
   ChainLaunch chain_fn = nullptr;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
-  int t_steps = 0, t_lb = 0, t_chain = 0;
+  int t_steps = 0;
+  // event times accumulated from timed graph chunks
+  double acc_lb = 0, acc_ch = 0, acc_step = 0;
+  int acc_n = 0, acc_step_n = 0;
   std::string err, desc;
   std::vector<void*> owned;
 };
@@ -211,6 +222,21 @@ void drop_graph(lb_ctx* ctx) {
     (void)hipGraphExecDestroy(ctx->gexec);
     ctx->gexec = nullptr;
   }
+  for (int x = 0; x < 2; x++)
+    if (ctx->gexec_t[x]) {
+      (void)hipGraphExecDestroy(ctx->gexec_t[x]);
+      ctx->gexec_t[x] = nullptr;
+    }
+}
+
+void drop_stamps(lb_ctx* ctx) {
+  if (ctx->d_stamps) dfree(ctx, ctx->d_stamps);
+  if (ctx->h_stamps) (void)hipHostFree(ctx->h_stamps);
+  for (auto& e : ctx->stamp_ev)
+    if (e) (void)hipEventDestroy(e);
+  ctx->d_stamps = nullptr;
+  ctx->h_stamps = nullptr;
+  ctx->stamp_ev[0] = ctx->stamp_ev[1] = nullptr;
 }
 
 // Default tile: whole interior rows in x (coalesced, one box row per wave
@@ -622,27 +648,51 @@ hipEvent_t next_event(lb_ctx* ctx) {
   return ctx->ev[ctx->ev_used++];
 }
 
-void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed) {
-  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-  if (timed) {
-    e0 = next_event(ctx);
-    (void)hipEventRecord(e0, s);
-  }
+// One step on stream s: k_chain, k_lb, k_finalize.  ev3 (optional) receives
+// event records, st3 (optional) device timestamps, before k_chain, before
+// k_lb and after k_lb.
+void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
+                  long long* st3 = nullptr) {
+  auto mark = [&](int k) {
+    if (ev3) (void)hipEventRecord(ev3[k], s);
+    if (st3) hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, st3 + k);
+  };
+  mark(0);
   if (!ctx->ch.empty())
     ctx->chain_fn((int)ctx->ch.size(), s, ctx->d_boxes, ctx->d_chains, ctx->arena[0], ctx->arena[1],
                   ctx->d_pos, ctx->d_vel, ctx->total_beads, ctx->d_rec_base, ctx->d_rec_d,
                   ctx->d_rec_dp, ctx->d_bbox, ctx->d_st, ctx->cfg.rho0, pre);
-  if (timed) {
-    e1 = next_event(ctx);
-    (void)hipEventRecord(e1, s);
-  }
+  mark(1);
   const LbArgs a = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
   ctx->lb_fn(dim3(ctx->grid), s, a);
-  if (timed) {
-    e2 = next_event(ctx);
-    (void)hipEventRecord(e2, s);
-  }
+  mark(2);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, s, a);
+}
+
+void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed) {
+  hipEvent_t ev3[3];
+  if (timed)
+    for (auto& e : ev3) e = next_event(ctx);
+  enqueue_step(ctx, s, pre, timed ? ev3 : nullptr);
+}
+
+// add the timestamps of one finished timed graph chunk x (copied to pinned
+// host memory behind the chunk on the context stream)
+lb_status accumulate_chunk(lb_ctx* ctx, int x) {
+  const int n = ctx->gsteps_t;
+  HIPCHK(hipEventSynchronize(ctx->stamp_ev[x]));
+  const long long* t = ctx->h_stamps + (size_t)x * 3 * n;
+  const double ms = 1.0 / ctx->clock_khz;  // one clock tick in ms
+  for (int k = 0; k < n; k++) {
+    ctx->acc_ch += (double)(t[3 * k + 1] - t[3 * k]) * ms;
+    ctx->acc_lb += (double)(t[3 * k + 2] - t[3 * k + 1]) * ms;
+    if (k + 1 < n) {
+      ctx->acc_step += (double)(t[3 * (k + 1)] - t[3 * k]) * ms;
+      ctx->acc_step_n++;
+    }
+  }
+  ctx->acc_n += n;
+  return LB_OK;
 }
 
 // Boundary nodes enumerated by boundary items, as rectangles.  Face priority
@@ -971,6 +1021,8 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
   if (timed) {
     ctx->ev_used = 0;
     ctx->t_steps = 0;
+    ctx->acc_lb = ctx->acc_ch = ctx->acc_step = 0;
+    ctx->acc_n = ctx->acc_step_n = 0;
   }
   if (ctx->state_pre) {
     enqueue_step(ctx, ctx->stream, 1, timed);
@@ -980,6 +1032,52 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
     if (timed) ctx->t_steps++;
   }
   const int gs = ctx->cfg.graph_steps;
+  if (gs > 0 && timed && left >= gs) {
+    // HIP events recorded inside a graph cannot be timed: the timed graphs
+    // carry timestamp kernels instead
+    if (!ctx->gexec_t[0] || ctx->gsteps_t != gs) {
+      drop_graph(ctx);
+      drop_stamps(ctx);
+      int dev = 0, khz = 0;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+      if (khz <= 0) return fail(ctx, LB_ERR_HIP, "device wall-clock rate unavailable");
+      ctx->clock_khz = khz;
+      bool ok = true;
+      ctx->d_stamps = dalloc_t<long long>(ctx, 6 * (size_t)gs, &ok);
+      if (!ok) return fail(ctx, LB_ERR_OOM, "timestamp buffer allocation failed");
+      HIPCHK(hipHostMalloc((void**)&ctx->h_stamps, 6 * (size_t)gs * sizeof(long long),
+                           hipHostMallocDefault));
+      for (auto& e : ctx->stamp_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      for (int x = 0; x < 2; x++) {
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+        for (int k = 0; k < gs; k++)
+          enqueue_step(ctx, ctx->cap_stream, 0, nullptr, ctx->d_stamps + (size_t)x * 3 * gs + 3 * k);
+        HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
+        HIPCHK(hipGraphInstantiate(&ctx->gexec_t[x], g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+      }
+      ctx->gsteps_t = gs;
+    }
+    const size_t nb = 3 * (size_t)gs * sizeof(long long);
+    int j = 0;
+    for (; left >= gs; j++, left -= gs) {
+      const int x = j & 1;
+      if (j >= 2) {  // chunk j-2 used the same buffers: its stamps must be read first
+        lb_status st = accumulate_chunk(ctx, x);
+        if (st) return st;
+      }
+      HIPCHK(hipGraphLaunch(ctx->gexec_t[x], ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->h_stamps + (size_t)x * 3 * gs, ctx->d_stamps + (size_t)x * 3 * gs,
+                            nb, hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipEventRecord(ctx->stamp_ev[x], ctx->stream));
+    }
+    for (int r = std::max(0, j - 2); r < j; r++) {
+      lb_status st = accumulate_chunk(ctx, r & 1);
+      if (st) return st;
+    }
+  }
   if (gs > 0 && !timed) {
     while (left >= gs) {
       if (!ctx->gexec || ctx->gsteps != gs) {
@@ -1217,22 +1315,25 @@ lb_status lb_set_timing(lb_ctx* ctx, int32_t on) {
 lb_status lb_get_timing(lb_ctx* ctx, double out[4]) {
   if (!ctx || !out) return LB_ERR_ARG;
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  double step_ms = 0, lb_ms = 0, ch_ms = 0;
-  const int n = ctx->ev_used / 3;
-  for (int k = 0; k < n; k++) {
+  double step_ms = ctx->acc_step, lb_ms = ctx->acc_lb, ch_ms = ctx->acc_ch;
+  int n_step = ctx->acc_step_n;
+  const int n_ev = ctx->ev_used / 3;
+  for (int k = 0; k < n_ev; k++) {
     float a = 0, b = 0, c = 0;
     HIPCHK(hipEventElapsedTime(&a, ctx->ev[3 * k], ctx->ev[3 * k + 1]));
     HIPCHK(hipEventElapsedTime(&b, ctx->ev[3 * k + 1], ctx->ev[3 * k + 2]));
     ch_ms += a;
     lb_ms += b;
-    if (k + 1 < n) {
+    if (k + 1 < n_ev) {
       HIPCHK(hipEventElapsedTime(&c, ctx->ev[3 * k], ctx->ev[3 * (k + 1)]));
       step_ms += c;
+      n_step++;
     }
   }
+  const int n = n_ev + ctx->acc_n;
   double bytes = 0;
   for (auto& b : ctx->bx) bytes += 2.0 * Q * store_bytes(ctx->S) * (double)b.interior;
-  out[0] = n > 1 ? step_ms / (n - 1) : (n ? (ch_ms + lb_ms) : 0);
+  out[0] = n_step > 0 ? step_ms / n_step : (n ? (ch_ms + lb_ms) / n : 0);
   out[1] = n ? lb_ms / n : 0;
   out[2] = (n && !ctx->ch.empty()) ? ch_ms / n : 0;
   out[3] = bytes;
@@ -1388,6 +1489,7 @@ void lb_free(lb_ctx* ctx) {
   dfree(ctx, ctx->d_rec_dp);
   dfree(ctx, ctx->d_bbox);
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
+  drop_stamps(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;

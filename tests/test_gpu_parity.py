@@ -202,10 +202,16 @@ def test_batched_equals_single_bitwise(storage):
 def test_graph_replay_and_determinism_bitwise():
     case = ks_case(24, 60, dt=20, res=9, n_beads=8, config_idx=3)
     runs = []
-    for graph_steps in (0, 0, 7):
+    for graph_steps, timed in ((0, False), (0, False), (7, False), (7, True), (0, True)):
         ctx = make_ctx(case, "f16", graph_steps=graph_steps)
         ctx.step(25)
+        # timed: per-step HIP events (inside the two alternating graphs when
+        # graph_steps > 0); the timed steps must compute the same state
+        ctx.set_timing(timed)
         ctx.step(35)
+        if timed:
+            t = ctx.timing()
+            assert t[1] > 0 and t[2] > 0 and t[0] >= t[1]
         runs.append((ctx.read(0, lbm.F_POP), ctx.read(0, lbm.F_BEAD_POS, n_beads=8),
                      ctx.read(0, lbm.F_MASS_MOM)))
         ctx.close()
