@@ -32,8 +32,8 @@
  *     LB_ERR_BUFSIZE.
  *   - Time: the state after n steps is the pre-collision state at t_n = n.
  *     Step n uses the boundary velocity at t_n.
- *   - Streams: all device work is ordered on lb_config.stream (NULL = a
- *     stream the context creates).  lb_step is asynchronous; lb_sync and
+ *   - Streams: all device work is ordered on lb_config.stream (NULL = the
+ *     null stream, which PyTorch's default stream also is).  lb_step is asynchronous; lb_sync and
  *     lb_read_fields synchronise.  A context is not thread-safe.
  *   - Errors found on the device (overstretched FENE bond, bead stencil
  *     leaving the interior, non-finite mass or momentum) are latched with the
@@ -89,7 +89,7 @@ typedef struct {
   double rho0;             /* rest density; also the density of the boundary equilibrium */
   int32_t reduce_every;    /* K > 0: record mass and momentum of the interior at t_n, n % K == 0 */
   int32_t fp16_exp;        /* s of LB_STORE_F16DEV, 0 = 10; |h| < 65504 needs |f/w - rho0| < 65504 / 2^s */
-  void* stream;            /* hipStream_t or NULL */
+  void* stream;            /* hipStream_t; NULL = the null stream */
   /* device allocator hook (e.g. PyTorch's caching allocator); NULL = hipMalloc/hipFree */
   void* (*dev_alloc)(size_t bytes, void* user);
   void (*dev_free)(void* ptr, void* user);
@@ -108,7 +108,7 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out);
  * u: host FP64 [nz][ny][nx][3], or NULL for rest.  Only before the first lb_step. */
 lb_status lb_set_initial(lb_ctx* ctx, int32_t box, const double* u);
 
-typedef enum { LB_BC_AFFINE = 0, LB_BC_SAMPLED = 1 } lb_bc_mode;
+typedef enum { LB_BC_AFFINE = 0, LB_BC_SAMPLED = 1, LB_BC_LEARNED = 2 } lb_bc_mode;
 
 /* Boundary velocity history of one box (Sec. 2-3).  Sample k belongs to step
  * t0 + k*dt; the velocity at step n is linear in time between the samples
@@ -122,6 +122,14 @@ typedef enum { LB_BC_AFFINE = 0, LB_BC_SAMPLED = 1 } lb_bc_mode;
  *            p (n-1)/(res-1) (corner aligned); u_b is bilinear on the face.
  *            A node on several faces takes the first face in the order above.
  *            FP64 if data_is_f64, else FP32.
+ *   LEARNED: data = a DEVICE pointer the caller owns and keeps alive, FP32
+ *            [n_samples][6][res][res][3] laid out as SAMPLED, used as a ring:
+ *            step n reads slot ((n - t0) / dt) mod n_samples (and the next slot
+ *            for the linear time weight when dt > 1), so stepping never runs
+ *            out of samples.  The caller refills slots on the context stream
+ *            before the steps that read them (the learned upsampler of
+ *            lbnet.h writes one window of dt = 1 slots per call).  Not copied;
+ *            FP32/FP16 storage only (LB_ERR_ARG for FP64 contexts).
  * The boundary density is rho0.  Boxes with a boundary layer need a boundary
  * before lb_step (LB_ERR_STATE).  May be replaced between lb_step calls. */
 typedef struct {

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbm.so")
 # (source, extra defines): the host side, and one translation unit per
 # storage x collision instantiation of the step kernels
-UNITS = [("lbm.hip", [])] + [
+UNITS = [("lbm.hip", []), ("lbnet.hip", [])] + [
     ("lb_step.hip", [f"-DLB_S={st}", f"-DLB_C={co}"]) for st in range(3) for co in range(3)
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

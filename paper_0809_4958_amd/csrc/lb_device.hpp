@@ -89,7 +89,7 @@ struct BoxDesc {
   int bc_mode;          // 0 affine, 1 sampled, -1 none
   int bc_dt, bc_ns, bc_res;
   int64_t bc_t0;
-  const void* bc;       // affine: double [ns][9]; sampled: T [ns][6][res][res][3]
+  const void* bc;       // affine: double [ns][9]; sampled: R [ns][6][res][res][3]; learned: float ring
   int chain_first, chain_count;
   int nbnd;             // boundary nodes enumerated by boundary items
   int n_rect;           // boundary rectangles (a face, or part of one)

@@ -287,11 +287,16 @@ __device__ __forceinline__ void boundary_velocity(const BoxDesc& b, int f, const
   if (rel < 0) rel = 0;
   long long k = rel / b.bc_dt;
   long long rem = rel - k * b.bc_dt;
-  if (k >= b.bc_ns) {
+  long long k1 = k + 1;  // second sample of the linear time weight
+  if (b.bc_mode == 2) {
+    // learned: ring of n_samples slots
+    k %= b.bc_ns;
+    k1 = (k + 1) % b.bc_ns;
+  } else if (k >= b.bc_ns) {
     k = b.bc_ns - 1;
     rem = 0;
   }
-  bool two = rem > 0 && k + 1 < b.bc_ns;
+  bool two = rem > 0 && (b.bc_mode == 2 || k1 < b.bc_ns);
   const R th = (R)rem / (R)b.bc_dt;
   if (b.bc_mode == 0) {
     const double* A0 = (const double*)b.bc + 9 * k;
@@ -328,7 +333,7 @@ __device__ __forceinline__ void boundary_velocity(const BoxDesc& b, int f, const
 #pragma unroll
   for (int t = 0; t < 2; t++) {
     if (t == 1 && !two) break;
-    const R* Sk = Sb + ((size_t)(k + t) * 6 + f) * fs;
+    const R* Sk = Sb + ((size_t)(t ? k1 : k) * 6 + f) * fs;
     R* out = t ? v1 : v0;
 #pragma unroll
     for (int cmp = 0; cmp < 3; cmp++) {

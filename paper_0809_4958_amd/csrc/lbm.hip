@@ -43,6 +43,7 @@ struct BoxHost {
   int bc_mode = -1, bc_dt = 1, bc_ns = 0, bc_res = 0;
   int64_t bc_t0 = 0;
   void* d_bc = nullptr;
+  const void* ring = nullptr;  // LEARNED: caller-owned device ring (not freed here)
   int ex = 0, ey = 0, ez = 0;  // tile shape
   int n_rect = 0;
   int rect_face[MAX_RECT] = {};
@@ -103,7 +104,6 @@ struct lb_ctx {
   std::vector<BoxHost> bx;
   std::vector<ChainHost> ch;
   hipStream_t stream = nullptr;
-  bool own_stream = false;
   hipStream_t cap_stream = nullptr;
   int S = 0, coll = 0;
   bool per = false;
@@ -474,7 +474,7 @@ lb_status upload_boxes(lb_ctx* ctx) {
     d.bc_ns = b.bc_ns;
     d.bc_res = b.bc_res;
     d.bc_t0 = b.bc_t0;
-    d.bc = b.d_bc;
+    d.bc = b.bc_mode == LB_BC_LEARNED ? b.ring : b.d_bc;
     d.chain_first = cfirst[i];
     d.chain_count = ccount[i];
     d.nbnd = b.nbnd;
@@ -841,15 +841,8 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     ctx->bx.push_back(b);
   }
   ctx->arena_elems = off;
-  if (cfg->stream) {
-    ctx->stream = (hipStream_t)cfg->stream;
-  } else {
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete ctx;
-      return LB_ERR_HIP;
-    }
-    ctx->own_stream = true;
-  }
+  // NULL is HIP's null stream (ordered with PyTorch's default stream)
+  ctx->stream = (hipStream_t)cfg->stream;
   if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     lb_free(ctx);
     return LB_ERR_HIP;
@@ -935,11 +928,28 @@ lb_status lb_set_boundary(lb_ctx* ctx, int32_t box, const lb_boundary* bc) {
   if (s) return s;
   if (!bc || !bc->data || bc->dt < 1 || bc->n_samples < 1)
     return fail(ctx, LB_ERR_ARG, "invalid boundary description");
-  if (bc->mode != LB_BC_AFFINE && bc->mode != LB_BC_SAMPLED)
+  if (bc->mode != LB_BC_AFFINE && bc->mode != LB_BC_SAMPLED && bc->mode != LB_BC_LEARNED)
     return fail(ctx, LB_ERR_ARG, "unknown boundary mode");
-  if (bc->mode == LB_BC_SAMPLED && (bc->res < 2 || bc->res > 8192))
+  if (bc->mode != LB_BC_AFFINE && (bc->res < 2 || bc->res > 8192))
     return fail(ctx, LB_ERR_ARG, "sampled boundary needs res >= 2");
   BoxHost& b = ctx->bx[box];
+  if (bc->mode == LB_BC_LEARNED) {
+    // caller-owned device ring, read in place
+    if (ctx->S == LB_STORE_F64 || bc->data_is_f64)
+      return fail(ctx, LB_ERR_ARG, "learned boundary rings are FP32 (FP32/FP16 storage)");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    dfree(ctx, b.d_bc);
+    b.d_bc = nullptr;
+    b.ring = bc->data;
+    b.has_bc = true;
+    b.bc_mode = bc->mode;
+    b.bc_t0 = bc->t0;
+    b.bc_dt = bc->dt;
+    b.bc_ns = bc->n_samples;
+    b.bc_res = bc->res;
+    drop_graph(ctx);
+    return upload_boxes(ctx);
+  }
   size_t per = bc->mode == LB_BC_AFFINE ? 9 : (size_t)6 * bc->res * bc->res * 3;
   size_t n = per * bc->n_samples;
   void* dptr = nullptr;
@@ -969,6 +979,7 @@ lb_status lb_set_boundary(lb_ctx* ctx, int32_t box, const lb_boundary* bc) {
   }
   dfree(ctx, b.d_bc);
   b.d_bc = dptr;
+  b.ring = nullptr;
   b.has_bc = true;
   b.bc_mode = bc->mode;
   b.bc_t0 = bc->t0;
@@ -1011,7 +1022,7 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
     if (!b.has_bc) return fail(ctx, LB_ERR_STATE, "a box with a boundary layer has no boundary");
     const int64_t first = ctx->host_step, last = ctx->host_step + n_steps - 1;
     const int64_t end = b.bc_t0 + (int64_t)(b.bc_ns - 1) * b.bc_dt;
-    if (first < b.bc_t0 || last > end)
+    if (first < b.bc_t0 || (b.bc_mode != LB_BC_LEARNED && last > end))
       return fail(ctx, LB_ERR_ARG, "steps beyond the boundary samples (no extrapolation)");
   }
   lb_status s = prepare(ctx);
@@ -1491,7 +1502,6 @@ void lb_free(lb_ctx* ctx) {
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
   drop_stamps(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 

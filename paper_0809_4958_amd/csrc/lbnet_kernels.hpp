@@ -1,0 +1,407 @@
+// lbnet_kernels.hpp -- gfx950 kernels of the learned boundary upsampler.
+//
+// The network maps the coarse boundary samples of one box face (an R x R
+// corner-aligned grid every dt steps, the SAMPLED source of the boundary
+// velocity, Sec. 2-3) to the per-step 64 x 64 face field, as a residual over
+// the bilinear-in-space x linear-in-time interpolation of those samples.
+//
+// One network sample is (face, step n in the window [t_k, t_k+1)):
+//   input   S_{k-1}, S_k, S_{k+1}, S_{k+2} on the coarse grid ([4][3][R][R])
+//           and the phase theta = (n - t_k) / dt
+//   lift    L = corner-aligned bilinear lift of a coarse grid to 64 x 64; with
+//           Sb = (1 - theta) S_k + theta S_k+1 and s the RMS of the sample's
+//           4 x 3 x R x R coarse values, the 16 input channels are
+//             0..2   L(Sb) / s
+//             3..5   L(Duu Sb) / s    Duu, Dvv: coarse second differences
+//             6..8   L(Dvv Sb) / s    (at the edge nodes: the next node's)
+//             9..11  L(S_k+2 - S_k+1 - S_k + S_k-1) / s
+//             12     theta
+//             13, 14 4 a (1 - a), 4 b (1 - b): position of the node inside
+//                    its coarse cell (a along u, b along v)
+//             15     0
+//   net     conv3x3(16 -> 64) ReLU, conv3x3(64 -> 64) ReLU, conv3x3(64 -> 16),
+//           zero padding; input channel 15 and output channels 3..15 carry
+//           zero weights
+//   output  u = base + s r, base = L(Sb) (the plain interpolation)
+//
+// Layouts: activations NHWC bfloat16 [B][64][64][C]; device weights
+// [tap][co][ci] bfloat16 (tap = 3 (dy + 1) + (dx + 1)) from FP32 master
+// weights of the same layout; the backward-data weights are the same array
+// with the tap mirrored and co/ci exchanged.  Products run on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation: lane l holds rows l % 16
+// (A) / columns l % 16 (B) and the eight K values 8 (l / 16) .. +7; the
+// accumulator holds rows 4 (l / 16) .. +3 of column l % 16.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbnet {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int NB = 256;     // threads per workgroup
+constexpr int IMG = 64;     // image edge (face nodes)
+constexpr int CIN = 16;     // lifted input channels (15 used)
+constexpr int CH = 64;      // hidden channels
+constexpr int COUT = 16;    // output channels of the last layer (3 used)
+constexpr int NTAP = 9;
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }  // round to nearest even
+__device__ __forceinline__ float from_bf16(__bf16 v) { return (float)v; }
+
+// ---------------------------------------------------------------- lift
+// One workgroup per sample.  coarse [B][4][3][R][R] (row v, column u),
+// theta [B]; writes x0 [B][64][64][16] bf16, base [B][64][64][3] and s [B].
+// The coarse feature grids (Sb, Duu Sb, Dvv Sb, temporal difference) are
+// formed in LDS first (R <= 64).
+__global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
+                                             const float* __restrict__ theta, int R,
+                                             __bf16* __restrict__ x0, float* __restrict__ base,
+                                             float* __restrict__ scale) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const float* c = coarse + (size_t)b * 12 * R * R;
+  const int RR = R * R;
+  __shared__ double red[NB];
+  extern __shared__ float feat[];  // [12][R][R]: Sb, Duu Sb, Dvv Sb, temporal difference
+  double ss = 0.0;
+  for (int i = tid; i < 12 * RR; i += NB) ss += (double)c[i] * (double)c[i];
+  red[tid] = ss;
+  __syncthreads();
+  for (int o = NB / 2; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  const double rms = sqrt(red[0] / (12.0 * RR));
+  const float s = rms > 0.0 ? (float)rms : 1.0f;
+  if (tid == 0) scale[b] = s;
+  const float th = theta[b];
+  // Sb and the temporal difference
+  for (int i = tid; i < 3 * RR; i += NB) {
+    const int cmp = i / RR, vu = i - cmp * RR;
+    const float sm = c[(0 * 3 + cmp) * RR + vu], s0 = c[(1 * 3 + cmp) * RR + vu];
+    const float s1 = c[(2 * 3 + cmp) * RR + vu], s2 = c[(3 * 3 + cmp) * RR + vu];
+    feat[(0 * 3 + cmp) * RR + vu] = (1.0f - th) * s0 + th * s1;
+    feat[(3 * 3 + cmp) * RR + vu] = (s2 - s1) - (s0 - sm);
+  }
+  __syncthreads();
+  // second differences of Sb along u and v (edge nodes take the next node's)
+  for (int i = tid; i < 3 * RR; i += NB) {
+    const int cmp = i / RR, vu = i - cmp * RR;
+    const int v = vu / R, u = vu - v * R;
+    const float* g = feat + cmp * RR;
+    const int uc = u < 1 ? 1 : (u > R - 2 ? R - 2 : u), vc = v < 1 ? 1 : (v > R - 2 ? R - 2 : v);
+    feat[(1 * 3 + cmp) * RR + vu] =
+        R >= 3 ? g[v * R + uc + 1] - 2.0f * g[v * R + uc] + g[v * R + uc - 1] : 0.0f;
+    feat[(2 * 3 + cmp) * RR + vu] =
+        R >= 3 ? g[(vc + 1) * R + u] - 2.0f * g[vc * R + u] + g[(vc - 1) * R + u] : 0.0f;
+  }
+  __syncthreads();
+  for (int p = tid; p < IMG * IMG; p += NB) {
+    const int v = p / IMG, u = p - v * IMG;
+    // corner-aligned bilinear weights (same integer mapping as the face grid)
+    const int su = u * (R - 1), sv = v * (R - 1);
+    const int pu = su / (IMG - 1), pv = sv / (IMG - 1);
+    const float au = (float)(su - pu * (IMG - 1)) / (float)(IMG - 1);
+    const float av = (float)(sv - pv * (IMG - 1)) / (float)(IMG - 1);
+    const int pu1 = pu + 1 < R ? pu + 1 : pu, pv1 = pv + 1 < R ? pv + 1 : pv;
+    float lifted[12];
+#pragma unroll
+    for (int ch = 0; ch < 12; ch++) {
+      const float* g = feat + ch * RR;
+      lifted[ch] = (1.0f - au) * (1.0f - av) * g[pv * R + pu] + au * (1.0f - av) * g[pv * R + pu1] +
+                   (1.0f - au) * av * g[pv1 * R + pu] + au * av * g[pv1 * R + pu1];
+    }
+    __bf16* xo = x0 + ((size_t)b * IMG * IMG + p) * CIN;
+#pragma unroll
+    for (int ch = 0; ch < 12; ch++) xo[ch] = to_bf16(lifted[ch] / s);
+    xo[12] = to_bf16(th);
+    xo[13] = to_bf16(4.0f * au * (1.0f - au));
+    xo[14] = to_bf16(4.0f * av * (1.0f - av));
+    xo[15] = to_bf16(0.0f);
+    float* bo = base + ((size_t)b * IMG * IMG + p) * 3;
+#pragma unroll
+    for (int k = 0; k < 3; k++) bo[k] = lifted[k];
+  }
+}
+
+// ---------------------------------------------------------------- conv
+// Implicit-GEMM 3x3 convolution over pairs of image rows.  EPI: 0 = bias +
+// ReLU -> bf16; 1 = bias -> fp32 (last layer, all CO channels); 2 = no bias,
+// times the mask (mask_src > 0) -> bf16 (backward data through a ReLU).
+// Persistent: workgroup g handles row pairs g, g + gridDim.x, ...
+template <int CI, int CO, int EPI>
+__global__ __launch_bounds__(NB) void k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
+                                             const float* __restrict__ bias,
+                                             const __bf16* __restrict__ mask_src,
+                                             void* __restrict__ out, int n_pairs) {
+  constexpr int CP = CI + 8;                 // padded channel stride in LDS
+  constexpr int KCH = (NTAP * CI + 31) / 32;  // K chunks of 32
+  constexpr int NBK = CO / 16;               // 16-column blocks
+  __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CP];
+  __shared__ __attribute__((aligned(16))) __bf16 sx[4 * (IMG + 2) * CP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // weights once per workgroup
+  for (int i = tid; i < NTAP * CO * (CI / 8); i += NB) {
+    const int row = i / (CI / 8), c8 = i - row * (CI / 8);
+    *(uint4*)&sw[row * CP + 8 * c8] = *(const uint4*)&w[(size_t)row * CI + 8 * c8];
+  }
+  const int r = wave >> 1, px0 = (wave & 1) * 32;
+  for (int pair = blockIdx.x; pair < n_pairs; pair += gridDim.x) {
+    const int b = pair / (IMG / 2), y0 = 2 * (pair - b * (IMG / 2));
+    __syncthreads();  // previous tile's reads of sx are done
+    // rows y0-1 .. y0+2, columns -1 .. 64, zero outside the image
+    for (int i = tid; i < 4 * (IMG + 2) * (CI / 8); i += NB) {
+      const int c8 = i % (CI / 8), q = i / (CI / 8);
+      const int xx = q % (IMG + 2) - 1, rr = q / (IMG + 2), yy = y0 - 1 + rr;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
+        v = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
+      *(uint4*)&sx[q * CP + 8 * c8] = v;
+    }
+    __syncthreads();
+    f32x4 acc[2][NBK];
+#pragma unroll
+    for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+      for (int nb = 0; nb < NBK; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int kc = 0; kc < KCH; kc++) {
+      const int k0 = 32 * kc + 8 * (lane >> 4);
+      const bool kv = k0 < NTAP * CI;
+      const int tap = kv ? k0 / CI : 0, ci = kv ? k0 - tap * CI : 0;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      bf16x8 a[2], bb[NBK];
+#pragma unroll
+      for (int mb = 0; mb < 2; mb++) {
+        const int px = px0 + 16 * mb + (lane & 15);
+        a[mb] = kv ? *(const bf16x8*)&sx[((r + 1 + dy) * (IMG + 2) + px + 1 + dx) * CP + ci]
+                   : bf16x8{};
+      }
+#pragma unroll
+      for (int nb = 0; nb < NBK; nb++) {
+        const int co = 16 * nb + (lane & 15);
+        bb[nb] = kv ? *(const bf16x8*)&sw[(tap * CO + co) * CP + ci] : bf16x8{};
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+        for (int nb = 0; nb < NBK; nb++)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bb[nb], acc[mb][nb], 0, 0, 0);
+    }
+    // epilogue: lane holds pixels px0 + 16 mb + 4 (lane / 16) + j of column co
+    const int y = y0 + r;
+#pragma unroll
+    for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+      for (int nb = 0; nb < NBK; nb++) {
+        const int co = 16 * nb + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int px = px0 + 16 * mb + 4 * (lane >> 4) + j;
+          const size_t o = (((size_t)b * IMG + y) * IMG + px) * CO + co;
+          float v = acc[mb][nb][j];
+          if (EPI == 0) {
+            v += bias[co];
+            ((__bf16*)out)[o] = to_bf16(v > 0.0f ? v : 0.0f);
+          } else if (EPI == 1) {
+            ((float*)out)[o] = v + bias[co];
+          } else {
+            ((__bf16*)out)[o] = to_bf16(from_bf16(mask_src[o]) > 0.0f ? v : 0.0f);
+          }
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// dW[tap][co][ci] = sum_p dz[p][co] x[p + off(tap)][ci], db[co] = sum_p dz[p][co]
+// over the image rows g, g + gridDim.x, ... of workgroup g; one partial per
+// workgroup (part[g][9][CO][CI], part_b[g][CO]), summed in a fixed order by
+// k_reduce_parts.
+template <int CI, int CO>
+__global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
+                                              float* __restrict__ part, float* __restrict__ part_b,
+                                              int n_rows) {
+  constexpr int PP = IMG + 8;                       // padded pixel stride
+  constexpr int TILES = NTAP * (CO / 16) * (CI / 16);
+  constexpr int TPW = (TILES + 3) / 4;              // tiles per wave
+  __shared__ __attribute__((aligned(16))) __bf16 sdz[CO * PP];          // [co][px]
+  __shared__ __attribute__((aligned(16))) __bf16 sxs[NTAP * CI * PP];  // [dx][dy][ci][px]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  f32x4 acc[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; j++) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float db = 0.0f;
+  for (int row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const int b = row / IMG, y = row - b * IMG;
+    __syncthreads();
+    // dz row, transposed to [co][px]
+    for (int i = tid; i < IMG * CO; i += NB) {
+      const int co = i % CO, px = i / CO;
+      sdz[co * PP + px] = dz[(((size_t)b * IMG + y) * IMG + px) * CO + co];
+    }
+    // x rows y-1 .. y+1, each shifted by dx, transposed to [ci][px]
+    for (int i = tid; i < 3 * (IMG + 2) * CI; i += NB) {
+      const int ci = i % CI, q = i / CI;
+      const int xx = q % (IMG + 2) - 1, dyi = q / (IMG + 2), yy = y + dyi - 1;
+      __bf16 v = to_bf16(0.0f);
+      if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
+        v = x[(((size_t)b * IMG + yy) * IMG + xx) * CI + ci];
+      // element xx feeds output pixel px = xx - dx for dx in {-1, 0, 1}; every
+      // (dx, dy, ci, px) slot has exactly one source xx = px + dx in -1 .. 64
+#pragma unroll
+      for (int dxi = 0; dxi < 3; dxi++) {
+        const int px = xx - (dxi - 1);
+        if (px >= 0 && px < IMG) sxs[((dxi * 3 + dyi) * CI + ci) * PP + px] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < CO) {
+      float s = 0.0f;
+      for (int px = 0; px < IMG; px++) s += from_bf16(sdz[tid * PP + px]);
+      db += s;
+    }
+#pragma unroll
+    for (int j = 0; j < TPW; j++) {
+      const int t = wave + 4 * j;
+      if (t >= TILES) break;
+      const int tap = t / ((CO / 16) * (CI / 16));
+      const int rem = t - tap * (CO / 16) * (CI / 16);
+      const int mb = rem / (CI / 16), nb = rem - mb * (CI / 16);
+      const int dyi = tap / 3, dxi = tap % 3;
+#pragma unroll
+      for (int kc = 0; kc < IMG / 32; kc++) {
+        const int p0 = 32 * kc + 8 * (lane >> 4);
+        const bf16x8 a = *(const bf16x8*)&sdz[(16 * mb + (lane & 15)) * PP + p0];
+        const bf16x8 bv = *(const bf16x8*)&sxs[((dxi * 3 + dyi) * CI + 16 * nb + (lane & 15)) * PP + p0];
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[j], 0, 0, 0);
+      }
+    }
+  }
+  float* pg = part + (size_t)blockIdx.x * NTAP * CO * CI;
+#pragma unroll
+  for (int j = 0; j < TPW; j++) {
+    const int t = wave + 4 * j;
+    if (t >= TILES) break;
+    const int tap = t / ((CO / 16) * (CI / 16));
+    const int rem = t - tap * (CO / 16) * (CI / 16);
+    const int mb = rem / (CI / 16), nb = rem - mb * (CI / 16);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int co = 16 * mb + 4 * (lane >> 4) + i, ci = 16 * nb + (lane & 15);
+      pg[((size_t)tap * CO + co) * CI + ci] = acc[j][i];
+    }
+  }
+  if (tid < CO) part_b[(size_t)blockIdx.x * CO + tid] = db;
+}
+
+// out[i] = sum_g part[g][i] in increasing g (fixed order), i < n
+__global__ void k_reduce_parts(const float* __restrict__ part, int n_parts, int n,
+                               float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int g = 0; g < n_parts; g++) s += part[(size_t)g * n + i];
+  out[i] = s;
+}
+
+// ---------------------------------------------------------------- loss
+// e = (pred - truth) / s with pred = base + s r (channels 0..2 of the fp32
+// last-layer output r [B][64][64][16]): the error in units of the sample's
+// coarse RMS.  Per-workgroup partial of sum e^2 (double) and
+// dy = dL/dr = 2 e / count as bf16 [B][64][64][16] (channels 3..15 zero).
+__global__ __launch_bounds__(NB) void k_loss(const float* __restrict__ r, const float* __restrict__ base,
+                                             const float* __restrict__ scale,
+                                             const float* __restrict__ truth, int n_px,
+                                             double inv_count, __bf16* __restrict__ dy,
+                                             double* __restrict__ part) {
+  __shared__ double red[NB];
+  double acc = 0.0;
+  for (int p = blockIdx.x * NB + threadIdx.x; p < n_px; p += gridDim.x * NB) {
+    const float s = scale[p / (IMG * IMG)];
+    __bf16* d = dy + (size_t)p * COUT;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const float pred = base[(size_t)p * 3 + c] + s * r[(size_t)p * COUT + c];
+      const float e = (pred - truth[(size_t)p * 3 + c]) / s;
+      acc += (double)e * (double)e;
+      d[c] = to_bf16((float)(2.0 * inv_count) * e);
+    }
+#pragma unroll
+    for (int c = 3; c < COUT; c++) d[c] = to_bf16(0.0f);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = NB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// u = base + s r for channels 0..2: out [B][64][64][3]
+__global__ void k_combine(const float* __restrict__ r, const float* __restrict__ base,
+                          const float* __restrict__ scale, int n_px, float* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_px) return;
+  const float s = scale[p / (IMG * IMG)];
+#pragma unroll
+  for (int c = 0; c < 3; c++) out[(size_t)p * 3 + c] = base[(size_t)p * 3 + c] + s * r[(size_t)p * COUT + c];
+}
+
+// ---------------------------------------------------------------- parameters
+// Adam (Kingma and Ba) on the FP32 master parameters, bias-corrected with
+// step t: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 forward weights [tap][co][ci] and backward-data weights
+// wt[tap][ci][co] = w[8 - tap][co][ci] from the FP32 master array
+__global__ void k_prep_weights(const float* __restrict__ w, int co_n, int ci_n,
+                               __bf16* __restrict__ wf, __bf16* __restrict__ wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NTAP * co_n * ci_n) return;
+  const int tap = i / (co_n * ci_n), rem = i - tap * co_n * ci_n;
+  const int co = rem / ci_n, ci = rem - co * ci_n;
+  const __bf16 h = to_bf16(w[i]);
+  wf[i] = h;
+  wt[((size_t)(NTAP - 1 - tap) * ci_n + ci) * co_n + co] = h;
+}
+
+}  // namespace lbnet
+
+namespace lbnet {
+
+// network inputs of one window k of a box's sampled face history
+// samples [ns][6][R][R][3]: sample b = j * 6 + f (step t_k + j, face f) gets
+// coarse[b][tau][c][v][u] = samples[clamp(k - 1 + tau)][f][v][u][c] and
+// theta[b] = j / dt
+__global__ void k_gather_window(const float* __restrict__ samples, int ns, int R, int k, int dt,
+                                float* __restrict__ coarse, float* __restrict__ theta) {
+  const int b = blockIdx.x;
+  const int j = b / 6, f = b - 6 * j;
+  if (threadIdx.x == 0) theta[b] = (float)j / (float)dt;
+  const int n = 12 * R * R;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int tau = i / (3 * R * R), rem = i - tau * 3 * R * R;
+    const int c = rem / (R * R), vu = rem - c * R * R;
+    int ks = k - 1 + tau;
+    ks = ks < 0 ? 0 : (ks > ns - 1 ? ns - 1 : ks);
+    coarse[(size_t)b * n + i] = samples[(((size_t)ks * 6 + f) * R * R + vu) * 3 + c];
+  }
+}
+
+}  // namespace lbnet

@@ -27,6 +27,10 @@ What it produces (all FP64 numpy arrays):
 * ``chain_init``     -- a bead-spring chain as a random walk of unit bonds,
                         shifted so its centre of mass sits on the anchor.
 * ``box_sizes``, ``anchors`` -- batch and multi-chain layouts.
+* ``upsampler_samples`` -- training / evaluation samples of the learned
+                        boundary upsampler: coarse face samples every dt
+                        steps and the dense per-step face field they should
+                        be mapped to, both from the KS field.
 
 Seeds follow ``np.random.SeedSequence(entropy=0x08094958,
 spawn_key=(config_idx, stream_idx))`` with streams 0 = OU / KS modes,
@@ -332,3 +336,57 @@ def ks_box_inputs(config_idx: int, box_idx: int, n: int, tau: float, n_steps: in
     u0 = initial_field(ks, tr, (n, n, n), units, 0)
     faces = face_samples(ks, tr, (n, n, n), units, res, steps)
     return units, u0, faces
+
+
+def upsampler_samples(config_idx: int, traj_ids, n: int = 64, tau: float = 0.6, R: int = 8,
+                      dt: int = 20, windows=(0, 1), phases=(0, 5, 10, 15), width_eta: float = 2.0,
+                      n_modes: int = 200):
+    """Samples (face, window k, phase j) of KS tracer trajectories for the upsampler.
+
+    Trajectory ``i`` draws its KS modes from stream 0 and its tracer start from
+    stream 1, both spawned per trajectory.  For every listed window k and phase
+    j and every face f it returns
+
+      coarse [4][3][R][R]   samples S_{k-1..k+2} of face f on the R x R
+                            corner-aligned grid (times clamped at 0),
+                            indexed [time][component][v][u]
+      theta                 j / dt
+      truth  [n][n][3]      the face field at step k dt + j on every face node
+
+    as float32 arrays (coarse [S][4][3][R][R], theta [S], truth [S][n][n][3]),
+    samples ordered (trajectory, window, phase, face).
+    """
+    windows = [int(k) for k in windows]
+    phases = [int(j) for j in phases]
+    co_list, th_list, tr_list = [], [], []
+    for i in traj_ids:
+        ks = KSField(np.random.Generator(np.random.PCG64(
+            np.random.SeedSequence(entropy=ENTROPY, spawn_key=(config_idx, 0, int(i))))), n_modes=n_modes)
+        g1 = np.random.Generator(np.random.PCG64(
+            np.random.SeedSequence(entropy=ENTROPY, spawn_key=(config_idx, 1, int(i)))))
+        x0 = g1.uniform(-50.0, 50.0, size=3)
+        units = UnitMap(n, tau, width_eta)
+        k_hi = max(windows) + 2
+        c_steps = np.arange(k_hi + 1) * dt
+        d_steps = np.array([k * dt + j for k in windows for j in phases])
+        all_steps = np.unique(np.concatenate([c_steps, d_steps]))
+        tr = tracer_path(ks, x0, all_steps / units.tau_eta)
+
+        def sub(steps):
+            idx = np.searchsorted(all_steps, steps)
+            return Tracer(tr.times[idx], tr.pos[idx], tr.vel[idx])
+        coarse = face_samples(ks, sub(c_steps), (n, n, n), units, R, c_steps)      # [K][6][R][R][3]
+        dense = face_samples(ks, sub(d_steps), (n, n, n), units, n, d_steps)       # [D][6][n][n][3]
+        d = 0
+        for k in windows:
+            ks_idx = [min(max(k - 1 + tau_i, 0), k_hi) for tau_i in range(4)]
+            cw = coarse[ks_idx].transpose(1, 0, 4, 2, 3)                           # [6][4][3][R][R]
+            for j in phases:
+                for f in range(6):
+                    co_list.append(cw[f])
+                    th_list.append(j / dt)
+                    tr_list.append(dense[d, f])
+                d += 1
+    return (np.asarray(co_list, dtype=np.float32), np.asarray(th_list, dtype=np.float32),
+            np.asarray(tr_list, dtype=np.float32))
+

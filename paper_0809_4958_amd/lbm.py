@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "LB_OK", -1: "LB_ERR_ARG", -2: "LB_ERR_OOM", -3: "LB_ERR_HIP"
                 -8: "LB_ERR_BUFSIZE"}
 BGK, MRT = 0, 1
 STORE_F64, STORE_F32, STORE_F16DEV = 0, 1, 2
-BC_AFFINE, BC_SAMPLED = 0, 1
+BC_AFFINE, BC_SAMPLED, BC_LEARNED = 0, 1, 2
 F_RHO, F_U, F_POP, F_BEAD_POS, F_BEAD_VEL, F_MASS_MOM, F_STEP, F_POP_DEV, F_BEAD_REL = range(9)
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
@@ -199,6 +199,18 @@ class Context:
         return self._check(self._lib.lb_set_initial(self._h, box, _p(u)))
 
     def set_boundary(self, box, mode, data, t0=0, dt=1, res=0):
+        if mode == BC_LEARNED:
+            # a float32 CUDA tensor [n_slots][6][res][res][3], read in place by
+            # the library: the caller keeps it alive and refills it
+            import torch
+            if not (isinstance(data, torch.Tensor) and data.is_cuda and data.dtype == torch.float32
+                    and data.is_contiguous() and data.dim() == 5):
+                raise TypeError("a learned boundary ring is a contiguous float32 CUDA tensor "
+                                "[n_slots][6][res][res][3]")
+            bc = LbBoundary(mode, t0, dt, data.shape[0], res or data.shape[2],
+                            ct.c_void_p(data.data_ptr()), 0)
+            self._ring = data
+            return self._check(self._lib.lb_set_boundary(self._h, box, ct.byref(bc)))
         f64 = mode == BC_AFFINE or np.asarray(data).dtype == np.float64
         data = np.ascontiguousarray(data, dtype=np.float64 if f64 else np.float32)
         bc = LbBoundary(mode, t0, dt, data.shape[0], res, _p(data), 1 if f64 else 0)
