@@ -102,6 +102,7 @@ struct BoxDesc {
   double interior;      // number of interior nodes
   int fast;             // non-periodic and 19*nn*sizeof(T) < 2^32 (32-bit offsets)
   int vec;              // interior rows handled as lane vectors (ITEM_ROWS) incl. the x-face nodes
+  int ylog;             // log2 of the rows interleaved per population row (see aidx)
 };
 
 struct Item {
@@ -436,10 +437,16 @@ __device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rh
   mrt_backward<R, GZ>(M, d);
 }
 
-// Arena layout: rows of 19 populations, pop[z][y][i][x] (x fastest).  The
-// populations a node pulls lie in at most nine neighbouring row blocks.
+// Arena layout: pop[z][y / Y][i][y % Y][x] (x fastest), Y = 2^ylog.  The
+// 19 population rows of a block of Y consecutive y lines are adjacent, and
+// each population's Y rows are contiguous, so that a population row of a
+// block spans whole 128-byte lines when nx is short (Y = 1 gives
+// pop[z][y][i][x]).  The populations a node pulls lie in at most nine
+// neighbouring lines (y - c_y, z - c_z).
 __host__ __device__ __forceinline__ int64_t aidx(const BoxDesc& b, int i, int x, int y, int z) {
-  return ((int64_t)(z * b.ny + y) * Q + i) * b.nx + x;
+  const int Y = 1 << b.ylog;
+  return (((int64_t)z * (b.ny >> b.ylog) + (y >> b.ylog)) * Q + i) * ((int64_t)b.nx << b.ylog) +
+         (int64_t)(y & (Y - 1)) * b.nx + x;
 }
 
 // Neighbour coordinate with wrap on periodic axes.

@@ -611,8 +611,10 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
   const int nx = b.nx, ny = b.ny, nyi = b.ny - 2;
   const int L = nx / V;                            // lane groups per row
   const int nxb = nx * SB;                         // bytes per population row
-  const int rsb = Q * nxb;                         // bytes per row block (19 rows)
-  const long long psb = (long long)rsb * ny;       // bytes per plane
+  const int yl = b.ylog, ym = (1 << b.ylog) - 1;
+  const int pib = nxb << yl;                       // bytes per population in a block of Y rows
+  const int bkb = Q * pib;                         // bytes per block of Y rows
+  const long long psb = (long long)Q * nxb * ny;   // bytes per plane
   const long long box_bytes = psb * b.nz;
   const int g_last = L * nyi * (b.nz - 2) - 1;     // last group of the box
   const int q_end = it.x0 + it.ex;
@@ -620,9 +622,11 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
   const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
   const int lane = (int)(threadIdx.x & 63);
   const unsigned lane_l = (unsigned)(lane - 1) & 63u, lane_r = (unsigned)(lane + 1) & 63u;
-  // population i of the node at lane offset v sits at v + soff(i) from the
-  // iteration's base plane (one plane below its first row): offsets >= 0
+  // population i of the node sits at vo[c_y] + soff(i) from the iteration's
+  // base plane (one plane below its first row): offsets >= 0; vo holds the
+  // lane's line offsets for y - c_y, c_y = 1, 0, -1
   const int ps = (int)psb;
+  auto ybytes = [&](int yy) { return (yy >> yl) * bkb + (yy & ym) * nxb; };
 #pragma unroll 1
   for (int qb = it.x0; qb < q_end; qb += BS) {
     const int zf = 1 + (qb / L) / nyi;             // first plane of this iteration
@@ -639,12 +643,15 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
     const int zi = row / nyi;
     const int y = 1 + row - zi * nyi, z = 1 + zi;
     const int x0 = c * V;
-    const unsigned voff = (unsigned)((z - zf) * ps + (y - 1) * rsb + x0 * SB);
+    const int zrel = (z - zf) * ps + x0 * SB;
+    const unsigned vo[3] = {(unsigned)(zrel + ybytes(y - 1)), (unsigned)(zrel + ybytes(y)),
+                            (unsigned)(zrel + ybytes(y + 1))};   // indexed 1 - c_y
+    const unsigned voff = vo[1];
     unsigned raw[Q][W];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      const int so = i * nxb + (PRE ? ps + rsb : (1 - CZ[i]) * ps + (1 - CY[i]) * rsb);
-      vload<W>(rsrc, voff, so, raw[i]);
+      const int so = i * pib + (PRE ? ps : (1 - CZ[i]) * ps);
+      vload<W>(rsrc, PRE ? voff : vo[1 - CY[i]], so, raw[i]);
     }
     // neighbour elements of the populations shifted in x
     unsigned left[Q], right[Q];
@@ -663,22 +670,24 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           if (CX[i] != 1) continue;
-          const int so = i * nxb + (1 - CZ[i]) * ps + (1 - CY[i]) * rsb - SB;
+          const int so = i * pib + (1 - CZ[i]) * ps - SB;
+          const int vl = (int)vo[1 - CY[i]];
           if constexpr (SB == 2)
-            left[i] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rsrc, (int)voff, so, 0) << 16;
+            left[i] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rsrc, vl, so, 0) << 16;
           else
-            left[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, so, 0);
+            left[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, vl, so, 0);
         }
       }
       if (lane == 63 && c != L - 1) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           if (CX[i] != -1) continue;
-          const int so = i * nxb + (1 - CZ[i]) * ps + (1 - CY[i]) * rsb + V * SB;
+          const int so = i * pib + (1 - CZ[i]) * ps + V * SB;
+          const int vr = (int)vo[1 - CY[i]];
           if constexpr (SB == 2)
-            right[i] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rsrc, (int)voff, so, 0);
+            right[i] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rsrc, vr, so, 0);
           else
-            right[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, so, 0);
+            right[i] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, vr, so, 0);
         }
       }
     }
@@ -755,7 +764,7 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
     }
     if (act) {
 #pragma unroll
-      for (int i = 0; i < Q; i++) vstore<W>(rdst, voff, i * nxb + ps + rsb, out[i]);
+      for (int i = 0; i < Q; i++) vstore<W>(rdst, voff, i * pib + ps, out[i]);
     }
   }
 }
@@ -763,10 +772,10 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
 // Face rows of a row box: the rows y = 0, y = ny-1 (1 <= z <= nz-2) and all
 // rows of the planes z = 0, z = nz-1, cut into the same lane groups, numbered
 // plane z = 0 (rows y = 0..ny-1), plane z = nz-1, then for each interior z its
-// rows y = 0 and y = ny-1.  Every node stores the full boundary equilibrium at
-// t_n with the face of lowest index it lies on (-x, +x, -y, +y, -z, +z), one
-// W-word vector per population; only the populations pointing into the
-// interior are ever read.
+// rows y = 0 and y = ny-1.  Every node takes the boundary equilibrium at t_n
+// with the face of lowest index it lies on (-x, +x, -y, +y, -z, +z); a row
+// stores, one W-word vector each, the populations whose target line
+// (y + c_y, z + c_z) is an interior line -- the only ones ever read.
 template <int S, int W, bool CHECK, int BS>
 __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
                                           typename Store<S>::T* dst, long long step,
@@ -777,7 +786,9 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
   constexpr int SB = (int)sizeof(typename St::T);
   const int nx = b.nx, ny = b.ny, nz = b.nz;
   const int L = nx / V;
-  const long long nxb = (long long)nx * SB, rsb = Q * nxb, psb = rsb * ny;
+  const long long nxb = (long long)nx * SB, psb = Q * nxb * ny;
+  const int yl = b.ylog, ym = (1 << b.ylog) - 1;
+  const long long pib = nxb << yl, bkb = Q * pib;
   const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
   const int q_end = it.x0 + it.ex;
 #pragma unroll 1
@@ -814,10 +825,14 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
         vput<S, W>(out[i], k, St::enc(eq[i], ke));
       }
     }
-    char* row = (char*)dst + (long long)z * psb + (long long)y * rsb + (long long)x0 * SB;
+    char* row = (char*)dst + (long long)z * psb + (long long)(y >> yl) * bkb + (long long)(y & ym) * nxb +
+                (long long)x0 * SB;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      char* p = row + i * nxb;
+      // only populations that stream into an interior line are ever read
+      const int ty = y + CY[i], tz = z + CZ[i];
+      if (ty < 1 || ty > ny - 2 || tz < 1 || tz > nz - 2) continue;
+      char* p = row + i * pib;
       if constexpr (W == 1) *(unsigned*)p = out[i][0];
       else if constexpr (W == 2) *(uint2*)p = make_uint2(out[i][0], out[i][1]);
       else *(uint4*)p = make_uint4(out[i][0], out[i][1], out[i][2], out[i][3]);

@@ -51,7 +51,8 @@ struct BoxHost {
   int rect_start[MAX_RECT][3] = {};
   int rect_len[MAX_RECT][3] = {};
   int nbnd = 0;
-  bool vec = false;  // interior rows as 16-byte vectors (ITEM_ROWS), x-face nodes included
+  bool vec = false;  // interior rows as lane vectors (ITEM_ROWS), x-face nodes included
+  int ylog = 0;      // log2 of the y lines interleaved per population row
 };
 
 struct ChainHost {
@@ -488,6 +489,7 @@ lb_status upload_boxes(lb_ctx* ctx) {
       }
     }
     d.vec = b.vec ? 1 : 0;
+    d.ylog = b.ylog;
     for (int c = 0; c < 3; c++) {
       d.enc[c] = (float)(s2 / WD[c]);
       d.dec[c] = (float)(WD[c] / s2);
@@ -835,6 +837,17 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
       const double span = (WG / ((double)(n3[0] / V) * (n3[1] - 2)) + 4.0) * plane;
       b.vec = cfg->storage != LB_STORE_F64 && pm == 0u && n3[0] % V == 0 && n3[0] >= 2 * V &&
               groups < 2.0e9 && span < 2147483648.0 && !getenv("LBM_NO_VEC");
+      // interleave Y = 2^ylog lines per population row so that a row of a
+      // block spans whole 128-byte lines (row boxes only)
+      b.ylog = 0;
+      if (b.vec) {
+        const int rowb = n3[0] * (int)store_bytes(cfg->storage);
+        for (int yl = 0; yl <= 2; yl++)
+          if ((rowb << yl) % 128 == 0 && n3[1] % (1 << yl) == 0) {
+            b.ylog = yl;
+            break;
+          }
+      }
     }
     face_tables(b);
     default_tile(b);
