@@ -47,7 +47,8 @@ def parse():
                    help="skip the plain-FP32 single-box and oracle legs")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-mib", type=int, default=1024, help="copy-probe size (0: skip)")
-    p.add_argument("--tune", action="store_true", help="run the autotuner before timing")
+    p.add_argument("--no-tune", action="store_true",
+                   help="skip the autotuner (default: tune item sizes and grid before timing)")
     return p.parse_args()
 
 
@@ -153,8 +154,10 @@ def main():
     copy_gbs = lbm.copy_probe(args.copy_mib << 20, 20) if args.copy_mib > 0 else None
     ctx = make_ctx(lbm, boxes, storage, tau, reduce_every=100, stream=stream,
                    graph_steps=args.graph_steps)
-    if args.tune:
+    t_tune = time.time()
+    if not args.no_tune:
         ctx.autotune(3)
+    t_tune = time.time() - t_tune
     ctx.step(args.warmup)
     ctx.sync()
     torch.cuda.synchronize()
@@ -189,6 +192,8 @@ def main():
             "interior_nodes": int(interior),
             "storage": args.storage,
             "graph_steps": args.graph_steps,
+            "autotuned": not args.no_tune,
+            "autotune_s": round(t_tune, 2),
             "launch": ctx.describe(),
         },
         "roofline": {

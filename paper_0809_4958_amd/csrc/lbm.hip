@@ -249,7 +249,9 @@ void default_tile(BoxHost& b) {
   b.ex = ix <= 128 ? ix : 64;
   b.ey = std::max(1, std::min(b.iy, 512 / std::max(1, b.ex)));
   while (b.ex * b.ey > WG * MAX_SLOTS) b.ey--;
-  b.ez = std::min(b.iz, 16);
+  // tiles: planes per item; row boxes: workgroup iterations per item (short
+  // items keep the tail of a launch short)
+  b.ez = b.vec ? 4 : std::min(b.iz, 16);
 }
 
 std::string box_key(const lb_ctx* ctx, const BoxHost& b) {

@@ -150,11 +150,16 @@ class Context:
             import torch
             dev = torch.cuda.current_device()
 
+            alloc, delete = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
+
             def _alloc(n, user):
-                return torch.cuda.caching_allocator_alloc(int(n), dev)
+                return alloc(int(n), dev)
 
             def _free(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    delete(ptr)
+                except Exception:  # interpreter shutdown: the process frees everything
+                    pass
             self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
             cfg.dev_alloc, cfg.dev_free = self._cb
         h = ct.c_void_p()

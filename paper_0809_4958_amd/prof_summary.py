@@ -13,7 +13,8 @@ Two summaries are written under ``profiles/``:
 
 Usage::
 
-    python -m paper_0809_4958_amd.prof_summary kernels STATS_CSV OUT --command "..."
+    python -m paper_0809_4958_amd.prof_summary kernels STATS_CSV OUT --command "..." \\
+        [--trace TRACE_CSV --tail N]
     python -m paper_0809_4958_amd.prof_summary traffic FETCH_CSV WRITE_CSV OUT \\
         --copy-bytes N --command-fetch "..." --command-write "..."
 """
@@ -48,10 +49,26 @@ def short_name(name: str) -> str:
     return name[:60]
 
 
-def kernels(stats_csv: str, out: str, command: str) -> None:
+def timed_average(trace_csv: str, kernel: str, tail: int):
+    """Average duration (ms) of the last `tail` dispatches of `kernel` in a
+    kernel-trace CSV, and how many dispatches it had in all."""
+    durs = []
+    for r in csv.DictReader(open(trace_csv)):
+        if short_name(r.get("Kernel_Name", "")).startswith(kernel):
+            durs.append((int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    durs.sort()
+    last = [d for _, d in durs[-tail:]]
+    return sum(last) / len(last) / 1e6, len(durs)
+
+
+def kernels(stats_csv: str, out: str, command: str, trace_csv: str | None = None, tail: int = 0) -> None:
     rows = list(csv.DictReader(open(stats_csv)))
-    lines = ["# rocprofv3 kernel-trace statistics", f"# command: {command}", "",
-             f"{'kernel':48s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'share_%':>8s}"]
+    lines = ["# rocprofv3 kernel-trace statistics", f"# command: {command}", ""]
+    if trace_csv and tail > 0:
+        avg, n = timed_average(trace_csv, "k_lb", tail)
+        lines += [f"k_lb average over the last {tail} dispatches (the timed steps): {avg:.4f} ms "
+                  f"({n} dispatches in all, the others are warm-up and autotuner trials)", ""]
+    lines += [f"{'kernel':48s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'share_%':>8s}"]
     for r in rows:
         name = short_name(r.get("Name", r.get("KernelName", "")))
         calls = int(float(r.get("Calls", 0)))
@@ -123,6 +140,8 @@ def main():
     k.add_argument("stats_csv")
     k.add_argument("out")
     k.add_argument("--command", required=True)
+    k.add_argument("--trace", help="kernel_trace.csv of the same run")
+    k.add_argument("--tail", type=int, default=0, help="timed k_lb dispatches at the end of the run")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -136,7 +155,7 @@ def main():
                    help="algorithmic bytes per k_lb launch (bench.py roofline)")
     a = p.parse_args()
     if a.what == "kernels":
-        kernels(a.stats_csv, a.out, a.command)
+        kernels(a.stats_csv, a.out, a.command, a.trace, a.tail)
     else:
         traffic(a.fetch_csv, a.write_csv, a.out, a.copy_bytes, a.command_fetch, a.command_write,
                 a.workload, a.storage, a.algorithmic)
