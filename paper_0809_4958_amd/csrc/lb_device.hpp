@@ -103,6 +103,7 @@ struct BoxDesc {
   int fast;             // non-periodic and 19*nn*sizeof(T) < 2^32 (32-bit offsets)
   int vec;              // interior rows handled as lane vectors (ITEM_ROWS) incl. the x-face nodes
   int ylog;             // log2 of the rows interleaved per population row (see aidx)
+  int vw;               // row boxes: 32-bit words per lane vector (2 or 3)
 };
 
 struct Item {

@@ -25,10 +25,9 @@ __global__ __launch_bounds__(WG) void k_finalize(LbArgs A) {
   if (check) {
     for (int bx = tid; bx < A.n_boxes; bx += WG) {
       double s[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int q = A.box_items_off[bx]; q < A.box_items_off[bx + 1]; q++) {
-        const int item = A.box_items[q];
+      for (int q = A.check_off[bx]; q < A.check_off[bx + 1]; q++) {
 #pragma unroll
-        for (int m = 0; m < 4; m++) s[m] += A.partials[4 * item + m];
+        for (int m = 0; m < 4; m++) s[m] += A.partials[4 * q + m];
       }
       const double M = A.rho0 * A.boxes[bx].interior + s[0];
       double* mm = A.mass_mom + 5 * bx;

@@ -9,10 +9,10 @@
 //             streaming, gather the spread force from the records of the
 //             chains whose box overlaps the tile (fixed bead order, no
 //             atomics), collide and store; boundary items store the boundary
-//             equilibrium populations that point into the interior.  On check
-//             steps every item writes FP64 partial sums of mass and momentum
-//             at t_{n+1}.
-//             The per-box sums are formed by k_finalize (lb_io_kernels.hpp).
+//             equilibrium populations that point into the interior.
+//   k_check   on check steps: FP64 partial sums of the interior's mass and
+//             momentum at t_{n+1} from the arena k_lb wrote; k_finalize
+//             (lb_io_kernels.hpp) adds them per box.
 #pragma once
 #include "lb_device.hpp"
 
@@ -21,19 +21,10 @@ namespace lbdev {
 constexpr int WG = 256;
 constexpr int MAX_SLOTS = 4;   // tile plane positions per thread (ex*ey <= 1024)
 constexpr int MAX_BOX_CHAINS = 64;
-// 32-bit words per lane in row items (2: 8-byte vectors, 4 FP16 or 2 FP32
-// nodes per lane) and the minimum resident waves per SIMD of the FP32/FP16
-// step kernel; both are build-time choices
-#ifndef LB_ROW_WORDS_F16
-#define LB_ROW_WORDS_F16 2
-#endif
-#ifndef LB_ROW_WORDS_F32
-#define LB_ROW_WORDS_F32 2
-#endif
+// minimum resident waves per SIMD of the FP32/FP16 step kernel (build-time)
 #ifndef LB_MIN_WAVES
 #define LB_MIN_WAVES 2
 #endif
-__host__ __device__ constexpr int row_words(int s) { return s == 2 ? LB_ROW_WORDS_F16 : LB_ROW_WORDS_F32; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -365,9 +356,9 @@ struct LbArgs {
   const void* rec_dp;
   const int* bbox;
   DevState* st;
-  double* partials;        // [n_items][4]
-  const int* box_items;    // CSR lists of item indices per box
-  const int* box_items_off;
+  double* partials;        // [n_check][4] mass/momentum partials of k_check
+  const int4* check_items; // k_check workgroups: box, first plane, end plane
+  const int* check_off;    // [n_boxes + 1] first k_check workgroup of each box
   double* mass_mom;        // [n_boxes][5]
   int n_boxes;
   int reduce_every;
@@ -419,39 +410,16 @@ __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
   }
 }
 
-// Contribution of the stored populations of node (x, y, z) to the interior's
-// mass and momentum at t_{n+1} (those that stream to an interior node).
-template <int S, bool PER>
-__device__ __forceinline__ void check_acc(const BoxDesc& b, int x, int y, int z,
-                                          const typename Store<S>::R d[Q], double acc[4]) {
-  using St = Store<S>;
-#pragma unroll
-  for (int i = 0; i < Q; i++) {
-    int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
-    if (PER) {
-      if (b.pmask & 1) tx = wrapc(tx, b.nx);
-      if (b.pmask & 2) ty = wrapc(ty, b.ny);
-      if (b.pmask & 4) tz = wrapc(tz, b.nz);
-    }
-    if (!is_interior(b, tx, ty, tz)) continue;
-    const double v = (double)St::dec(St::enc(d[i], b.enc[WCLS[i]]), b.dec[WCLS[i]]);
-    acc[0] += v;
-    if (CX[i]) acc[1] += CX[i] * v;
-    if (CY[i]) acc[2] += CY[i] * v;
-    if (CZ[i]) acc[3] += CZ[i] * v;
-  }
-}
-
 // Interior tile of a non-periodic box whose population groups (0..9 and
 // 10..18) each span less than 4 GiB: every load is one 32-bit offset add on
 // a per-thread node offset plus a scalar (uniform) group base.
-template <int S, int COLL, bool CHECK, bool GATHER, int BS>
+template <int S, int COLL, bool GATHER, int BS>
 __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, const Item& it,
                                           const typename Store<S>::T* src,
                                           typename Store<S>::T* dst, bool pre,
                                           unsigned long long cmask, typename Store<S>::R rho0,
                                           typename Store<S>::R omega, typename Store<S>::R omb,
-                                          typename Store<S>::R omg, double acc[4]) {
+                                          typename Store<S>::R omg) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -493,7 +461,6 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
         const float k = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
         *(T*)(d0 + (voff + doff[i])) = St::enc(d[i], k);
       }
-      if (CHECK) check_acc<S, false>(b, x, y, z, d, acc);
     }
   }
 }
@@ -534,8 +501,13 @@ __device__ __forceinline__ void vload(__amdgpu_buffer_rsrc_t r, unsigned voff, i
     const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0);
     w[0] = v[0];
     w[1] = v[1];
+  } else if constexpr (W == 3) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)voff, soff, 0);
+    w[0] = v[0];
+    w[1] = v[1];
+    w[2] = v[2];
   } else {
-    static_assert(W == 4, "row vectors are 1, 2 or 4 words");
+    static_assert(W == 4, "row vectors are 1 to 4 words");
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, 0);
     w[0] = v[0];
     w[1] = v[1];
@@ -554,6 +526,12 @@ __device__ __forceinline__ void vstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
     v[0] = w[0];
     v[1] = w[1];
     __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, soff, 0);
+  } else if constexpr (W == 3) {
+    __attribute__((ext_vector_type(3))) unsigned v;
+    v[0] = w[0];
+    v[1] = w[1];
+    v[2] = w[2];
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, (int)voff, soff, 0);
   } else {
     __attribute__((ext_vector_type(4))) unsigned v;
     v[0] = w[0];
@@ -596,13 +574,13 @@ __device__ __forceinline__ void vput(unsigned (&w)[W], int e, typename Store<S>:
   }
 }
 
-template <int S, int W, int COLL, bool CHECK, bool GATHER, bool PRE, int BS>
+template <int S, int W, int COLL, bool GATHER, bool PRE, int BS>
 __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, const Item& it,
                                           const typename Store<S>::T* src,
                                           typename Store<S>::T* dst, long long step,
                                           unsigned long long cmask, typename Store<S>::R rho0,
                                           typename Store<S>::R omega, typename Store<S>::R omb,
-                                          typename Store<S>::R omg, double acc[4]) {
+                                          typename Store<S>::R omg) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -737,7 +715,6 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
       const int x = x0 + k;
       collide_any<R, COLL>(d, GATHER ? g[k][0] : (R)0, GATHER ? g[k][1] : (R)0,
                            GATHER ? g[k][2] : (R)0, rho0, omega, omb, omg);
-      if (CHECK && act && x >= 1 && x <= nx - 2) check_acc<S, false>(b, x, y, z, d, acc);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
@@ -754,7 +731,6 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
         boundary_velocity<R>(b, side, qn, step, u);
         R eq[Q];
         eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
-        if (CHECK) check_acc<S, false>(b, qn[0], y, z, eq, acc);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
@@ -776,10 +752,10 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
 // with the face of lowest index it lies on (-x, +x, -y, +y, -z, +z); a row
 // stores, one W-word vector each, the populations whose target line
 // (y + c_y, z + c_z) is an interior line -- the only ones ever read.
-template <int S, int W, bool CHECK, int BS>
+template <int S, int W, int BS>
 __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
                                           typename Store<S>::T* dst, long long step,
-                                          typename Store<S>::R rho0, double acc[4]) {
+                                          typename Store<S>::R rho0) {
   using St = Store<S>;
   using R = typename St::R;
   constexpr int V = RowVec<S, W>::V;
@@ -818,7 +794,6 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
       boundary_velocity<R>(b, f, qn, step, u);
       R eq[Q];
       eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
-      if (CHECK) check_acc<S, false>(b, x, y, z, eq, acc);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
@@ -835,6 +810,7 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
       char* p = row + i * pib;
       if constexpr (W == 1) *(unsigned*)p = out[i][0];
       else if constexpr (W == 2) *(uint2*)p = make_uint2(out[i][0], out[i][1]);
+      else if constexpr (W == 3) *(uint3*)p = make_uint3(out[i][0], out[i][1], out[i][2]);
       else *(uint4*)p = make_uint4(out[i][0], out[i][1], out[i][2], out[i][3]);
     }
   }
@@ -844,10 +820,10 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
 template <int S, int COLL, bool PER, int BS>
 __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, const Item& it,
                                              const typename Store<S>::T* src,
-                                             typename Store<S>::T* dst, bool pre, bool check,
+                                             typename Store<S>::T* dst, bool pre,
                                              unsigned long long cmask, typename Store<S>::R rho0,
                                              typename Store<S>::R omega, typename Store<S>::R omb,
-                                             typename Store<S>::R omg, double acc[4]) {
+                                             typename Store<S>::R omg) {
   using St = Store<S>;
   using R = typename St::R;
   const int plane = it.ex * it.ey;
@@ -864,7 +840,6 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
       collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
 #pragma unroll
       for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
-      if (check) check_acc<S, PER>(b, x, y, z, d, acc);
     }
   }
 }
@@ -876,7 +851,6 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
-  __shared__ double sred[4][BS / 64];
 
   const int tid = threadIdx.x;
   const bool skip =
@@ -884,7 +858,6 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A
   if (skip) return;  // uniform: the latch is set before this launch or not at all
   const long long step = A.st->step;
   const int par = (int)(step & 1);
-  const bool check = A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0;
   const R rho0 = (R)A.rho0, omega = (R)A.omega, omb = (R)A.om_bulk, omg = (R)A.om_ghost;
   const T* __restrict__ srcA = (const T*)(par ? A.a1 : A.a0);
   T* __restrict__ dstA = (T*)(par ? A.a0 : A.a1);
@@ -897,8 +870,6 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A
     const BoxDesc& b = A.boxes[it.box];
     const T* __restrict__ src = srcA + b.off;
     T* __restrict__ dst = dstA + b.off;
-    const int64_t nn = b.nn;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 
     if (it.kind == ITEM_ROWS) {
       unsigned long long cmask = 0;
@@ -909,21 +880,26 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A
         if (ov) cmask |= 1ull << c;
       }
       if constexpr (S != 0 && !PER) {
-#define LB_ROWS(CH, GA, PR) \
-  tile_rows<S, row_words(S), COLL, CH, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg, acc)
+#define LB_ROWS(GA, PR)                                                                      \
+  do {                                                                                       \
+    if (b.vw == 3)                                                                           \
+      tile_rows<S, 3, COLL, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg); \
+    else                                                                                     \
+      tile_rows<S, 2, COLL, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg); \
+  } while (0)
         if (pre) {
-          if (cmask) { if (check) LB_ROWS(true, true, true); else LB_ROWS(false, true, true); }
-          else { if (check) LB_ROWS(true, false, true); else LB_ROWS(false, false, true); }
+          if (cmask) LB_ROWS(true, true);
+          else LB_ROWS(false, true);
         } else {
-          if (cmask) { if (check) LB_ROWS(true, true, false); else LB_ROWS(false, true, false); }
-          else { if (check) LB_ROWS(true, false, false); else LB_ROWS(false, false, false); }
+          if (cmask) LB_ROWS(true, false);
+          else LB_ROWS(false, false);
         }
 #undef LB_ROWS
       }
     } else if (it.kind == ITEM_FACE_ROWS) {
       if constexpr (S != 0 && !PER) {
-        if (check) face_rows<S, row_words(S), true, BS>(b, it, dst, step, rho0, acc);
-        else face_rows<S, row_words(S), false, BS>(b, it, dst, step, rho0, acc);
+        if (b.vw == 3) face_rows<S, 3, BS>(b, it, dst, step, rho0);
+        else face_rows<S, 2, BS>(b, it, dst, step, rho0);
       }
     } else if (it.kind == ITEM_TILE) {
       // chains whose stencil box overlaps this tile
@@ -935,15 +911,10 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A
         if (ov) cmask |= 1ull << c;
       }
       if (!PER && b.fast) {
-        if (cmask) {
-          if (check) tile_fast<S, COLL, true, true, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg, acc);
-          else tile_fast<S, COLL, false, true, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg, acc);
-        } else {
-          if (check) tile_fast<S, COLL, true, false, BS>(A, b, it, src, dst, pre, 0, rho0, omega, omb, omg, acc);
-          else tile_fast<S, COLL, false, false, BS>(A, b, it, src, dst, pre, 0, rho0, omega, omb, omg, acc);
-        }
+        if (cmask) tile_fast<S, COLL, true, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg);
+        else tile_fast<S, COLL, false, BS>(A, b, it, src, dst, pre, 0, rho0, omega, omb, omg);
       } else {
-        tile_generic<S, COLL, PER, BS>(A, b, it, src, dst, pre, check, cmask, rho0, omega, omb, omg, acc);
+        tile_generic<S, COLL, PER, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg);
       }
     } else {
       // boundary chunk: equilibrium at rho0 and u_b(t_n) for the populations
@@ -973,35 +944,67 @@ __global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A
             if (b.pmask & 4) tz = wrapc(tz, b.nz);
           }
           if (!is_interior(b, tx, ty, tz)) continue;
-          const T v = St::enc(eq[i], b.enc[WCLS[i]]);
-          dst[aidx(b, i, q[0], q[1], q[2])] = v;
-          if (check) {
-            const double dv = (double)St::dec(v, b.dec[WCLS[i]]);
-            acc[0] += dv;
-            if (CX[i]) acc[1] += CX[i] * dv;
-            if (CY[i]) acc[2] += CY[i] * dv;
-            if (CZ[i]) acc[3] += CZ[i] * dv;
-          }
+          dst[aidx(b, i, q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
         }
       }
     }
-    if (check) {
-      // fixed-order reduction: wave shuffle -> LDS -> one partial per item
+  }
+}
+
+// ----------------------------------------------------------- mass / momentum
+// On check steps ((n+1) % K == 0), after the fused step: the interior's mass
+// and momentum at t_{n+1}, i.e. every stored population of the arena just
+// written whose target node x + c_i is interior (FP64).  Workgroup w covers
+// the planes [cz0, cz1) of box cbox, one FP64 partial of each sum per
+// workgroup (wave shuffle -> LDS, fixed order); k_finalize adds the partials
+// of a box in workgroup order.  A separate pass, so the step itself is the
+// same arithmetic on every step.
+template <int S, bool PER>
+__global__ __launch_bounds__(WG) void k_check(LbArgs A) {
+  using St = Store<S>;
+  using T = typename St::T;
+  __shared__ double sred[4][WG / 64];
+  const int tid = threadIdx.x, w = blockIdx.x;
+  if (__hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE) return;
+  const long long step = A.st->step;
+  if (!(A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0)) return;
+  const int par = (int)(step & 1);
+  const int4 cw = A.check_items[w];  // box, first plane, end plane
+  const BoxDesc& b = A.boxes[cw.x];
+  const T* __restrict__ arena = (const T*)(par ? A.a0 : A.a1) + b.off;  // written by this step
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t plane = (int64_t)b.nx * b.ny;
+  for (int64_t p = tid; p < (int64_t)(cw.z - cw.y) * plane; p += WG) {
+    const int z = cw.y + (int)(p / plane);
+    const int rem = (int)(p - (p / plane) * plane);
+    const int y = rem / b.nx, x = rem - (rem / b.nx) * b.nx;
 #pragma unroll
-      for (int m = 0; m < 4; m++) {
-        const double v = wave_sum(acc[m]);
-        if ((tid & 63) == 0) sred[m][tid >> 6] = v;
+    for (int i = 0; i < Q; i++) {
+      int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+      if (PER) {
+        if (b.pmask & 1) tx = wrapc(tx, b.nx);
+        if (b.pmask & 2) ty = wrapc(ty, b.ny);
+        if (b.pmask & 4) tz = wrapc(tz, b.nz);
       }
-      __syncthreads();
-      if (tid < 4) {
-        double s = 0.0;
-        for (int w = 0; w < BS / 64; w++) s += sred[tid][w];
-        A.partials[4 * ii + tid] = s;
-      }
-      __syncthreads();
+      if (!is_interior(b, tx, ty, tz)) continue;
+      const double v = (double)St::dec(arena[aidx(b, i, x, y, z)], b.dec[WCLS[i]]);
+      acc[0] += v;
+      if (CX[i]) acc[1] += CX[i] * v;
+      if (CY[i]) acc[2] += CY[i] * v;
+      if (CZ[i]) acc[3] += CZ[i] * v;
     }
   }
-
+#pragma unroll
+  for (int m = 0; m < 4; m++) {
+    const double v = wave_sum(acc[m]);
+    if ((tid & 63) == 0) sred[m][tid >> 6] = v;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double s = 0.0;
+    for (int k = 0; k < WG / 64; k++) s += sred[tid][k];
+    A.partials[4 * w + tid] = s;
+  }
 }
 
 }  // namespace lbdev

@@ -53,6 +53,7 @@ struct BoxHost {
   int nbnd = 0;
   bool vec = false;  // interior rows as lane vectors (ITEM_ROWS), x-face nodes included
   int ylog = 0;      // log2 of the y lines interleaved per population row
+  int vw = 0;        // row boxes: 32-bit words per lane vector
 };
 
 struct ChainHost {
@@ -85,6 +86,18 @@ void launch_sites(bool per, int nblk, hipStream_t s, const BoxDesc& d, const voi
     hipLaunchKernelGGL((k_read_sites<S, false>), dim3(nblk), dim3(WG), 0, s, d, (const T*)src, xyz, n, out, pre, r0);
 }
 
+using CheckLaunch = void (*)(int, hipStream_t, const LbArgs&);
+
+template <int S, bool P>
+void launch_check(int n, hipStream_t s, const LbArgs& a) {
+  hipLaunchKernelGGL((k_check<S, P>), dim3(n), dim3(WG), 0, s, a);
+}
+
+template <int S>
+CheckLaunch pick_check(bool per) {
+  return per ? launch_check<S, true> : launch_check<S, false>;
+}
+
 // coll: 0 BGK, 1 MRT, 2 MRT with ghost relaxation rate 1 (ghost moments not formed)
 template <int S>
 LbLaunch pick_lb(int coll, bool per) {
@@ -95,8 +108,24 @@ LbLaunch pick_lb(int coll, bool per) {
 
 size_t store_bytes(int s) { return s == LB_STORE_F64 ? 8 : (s == LB_STORE_F32 ? 4 : 2); }
 size_t real_bytes(int s) { return s == LB_STORE_F64 ? 8 : 4; }
-// nodes per lane of the row items
-int row_nodes(int s) { return row_words(s) * 4 / (int)store_bytes(s); }
+// nodes per lane of the row items with w 32-bit words per lane
+int row_nodes(int s, int w) { return w * 4 / (int)store_bytes(s); }
+
+// Lane-vector width of a row box: prefer 2 words, then 3, among the widths
+// whose lane groups per row divide a wavefront (or fill whole wavefronts) --
+// groups of a row that straddle wavefronts need a halo load per wavefront
+// edge; then any width that divides the row.  0 = no row path.
+int pick_row_words(int storage, int nx) {
+  int fallback = 0;
+  for (int w : {2, 3}) {
+    const int V = row_nodes(storage, w);
+    if (nx % V != 0 || nx < 2 * V) continue;
+    const int L = nx / V;
+    if (64 % L == 0 || L % 64 == 0) return w;
+    if (!fallback) fallback = w;
+  }
+  return fallback;
+}
 
 }  // namespace
 
@@ -115,9 +144,10 @@ struct lb_ctx {
   BoxDesc* d_boxes = nullptr;
   Item* d_items = nullptr;
   int* d_order = nullptr;
-  int* d_box_items = nullptr;
-  int* d_box_items_off = nullptr;
-  double* d_partials = nullptr;
+  int4* d_check_items = nullptr;   // k_check workgroups: box, first plane, end plane
+  int* d_check_off = nullptr;      // [n_boxes + 1]
+  double* d_partials = nullptr;    // [n_check][4]
+  int n_check = 0;
   double* d_mass_mom = nullptr;
   DevState* d_st = nullptr;
   ChainDesc* d_chains = nullptr;
@@ -148,6 +178,7 @@ struct lb_ctx {
   int gsteps_t = 0;
   LbLaunch lb_fn = nullptr;
   ChainLaunch chain_fn = nullptr;
+  CheckLaunch check_fn = nullptr;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -298,13 +329,13 @@ void load_tune_cache(lb_ctx* ctx) {
 void free_tables(lb_ctx* ctx) {
   dfree(ctx, ctx->d_items);
   dfree(ctx, ctx->d_order);
-  dfree(ctx, ctx->d_box_items);
-  dfree(ctx, ctx->d_box_items_off);
+  dfree(ctx, ctx->d_check_items);
+  dfree(ctx, ctx->d_check_off);
   dfree(ctx, ctx->d_partials);
   ctx->d_items = nullptr;
   ctx->d_order = nullptr;
-  ctx->d_box_items = nullptr;
-  ctx->d_box_items_off = nullptr;
+  ctx->d_check_items = nullptr;
+  ctx->d_check_off = nullptr;
   ctx->d_partials = nullptr;
   ctx->tables_ready = false;
   drop_graph(ctx);
@@ -335,7 +366,7 @@ lb_status build_tables(lb_ctx* ctx, int grid_override) {
     if (b.vec) {
       // interior rows cut into lane groups of V nodes, numbered row by row
       // (y fastest, then z); an item is b.ez workgroup iterations of WG groups
-      const int V = row_nodes(ctx->S);
+      const int V = row_nodes(ctx->S, b.vw);
       const int L = b.dim.nx / V, nyi = b.dim.ny - 2;
       const int64_t groups = (int64_t)L * nyi * (b.dim.nz - 2);
       const int64_t per = (int64_t)WG * std::max(1, b.ez);
@@ -420,17 +451,26 @@ lb_status build_tables(lb_ctx* ctx, int grid_override) {
   bool ok = true;
   ctx->d_items = dalloc_t<Item>(ctx, items.size(), &ok);
   ctx->d_order = dalloc_t<int>(ctx, order.size(), &ok);
-  ctx->d_box_items = dalloc_t<int>(ctx, n_items, &ok);
-  ctx->d_box_items_off = dalloc_t<int>(ctx, box_off.size(), &ok);
-  ctx->d_partials = dalloc_t<double>(ctx, 4 * (size_t)n_items, &ok);
+  // mass/momentum check work list: slabs of whole planes, about 64k nodes each
+  std::vector<int4> check;
+  std::vector<int> check_off(ctx->bx.size() + 1, 0);
+  for (size_t bi = 0; bi < ctx->bx.size(); bi++) {
+    const BoxHost& b = ctx->bx[bi];
+    check_off[bi] = (int)check.size();
+    const int zc = std::max(1, 65536 / std::max(1, b.dim.nx * b.dim.ny));
+    for (int z = 0; z < b.dim.nz; z += zc) check.push_back(make_int4((int)bi, z, std::min(b.dim.nz, z + zc), 0));
+  }
+  check_off[ctx->bx.size()] = (int)check.size();
+  ctx->n_check = (int)check.size();
+  ctx->d_check_items = dalloc_t<int4>(ctx, check.size(), &ok);
+  ctx->d_check_off = dalloc_t<int>(ctx, check_off.size(), &ok);
+  ctx->d_partials = dalloc_t<double>(ctx, 4 * check.size(), &ok);
   if (!ok) return fail(ctx, LB_ERR_OOM, "work-list allocation failed");
-  std::vector<int> ident(n_items);
-  std::iota(ident.begin(), ident.end(), 0);
   HIPCHK(h2d(ctx, ctx->d_items, items.data(), items.size() * sizeof(Item)));
   HIPCHK(h2d(ctx, ctx->d_order, order.data(), order.size() * sizeof(int)));
-  HIPCHK(h2d(ctx, ctx->d_box_items, ident.data(), ident.size() * sizeof(int)));
-  HIPCHK(h2d(ctx, ctx->d_box_items_off, box_off.data(), box_off.size() * sizeof(int)));
-  HIPCHK(dzero(ctx, ctx->d_partials, 4 * sizeof(double) * (size_t)n_items));
+  HIPCHK(h2d(ctx, ctx->d_check_items, check.data(), check.size() * sizeof(int4)));
+  HIPCHK(h2d(ctx, ctx->d_check_off, check_off.data(), check_off.size() * sizeof(int)));
+  HIPCHK(dzero(ctx, ctx->d_partials, 4 * sizeof(double) * check.size()));
   ctx->items = items;
   ctx->tables_ready = true;
   std::ostringstream d;
@@ -492,6 +532,7 @@ lb_status upload_boxes(lb_ctx* ctx) {
     }
     d.vec = b.vec ? 1 : 0;
     d.ylog = b.ylog;
+    d.vw = b.vw;
     for (int c = 0; c < 3; c++) {
       d.enc[c] = (float)(s2 / WD[c]);
       d.dec[c] = (float)(WD[c] / s2);
@@ -629,8 +670,8 @@ LbArgs make_args(lb_ctx* ctx, int pre, int advance, int reduce_every) {
   a.bbox = ctx->d_bbox;
   a.st = ctx->d_st;
   a.partials = ctx->d_partials;
-  a.box_items = ctx->d_box_items;
-  a.box_items_off = ctx->d_box_items_off;
+  a.check_items = ctx->d_check_items;
+  a.check_off = ctx->d_check_off;
   a.mass_mom = ctx->d_mass_mom;
   a.n_boxes = (int)ctx->bx.size();
   a.reduce_every = reduce_every;
@@ -670,6 +711,7 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
   const LbArgs a = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
   ctx->lb_fn(dim3(ctx->grid), s, a);
   mark(2);
+  if (ctx->cfg.reduce_every > 0) ctx->check_fn(ctx->n_check, s, a);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, s, a);
 }
 
@@ -832,13 +874,13 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     off += nn * Q;
     if (pm) ctx->per = true;
     {
-      const int V = row_nodes(cfg->storage);
+      b.vw = cfg->storage == LB_STORE_F64 ? 0 : pick_row_words(cfg->storage, n3[0]);
+      const int V = b.vw ? row_nodes(cfg->storage, b.vw) : 1;
       const double groups = (double)(n3[0] / V) * (n3[1] - 2) * (n3[2] - 2);
       // 32-bit buffer offsets: the planes one workgroup iteration touches
       const double plane = (double)Q * n3[0] * n3[1] * (double)store_bytes(cfg->storage);
       const double span = (WG / ((double)(n3[0] / V) * (n3[1] - 2)) + 4.0) * plane;
-      b.vec = cfg->storage != LB_STORE_F64 && pm == 0u && n3[0] % V == 0 && n3[0] >= 2 * V &&
-              groups < 2.0e9 && span < 2147483648.0 && !getenv("LBM_NO_VEC");
+      b.vec = b.vw != 0 && pm == 0u && groups < 2.0e9 && span < 2147483648.0 && !getenv("LBM_NO_VEC");
       // interleave Y = 2^ylog lines per population row so that a row of a
       // block spans whole 128-byte lines (row boxes only)
       b.ylog = 0;
@@ -895,6 +937,8 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
       default: ctx->lb_fn = pick_lb<2>(kc, ctx->per); break;
     }
   }
+  ctx->check_fn = ctx->S == 0 ? pick_check<0>(ctx->per)
+                              : (ctx->S == 1 ? pick_check<1>(ctx->per) : pick_check<2>(ctx->per));
   if (ctx->S == 0)
     ctx->chain_fn = lbhost::pick_chain<0>(ctx->per);
   else if (ctx->S == 1)
