@@ -175,20 +175,23 @@ __global__ void k_read_beads(const ChainDesc* __restrict__ chains, int c0, int c
 }
 
 // stream copy with 16-byte accesses, four independent loads in flight per
-// thread (HBM ceiling probe); n is a multiple of 4 * WG * gridDim.x or the
-// tail is copied one vector at a time
-__global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+// thread, non-temporal stores (HBM ceiling probe); n is a multiple of
+// 4 * WG * gridDim.x or the tail is copied one vector at a time
+__global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src_, uint4* __restrict__ dst_,
                                              size_t n) {
+  typedef unsigned v4 __attribute__((ext_vector_type(4)));
+  const v4* __restrict__ src = (const v4*)src_;
+  v4* __restrict__ dst = (v4*)dst_;
   const size_t stride = (size_t)gridDim.x * WG;
   size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
   for (; i + 3 * stride < n; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
+    const v4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    __builtin_nontemporal_store(a, &dst[i]);
+    __builtin_nontemporal_store(b, &dst[i + stride]);
+    __builtin_nontemporal_store(c, &dst[i + 2 * stride]);
+    __builtin_nontemporal_store(d, &dst[i + 3 * stride]);
   }
-  for (; i < n; i += stride) dst[i] = src[i];
+  for (; i < n; i += stride) __builtin_nontemporal_store(src[i], &dst[i]);
 }
 
 // one constant-rate device timestamp (hipDeviceAttributeWallClockRate kHz),

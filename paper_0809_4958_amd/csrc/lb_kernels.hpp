@@ -21,9 +21,19 @@ namespace lbdev {
 constexpr int WG = 256;
 constexpr int MAX_SLOTS = 4;   // tile plane positions per thread (ex*ey <= 1024)
 constexpr int MAX_BOX_CHAINS = 64;
-// minimum resident waves per SIMD of the FP32/FP16 step kernel (build-time)
+// minimum resident waves per SIMD of the FP32/FP16 step kernel, and the
+// cache-policy bits of the row items' population loads and stores (0, or the
+// non-temporal hint 2): every population is written once per step and read
+// only in the next, so the stores stream past the caches (measured +6% on the
+// batched FP16 step); non-temporal loads measured slower.  Build-time choices.
 #ifndef LB_MIN_WAVES
 #define LB_MIN_WAVES 2
+#endif
+#ifndef LB_LOAD_POLICY
+#define LB_LOAD_POLICY 0
+#endif
+#ifndef LB_STORE_POLICY
+#define LB_STORE_POLICY 2
 #endif
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -496,19 +506,19 @@ template <int W>
 __device__ __forceinline__ void vload(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff,
                                       unsigned (&w)[W]) {
   if constexpr (W == 1) {
-    w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0);
+    w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, LB_LOAD_POLICY);
   } else if constexpr (W == 2) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, LB_LOAD_POLICY);
     w[0] = v[0];
     w[1] = v[1];
   } else if constexpr (W == 3) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)voff, soff, 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)voff, soff, LB_LOAD_POLICY);
     w[0] = v[0];
     w[1] = v[1];
     w[2] = v[2];
   } else {
     static_assert(W == 4, "row vectors are 1 to 4 words");
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, soff, LB_LOAD_POLICY);
     w[0] = v[0];
     w[1] = v[1];
     w[2] = v[2];
@@ -520,25 +530,25 @@ template <int W>
 __device__ __forceinline__ void vstore(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff,
                                        const unsigned (&w)[W]) {
   if constexpr (W == 1) {
-    __builtin_amdgcn_raw_buffer_store_b32(w[0], r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(w[0], r, (int)voff, soff, LB_STORE_POLICY);
   } else if constexpr (W == 2) {
     __attribute__((ext_vector_type(2))) unsigned v;
     v[0] = w[0];
     v[1] = w[1];
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, soff, LB_STORE_POLICY);
   } else if constexpr (W == 3) {
     __attribute__((ext_vector_type(3))) unsigned v;
     v[0] = w[0];
     v[1] = w[1];
     v[2] = w[2];
-    __builtin_amdgcn_raw_buffer_store_b96(v, r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, (int)voff, soff, LB_STORE_POLICY);
   } else {
     __attribute__((ext_vector_type(4))) unsigned v;
     v[0] = w[0];
     v[1] = w[1];
     v[2] = w[2];
     v[3] = w[3];
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, soff, LB_STORE_POLICY);
   }
 }
 
