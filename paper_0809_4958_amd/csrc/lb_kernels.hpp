@@ -983,25 +983,57 @@ __global__ __launch_bounds__(WG) void k_check(LbArgs A) {
   const BoxDesc& b = A.boxes[cw.x];
   const T* __restrict__ arena = (const T*)(par ? A.a0 : A.a1) + b.off;  // written by this step
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t plane = (int64_t)b.nx * b.ny;
-  for (int64_t p = tid; p < (int64_t)(cw.z - cw.y) * plane; p += WG) {
-    const int z = cw.y + (int)(p / plane);
-    const int rem = (int)(p - (p / plane) * plane);
-    const int y = rem / b.nx, x = rem - (rem / b.nx) * b.nx;
+  if (!PER && b.nx % 8 == 0) {
+    // chunks of 8 consecutive nodes of a row, every population read as
+    // 16-byte vectors (rows start 16-byte aligned: box offsets are multiples
+    // of 128 elements and 8 nodes span 16 bytes or a multiple of it)
+    const int cpr = b.nx / 8;
+    const int n_chunks = (cw.z - cw.y) * b.ny * cpr;
+    for (int p = tid; p < n_chunks; p += WG) {
+      const int row = p / cpr, c = p - row * cpr;
+      const int zz = row / b.ny, y = row - zz * b.ny, z = cw.y + zz;
+      const int x0 = 8 * c;
 #pragma unroll
-    for (int i = 0; i < Q; i++) {
-      int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
-      if (PER) {
-        if (b.pmask & 1) tx = wrapc(tx, b.nx);
-        if (b.pmask & 2) ty = wrapc(ty, b.ny);
-        if (b.pmask & 4) tz = wrapc(tz, b.nz);
+      for (int i = 0; i < Q; i++) {
+        const int ty = y + CY[i], tz = z + CZ[i];
+        if (ty < 1 || ty > b.ny - 2 || tz < 1 || tz > b.nz - 2) continue;
+        T v[8];
+        const uint4* src = (const uint4*)(arena + aidx(b, i, x0, y, z));
+#pragma unroll
+        for (int q = 0; q < 8 * (int)sizeof(T) / 16; q++) ((uint4*)v)[q] = src[q];
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          const int tx = x0 + k + CX[i];
+          if (tx >= 1 && tx <= b.nx - 2) sum += (double)St::dec(v[k], b.dec[WCLS[i]]);
+        }
+        acc[0] += sum;
+        if (CX[i]) acc[1] += CX[i] * sum;
+        if (CY[i]) acc[2] += CY[i] * sum;
+        if (CZ[i]) acc[3] += CZ[i] * sum;
       }
-      if (!is_interior(b, tx, ty, tz)) continue;
-      const double v = (double)St::dec(arena[aidx(b, i, x, y, z)], b.dec[WCLS[i]]);
-      acc[0] += v;
-      if (CX[i]) acc[1] += CX[i] * v;
-      if (CY[i]) acc[2] += CY[i] * v;
-      if (CZ[i]) acc[3] += CZ[i] * v;
+    }
+  } else {
+    // node by node; a slab holds fewer than 2^31 nodes (32-bit indices)
+    const int n_slab = (cw.z - cw.y) * b.ny * b.nx;
+    for (int p = tid; p < n_slab; p += WG) {
+      const int row = p / b.nx, x = p - row * b.nx;
+      const int zz = row / b.ny, y = row - zz * b.ny, z = cw.y + zz;
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+        if (PER) {
+          if (b.pmask & 1) tx = wrapc(tx, b.nx);
+          if (b.pmask & 2) ty = wrapc(ty, b.ny);
+          if (b.pmask & 4) tz = wrapc(tz, b.nz);
+        }
+        if (!is_interior(b, tx, ty, tz)) continue;
+        const double v = (double)St::dec(arena[aidx(b, i, x, y, z)], b.dec[WCLS[i]]);
+        acc[0] += v;
+        if (CX[i]) acc[1] += CX[i] * v;
+        if (CY[i]) acc[2] += CY[i] * v;
+        if (CZ[i]) acc[3] += CZ[i] * v;
+      }
     }
   }
 #pragma unroll

@@ -457,6 +457,8 @@ lb_status build_tables(lb_ctx* ctx, int grid_override) {
   for (size_t bi = 0; bi < ctx->bx.size(); bi++) {
     const BoxHost& b = ctx->bx[bi];
     check_off[bi] = (int)check.size();
+    // whole planes of about 64k nodes; a slab stays below 2^31 nodes (32-bit
+    // indices in k_check)
     const int zc = std::max(1, 65536 / std::max(1, b.dim.nx * b.dim.ny));
     for (int z = 0; z < b.dim.nz; z += zc) check.push_back(make_int4((int)bi, z, std::min(b.dim.nz, z + zc), 0));
   }
@@ -870,6 +872,8 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     b.interior = (int64_t)b.ix * b.iy * b.iz;
     b.has_layer = pm != 7u;
     b.nn = nn;
+    // every box starts on a 128-element boundary (aligned vector access)
+    off = (off + 127) / 128 * 128;
     b.off = off;
     off += nn * Q;
     if (pm) ctx->per = true;

@@ -28,6 +28,7 @@ constexpr size_t OFF_W1 = 0, OFF_B1 = OFF_W1 + W1N, OFF_W2 = OFF_B1 + CH, OFF_B2
                  OFF_W3 = OFF_B2 + CH, OFF_B3 = OFF_W3 + W3N, NDEV = OFF_B3 + COUT;
 constexpr int IN_USED = 15, OUT_USED = 3;
 constexpr int MAX_PART = 256;  // weight-gradient partials (workgroups)
+constexpr int RSEG = 16;       // first-stage ranges of the partial reduction
 
 static_assert((size_t)CH * IN_USED * 9 + CH + (size_t)CH * CH * 9 + CH + (size_t)OUT_USED * CH * 9 +
                       OUT_USED ==
@@ -48,6 +49,7 @@ struct lbn_ctx {
   // activations for max_batch samples
   __bf16 *x0 = nullptr, *a1 = nullptr, *a2 = nullptr, *dy = nullptr, *dz1 = nullptr, *dz2 = nullptr;
   float *r = nullptr, *base = nullptr, *scale = nullptr, *part = nullptr, *part_b = nullptr;
+  float* part_seg = nullptr;
   float *wcoarse = nullptr, *wtheta = nullptr;
   double* loss_part = nullptr;
   int last_batch = 0;
@@ -179,8 +181,11 @@ lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size
   const int grid = std::min(rows, MAX_PART);
   hipStream_t st = ctx->stream;
   hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NB), 0, st, x, dz, ctx->part, ctx->part_b, rows);
+  // two fixed-order stages: RSEG ranges of partials in parallel, then their sum
   const int nw = NTAP * CO * CI;
-  hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256), dim3(256), 0, st, ctx->part, grid, nw,
+  hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, nw,
+                     ctx->part_seg);
+  hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256), dim3(256), 0, st, ctx->part_seg, RSEG, nw,
                      ctx->g + off_w);
   hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, ctx->part_b, grid, CO, ctx->g + off_b);
   HIPCHK(hipGetLastError());
@@ -229,6 +234,7 @@ lb_status lbn_init(const lbn_config* cfg, lbn_ctx** out) {
   ctx->scale = dalloc_t<float>(ctx, B, &ok);
   ctx->part = dalloc_t<float>(ctx, (size_t)MAX_PART * NTAP * CH * CH, &ok);
   ctx->part_b = dalloc_t<float>(ctx, (size_t)MAX_PART * CH, &ok);
+  ctx->part_seg = dalloc_t<float>(ctx, (size_t)RSEG * NTAP * CH * CH, &ok);
   ctx->wcoarse = dalloc_t<float>(ctx, B * 12 * cfg->coarse * cfg->coarse, &ok);
   ctx->wtheta = dalloc_t<float>(ctx, B, &ok);
   ctx->loss_part = dalloc_t<double>(ctx, 1024, &ok);

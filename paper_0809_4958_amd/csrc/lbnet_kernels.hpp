@@ -227,6 +227,9 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
   constexpr int PP = IMG + 8;                       // padded pixel stride
   constexpr int TILES = NTAP * (CO / 16) * (CI / 16);
   constexpr int TPW = (TILES + 3) / 4;              // tiles per wave
+  constexpr int XV = 3 * (IMG + 2) * (CI / 8);      // 8-channel vectors of the three x rows
+  constexpr int DV = IMG * (CO / 8);                // 8-channel vectors of the dz row
+  constexpr int XS = (XV + NB - 1) / NB, DS = (DV + NB - 1) / NB;
   __shared__ __attribute__((aligned(16))) __bf16 sdz[CO * PP];          // [co][px]
   __shared__ __attribute__((aligned(16))) __bf16 sxs[NTAP * CI * PP];  // [dx][dy][ci][px]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -234,30 +237,63 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
 #pragma unroll
   for (int j = 0; j < TPW; j++) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   float db = 0.0f;
-  for (int row = blockIdx.x; row < n_rows; row += gridDim.x) {
+  // the next row's vectors travel in registers while the current row computes
+  uint4 xr[XS], dr[DS];
+  auto load_row = [&](int row) {
     const int b = row / IMG, y = row - b * IMG;
-    __syncthreads();
-    // dz row, transposed to [co][px]
-    for (int i = tid; i < IMG * CO; i += NB) {
-      const int co = i % CO, px = i / CO;
-      sdz[co * PP + px] = dz[(((size_t)b * IMG + y) * IMG + px) * CO + co];
+#pragma unroll
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NB;
+      xr[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (v < XV) {
+        const int c8 = v % (CI / 8), q = v / (CI / 8);
+        const int xx = q % (IMG + 2) - 1, dyi = q / (IMG + 2), yy = y + dyi - 1;
+        if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
+          xr[j] = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
+      }
     }
-    // x rows y-1 .. y+1, each shifted by dx, transposed to [ci][px]
-    for (int i = tid; i < 3 * (IMG + 2) * CI; i += NB) {
-      const int ci = i % CI, q = i / CI;
-      const int xx = q % (IMG + 2) - 1, dyi = q / (IMG + 2), yy = y + dyi - 1;
-      __bf16 v = to_bf16(0.0f);
-      if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
-        v = x[(((size_t)b * IMG + yy) * IMG + xx) * CI + ci];
-      // element xx feeds output pixel px = xx - dx for dx in {-1, 0, 1}; every
-      // (dx, dy, ci, px) slot has exactly one source xx = px + dx in -1 .. 64
+#pragma unroll
+    for (int j = 0; j < DS; j++) {
+      const int v = tid + j * NB;
+      dr[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (v < DV) {
+        const int c8 = v % (CO / 8), px = v / (CO / 8);
+        dr[j] = *(const uint4*)&dz[(((size_t)b * IMG + y) * IMG + px) * CO + 8 * c8];
+      }
+    }
+  };
+  if ((int)blockIdx.x < n_rows) load_row(blockIdx.x);
+  for (int row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    __syncthreads();  // previous row's reads of the LDS tiles are done
+    // x rows y-1 .. y+1 transposed to [ci][px], once per dx shift: element xx
+    // feeds output pixel px = xx - dx; every (dx, dy, ci, px) slot has exactly
+    // one source xx = px + dx in -1 .. 64
+#pragma unroll
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NB;
+      if (v >= XV) continue;
+      const int c8 = v % (CI / 8), q = v / (CI / 8);
+      const int xx = q % (IMG + 2) - 1, dyi = q / (IMG + 2);
+      const __bf16* e = (const __bf16*)&xr[j];
 #pragma unroll
       for (int dxi = 0; dxi < 3; dxi++) {
         const int px = xx - (dxi - 1);
-        if (px >= 0 && px < IMG) sxs[((dxi * 3 + dyi) * CI + ci) * PP + px] = v;
+        if (px < 0 || px >= IMG) continue;
+#pragma unroll
+        for (int k = 0; k < 8; k++) sxs[((dxi * 3 + dyi) * CI + 8 * c8 + k) * PP + px] = e[k];
       }
     }
+#pragma unroll
+    for (int j = 0; j < DS; j++) {
+      const int v = tid + j * NB;
+      if (v >= DV) continue;
+      const int c8 = v % (CO / 8), px = v / (CO / 8);
+      const __bf16* e = (const __bf16*)&dr[j];
+#pragma unroll
+      for (int k = 0; k < 8; k++) sdz[(8 * c8 + k) * PP + px] = e[k];
+    }
     __syncthreads();
+    if (row + (int)gridDim.x < n_rows) load_row(row + gridDim.x);
     if (tid < CO) {
       float s = 0.0f;
       for (int px = 0; px < IMG; px++) s += from_bf16(sdz[tid * PP + px]);
@@ -297,14 +333,17 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
   if (tid < CO) part_b[(size_t)blockIdx.x * CO + tid] = db;
 }
 
-// out[i] = sum_g part[g][i] in increasing g (fixed order), i < n
+// out[s][i] = sum of part[g][i] over the s-th of gridDim.y equal ranges of g,
+// in increasing g (fixed order), i < n; with gridDim.y = 1 the full sum
 __global__ void k_reduce_parts(const float* __restrict__ part, int n_parts, int n,
                                float* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int per = (n_parts + gridDim.y - 1) / gridDim.y;
+  const int g0 = blockIdx.y * per, g1 = min(n_parts, g0 + per);
   float s = 0.0f;
-  for (int g = 0; g < n_parts; g++) s += part[(size_t)g * n + i];
-  out[i] = s;
+  for (int g = g0; g < g1; g++) s += part[(size_t)g * n + i];
+  out[(size_t)blockIdx.y * n + i] = s;
 }
 
 // ---------------------------------------------------------------- loss
