@@ -49,6 +49,9 @@ def parse():
     p.add_argument("--copy-mib", type=int, default=1024, help="copy-probe size (0: skip)")
     p.add_argument("--no-tune", action="store_true",
                    help="skip the autotuner (default: tune item sizes and grid before timing)")
+    p.add_argument("--tune-cache", default=None,
+                   help="autotuner cache: if the file exists its launch shape is used and the "
+                        "autotuner is skipped; otherwise the autotuner writes it")
     return p.parse_args()
 
 
@@ -78,10 +81,10 @@ def bead_mass(n_beads):
     return 0.5 / n_beads
 
 
-def make_ctx(lbm, boxes, storage, tau, reduce_every=0, stream=None, graph_steps=0):
+def make_ctx(lbm, boxes, storage, tau, reduce_every=0, stream=None, graph_steps=0, tune_cache=None):
     ctx = lbm.Context([(b["n"],) * 3 for b in boxes], collision=lbm.MRT, tau=tau, tau_bulk=tau,
                       ghost_rate=1.0, storage=storage, reduce_every=reduce_every, stream=stream,
-                      torch_alloc=True, graph_steps=graph_steps)
+                      torch_alloc=True, graph_steps=graph_steps, tune_cache=tune_cache)
     for k, b in enumerate(boxes):
         ctx.set_initial(k, b["u0"])
         ctx.set_boundary(k, lbm.BC_SAMPLED, b["faces"], t0=0, dt=20, res=b["faces"].shape[2])
@@ -152,10 +155,11 @@ def main():
     storage = lbm.STORE_F16DEV if args.storage == "f16" else lbm.STORE_F32
     stream = torch.cuda.current_stream().cuda_stream
     copy_gbs = lbm.copy_probe(args.copy_mib << 20, 20) if args.copy_mib > 0 else None
+    cached = bool(args.tune_cache) and os.path.exists(args.tune_cache)
     ctx = make_ctx(lbm, boxes, storage, tau, reduce_every=100, stream=stream,
-                   graph_steps=args.graph_steps)
+                   graph_steps=args.graph_steps, tune_cache=args.tune_cache)
     t_tune = time.time()
-    if not args.no_tune:
+    if not args.no_tune and not cached:
         ctx.autotune(3)
     t_tune = time.time() - t_tune
     ctx.step(args.warmup)
@@ -192,7 +196,8 @@ def main():
             "interior_nodes": int(interior),
             "storage": args.storage,
             "graph_steps": args.graph_steps,
-            "autotuned": not args.no_tune,
+            "autotuned": not args.no_tune and not cached,
+            "tune_cache": args.tune_cache if cached else None,
             "autotune_s": round(t_tune, 2),
             "launch": ctx.describe(),
         },

@@ -94,7 +94,8 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* user);
   void (*dev_free)(void* ptr, void* user);
   void* alloc_user;
-  const char* tune_cache;  /* path of the autotuner cache (JSON lines) or NULL */
+  const char* tune_cache;  /* path of the autotuner cache (JSON lines: item sizes per box-size
+                              class, grid per set of classes), read by lb_init, or NULL */
   int32_t graph_steps;     /* > 0: lb_step replays a HIP graph of this many steps; 0 = eager launches */
 } lb_config;
 
@@ -209,7 +210,8 @@ lb_status lb_set_timing(lb_ctx* ctx, int32_t on);
 lb_status lb_get_timing(lb_ctx* ctx, double out[4]);
 
 /* Practical HBM ceiling: copies a device buffer of `bytes` (rounded down to a
- * multiple of 16) with 16-byte loads and stores, `iters` times, and returns in
+ * multiple of 16) with 16-byte loads and stores, each workgroup streaming its
+ * own contiguous 256 KiB chunk, `iters` times, and returns in
  * gbs the measured (read + write) bytes per second / 1e9.  Allocates and frees
  * its two buffers with hipMalloc; runs on the current device's null stream. */
 lb_status lb_copy_probe(size_t bytes, int32_t iters, double* gbs);

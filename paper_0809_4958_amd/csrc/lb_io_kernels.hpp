@@ -4,7 +4,8 @@
 //   k_finalize  one workgroup after k_lb: reduces the item partials in a fixed
 //               order per box, checks finiteness, advances the step counter.
 //   k_set_pre / k_read / k_read_sites / k_read_beads   state upload and readout.
-//   k_copy      16-byte stream copy (HBM ceiling probe).
+//   k_copy      16-byte stream copy in contiguous per-workgroup chunks (HBM
+//               ceiling probe).
 //   k_stamp     device wall-clock timestamp (timing inside captured graphs).
 #pragma once
 #include "lb_kernels.hpp"
@@ -178,20 +179,22 @@ __global__ void k_read_beads(const ChainDesc* __restrict__ chains, int c0, int c
 // thread, non-temporal stores (HBM ceiling probe); n is a multiple of
 // 4 * WG * gridDim.x or the tail is copied one vector at a time
 __global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src_, uint4* __restrict__ dst_,
-                                             size_t n) {
+                                             size_t n, size_t per_block) {
   typedef unsigned v4 __attribute__((ext_vector_type(4)));
   const v4* __restrict__ src = (const v4*)src_;
   v4* __restrict__ dst = (v4*)dst_;
-  const size_t stride = (size_t)gridDim.x * WG;
-  size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const v4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+  // each workgroup streams its own contiguous chunk of per_block vectors
+  const size_t b0 = (size_t)blockIdx.x * per_block;
+  const size_t b1 = b0 + per_block < n ? b0 + per_block : n;
+  size_t i = b0 + threadIdx.x;
+  for (; i + 3 * WG < b1; i += 4 * WG) {
+    const v4 a = src[i], b = src[i + WG], c = src[i + 2 * WG], d = src[i + 3 * WG];
     __builtin_nontemporal_store(a, &dst[i]);
-    __builtin_nontemporal_store(b, &dst[i + stride]);
-    __builtin_nontemporal_store(c, &dst[i + 2 * stride]);
-    __builtin_nontemporal_store(d, &dst[i + 3 * stride]);
+    __builtin_nontemporal_store(b, &dst[i + WG]);
+    __builtin_nontemporal_store(c, &dst[i + 2 * WG]);
+    __builtin_nontemporal_store(d, &dst[i + 3 * WG]);
   }
-  for (; i < n; i += stride) __builtin_nontemporal_store(src[i], &dst[i]);
+  for (; i < b1; i += WG) __builtin_nontemporal_store(src[i], &dst[i]);
 }
 
 // one constant-rate device timestamp (hipDeviceAttributeWallClockRate kHz),

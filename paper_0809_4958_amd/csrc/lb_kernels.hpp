@@ -21,13 +21,15 @@ namespace lbdev {
 constexpr int WG = 256;
 constexpr int MAX_SLOTS = 4;   // tile plane positions per thread (ex*ey <= 1024)
 constexpr int MAX_BOX_CHAINS = 64;
-// minimum resident waves per SIMD of the FP32/FP16 step kernel, and the
+// minimum resident waves per SIMD of the FP32/FP16 step kernel (3 caps the
+// register allocation at 168 VGPRs without spills; left free, the allocator
+// lands just above and runs 2 waves, measured up to 11% slower), and the
 // cache-policy bits of the row items' population loads and stores (0, or the
 // non-temporal hint 2): every population is written once per step and read
 // only in the next, so the stores stream past the caches (measured +6% on the
 // batched FP16 step); non-temporal loads measured slower.  Build-time choices.
 #ifndef LB_MIN_WAVES
-#define LB_MIN_WAVES 2
+#define LB_MIN_WAVES 3
 #endif
 #ifndef LB_LOAD_POLICY
 #define LB_LOAD_POLICY 0
@@ -684,30 +686,64 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
     R g[GATHER ? V : 1][3];
 #pragma unroll
     for (int k = 0; k < (GATHER ? V : 1); k++) g[k][0] = g[k][1] = g[k][2] = (R)0;
-    if (GATHER && act) {
+    if (GATHER) {
+      static_assert(sizeof(R) == 4, "row items compute in FP32");
+      // the wavefront loads up to 64 spreading records at once (one per
+      // lane), keeps those whose 2x2 (y, z) stencil meets the wavefront's own
+      // rows and walks them in increasing bead order, reading each from its
+      // lane
       const R* rd = (const R*)A.rec_d;
       const R* rp = (const R*)A.rec_dp;
-      for (int ci = 0; ci < b.chain_count && ci < MAX_BOX_CHAINS; ci++) {
+      const int qw0 = qb + (int)(threadIdx.x & ~63u);
+      const int qw1 = min(min(qw0 + 63, q_end - 1), g_last);
+      const int rw0 = qw0 / L, rw1 = qw1 / L;
+      const int zw0 = 1 + rw0 / nyi, zw1 = 1 + rw1 / nyi;
+      const bool one_plane = zw0 == zw1;
+      const int iy0 = one_plane ? rw0 - (zw0 - 1) * nyi : 0;          // lowest row y, minus 1
+      const int iy1 = one_plane ? 1 + rw1 - (zw1 - 1) * nyi : nyi;    // highest row y
+      const int iz0 = zw0 - 1, iz1 = zw1;
+      for (int ci = 0; ci < b.chain_count && ci < MAX_BOX_CHAINS && qw0 < q_end; ci++) {
         if (!((cmask >> ci) & 1ull)) continue;
-        const int gc = b.chain_first + ci;
-        const int* bb = A.bbox + 6 * gc;
-        if (z < bb[2] || z > bb[5] || y < bb[1] || y > bb[4] || x0 + V - 1 < bb[0] || x0 > bb[3])
-          continue;
-        const ChainDesc& ch = A.chains[gc];
-        for (int jb = ch.first; jb < ch.first + ch.nb; jb++) {
-          const int4 bs = A.rec_base[jb];
-          const int oy = y - bs.y, oz = z - bs.z;
-          if ((unsigned)oy > 1u || (unsigned)oz > 1u) continue;
-          const R dx = rd[3 * jb], dy = rd[3 * jb + 1], dz = rd[3 * jb + 2];
-          const R px = rp[3 * jb], py = rp[3 * jb + 1], pz = rp[3 * jb + 2];
+        const ChainDesc& ch = A.chains[b.chain_first + ci];
+        const int jend = ch.first + ch.nb;
+        for (int j0 = ch.first; j0 < jend; j0 += 64) {
+          const int jb = j0 + lane;
+          int4 bs = make_int4(0, 0, 0, 0);
+          R dx = (R)0, dy = (R)0, dz = (R)0, px = (R)0, py = (R)0, pz = (R)0;
+          bool hit = false;
+          if (jb < jend) {
+            bs = A.rec_base[jb];
+            dx = rd[3 * jb];
+            dy = rd[3 * jb + 1];
+            dz = rd[3 * jb + 2];
+            px = rp[3 * jb];
+            py = rp[3 * jb + 1];
+            pz = rp[3 * jb + 2];
+            hit = bs.y >= iy0 && bs.y <= iy1 && bs.z >= iz0 && bs.z <= iz1;
+          }
+          unsigned long long m = __ballot(hit);
+          while (m) {
+            const int sl = __builtin_ctzll(m);
+            m &= m - 1;
+            const int by = __builtin_amdgcn_readlane(bs.y, sl), bz = __builtin_amdgcn_readlane(bs.z, sl);
+            const int oy = y - by, oz = z - bz;
+            if (!act || (unsigned)oy > 1u || (unsigned)oz > 1u) continue;
+            const int bx = __builtin_amdgcn_readlane(bs.x, sl);
+            const R wdx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dx), sl));
+            const R wdy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dy), sl));
+            const R wdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dz), sl));
+            const R wpx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(px), sl));
+            const R wpy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(py), sl));
+            const R wpz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pz), sl));
 #pragma unroll
-          for (int k = 0; k < V; k++) {
-            const int ox = x0 + k - bs.x;
-            if ((unsigned)ox > 1u) continue;
-            const R w = (ox ? dx : (R)1 - dx) * (oy ? dy : (R)1 - dy) * (oz ? dz : (R)1 - dz);
-            g[k][0] -= w * px;
-            g[k][1] -= w * py;
-            g[k][2] -= w * pz;
+            for (int k = 0; k < V; k++) {
+              const int ox = x0 + k - bx;
+              if ((unsigned)ox > 1u) continue;
+              const R w = (ox ? wdx : (R)1 - wdx) * (oy ? wdy : (R)1 - wdy) * (oz ? wdz : (R)1 - wdz);
+              g[k][0] -= w * wpx;
+              g[k][1] -= w * wpy;
+              g[k][2] -= w * wpz;
+            }
           }
         }
       }

@@ -292,6 +292,16 @@ std::string box_key(const lb_ctx* ctx, const BoxHost& b) {
   return s.str();
 }
 
+// key of a whole context's launch grid: its box-size classes and their counts
+std::string grid_key(lb_ctx* ctx) {
+  std::map<std::string, int> cnt;
+  for (auto& b : ctx->bx) cnt[box_key(ctx, b)]++;
+  std::ostringstream s;
+  s << "grid";
+  for (auto& kv : cnt) s << "_" << kv.first << "n" << kv.second;
+  return s.str();
+}
+
 void load_tune_cache(lb_ctx* ctx) {
   if (!ctx->cfg.tune_cache) return;
   std::ifstream in(ctx->cfg.tune_cache);
@@ -311,8 +321,10 @@ void load_tune_cache(lb_ctx* ctx) {
       if (p == std::string::npos) return -1;
       return atoi(line.c_str() + line.find(':', p) + 1);
     };
-    entries[key] = {num("ex"), num("ey"), num("ez")};
+    entries[key] = {num("ex"), num("ey"), num("ez"), num("grid")};
   }
+  auto g = entries.find(grid_key(ctx));
+  if (g != entries.end() && g->second[3] >= 8) ctx->grid = g->second[3];
   for (auto& b : ctx->bx) {
     auto it = entries.find(box_key(ctx, b));
     if (it == entries.end()) continue;
@@ -1502,6 +1514,7 @@ lb_status lb_autotune(lb_ctx* ctx, int32_t trials) {
       o << "{\"key\": \"" << kv.first << "\", \"ex\": " << b.ex << ", \"ey\": " << b.ey
         << ", \"ez\": " << b.ez << "}\n";
     }
+    o << "{\"key\": \"" << grid_key(ctx) << "\", \"grid\": " << ctx->grid << "}\n";
   }
   return LB_OK;
 }
@@ -1521,17 +1534,21 @@ lb_status lb_copy_probe(size_t bytes, int32_t iters, double* gbs) {
       hipEventCreate(&e1) != hipSuccess) {
     st = LB_ERR_HIP;
   } else {
-    const int grid = 256 * 32;
-    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, nullptr, (const uint4*)a, (uint4*)b, n);
+    // 256 KiB per workgroup: the fastest of the copy shapes measured (grid
+    // strides and chunks of 64 KiB .. 1 MiB)
+    const size_t per_block = 16384;
+    const int grid = (int)std::min<size_t>((n + per_block - 1) / per_block, 1u << 30);
+    const size_t nn = std::min(n, (size_t)grid * per_block);
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, nullptr, (const uint4*)a, (uint4*)b, nn, per_block);
     (void)hipEventRecord(e0, nullptr);
     for (int k = 0; k < iters; k++)
-      hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, nullptr, (const uint4*)a, (uint4*)b, n);
+      hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, nullptr, (const uint4*)a, (uint4*)b, nn, per_block);
     (void)hipEventRecord(e1, nullptr);
     float ms = 0;
     if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
       st = LB_ERR_HIP;
     else
-      *gbs = 2.0 * (double)n * 16.0 * iters / (ms * 1e-3) / 1e9;
+      *gbs = 2.0 * (double)nn * 16.0 * iters / (ms * 1e-3) / 1e9;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }

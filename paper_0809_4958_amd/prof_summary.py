@@ -14,7 +14,7 @@ Two summaries are written under ``profiles/``:
 Usage::
 
     python -m paper_0809_4958_amd.prof_summary kernels STATS_CSV OUT --command "..." \\
-        [--trace TRACE_CSV --tail N]
+        [--trace TRACE_CSV --tail N] [--tune-cache TUNE_JSONL]
     python -m paper_0809_4958_amd.prof_summary traffic FETCH_CSV WRITE_CSV OUT \\
         --copy-bytes N --command-fetch "..." --command-write "..."
 """
@@ -41,12 +41,15 @@ def kernel_source_hash() -> str:
 
 def short_name(name: str) -> str:
     """Readable kernel name: template arguments of the step kernels kept."""
-    for k in ("k_lb", "k_chain", "k_finalize", "k_copy", "k_set_pre", "k_read_sites", "k_read_beads",
-              "k_read"):
+    for k in ("k_lb", "k_chain", "k_check", "k_finalize", "k_copy", "k_stamp", "k_set_pre", "k_read_sites",
+              "k_read_beads", "k_read"):
         if k in name:
             i = name.find(k)
             return name[i:i + 60].split("(")[0]
-    return name[:60]
+    # other kernels: the name without return type, namespace and argument list
+    n = name.split("(")[0]
+    n = n[5:] if n.startswith("void ") else n
+    return n.split("::")[-1][:60] if "<" not in n else n[n.find("::") + 2:][:60]
 
 
 def timed_average(trace_csv: str, kernel: str, tail: int):
@@ -61,13 +64,17 @@ def timed_average(trace_csv: str, kernel: str, tail: int):
     return sum(last) / len(last) / 1e6, len(durs)
 
 
-def kernels(stats_csv: str, out: str, command: str, trace_csv: str | None = None, tail: int = 0) -> None:
+def kernels(stats_csv: str, out: str, command: str, trace_csv: str | None = None, tail: int = 0,
+            tune_cache: str | None = None) -> None:
     rows = list(csv.DictReader(open(stats_csv)))
     lines = ["# rocprofv3 kernel-trace statistics", f"# command: {command}", ""]
+    if tune_cache:
+        lines += [f"launch shape (autotuner cache {os.path.basename(tune_cache)}):"]
+        lines += ["  " + ln.strip() for ln in open(tune_cache) if ln.strip()] + [""]
     if trace_csv and tail > 0:
         avg, n = timed_average(trace_csv, "k_lb", tail)
         lines += [f"k_lb average over the last {tail} dispatches (the timed steps): {avg:.4f} ms "
-                  f"({n} dispatches in all, the others are warm-up and autotuner trials)", ""]
+                  f"({n} dispatches in all; the others are warm-up and any autotuner trials)", ""]
     lines += [f"{'kernel':48s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'share_%':>8s}"]
     for r in rows:
         name = short_name(r.get("Name", r.get("KernelName", "")))
@@ -142,6 +149,7 @@ def main():
     k.add_argument("--command", required=True)
     k.add_argument("--trace", help="kernel_trace.csv of the same run")
     k.add_argument("--tail", type=int, default=0, help="timed k_lb dispatches at the end of the run")
+    k.add_argument("--tune-cache", help="autotuner cache the profiled run used")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -155,7 +163,7 @@ def main():
                    help="algorithmic bytes per k_lb launch (bench.py roofline)")
     a = p.parse_args()
     if a.what == "kernels":
-        kernels(a.stats_csv, a.out, a.command, a.trace, a.tail)
+        kernels(a.stats_csv, a.out, a.command, a.trace, a.tail, a.tune_cache)
     else:
         traffic(a.fetch_csv, a.write_csv, a.out, a.copy_bytes, a.command_fetch, a.command_write,
                 a.workload, a.storage, a.algorithmic)

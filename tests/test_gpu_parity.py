@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from lbcase import Case, cfg0_case, ks_case, rel_l2
+from lbcase import CHAIN_BOND, Case, cfg0_case, ks_case, rel_l2
 from paper_0809_4958_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -153,6 +153,34 @@ def test_reduced_precision_storage(storage):
     r = compare(ctx, ob, case, storage)
     say(storage, r)
     assert r["u"] < TOL_U[storage]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("layout", ["one_chain", "three_chains"])
+def test_row_gather_many_beads(storage, layout):
+    """Spreading into row items from many beads near the same rows of a 40^3
+    KS box: "one_chain" has one 200-bead chain at the centre (four 64-record
+    chunks per wavefront), "three_chains" three 120-bead chains at the same
+    centre (several chains per item, 360 records).  Bead masses keep the
+    whole load at half a fluid node."""
+    n, steps = 40, 100
+    units, u0, faces = inputs.ks_box_inputs(1, 3, n=n, tau=0.6, n_steps=steps, dt=20, res=17)
+    xc = np.full(3, (n - 1) / 2.0)
+    sizes = [200] if layout == "one_chain" else [120, 120, 120]
+    chains = []
+    for k, nb in enumerate(sizes):
+        pos, vel = inputs.chain_init(nb, xc, inputs.rng(1, 10 + k), bond=CHAIN_BOND)
+        chains.append(dict(pos=pos, vel=vel, anchor=xc, mass=0.5 / sum(sizes)))
+    case = Case((n, n, n), collision=oracle.MRT, tau=0.6, tau_bulk=0.6, ghost_rate=1.0,
+                bc=(oracle.BC_SAMPLED, faces.astype(np.float32), 0, 20, 17), u0=u0, chains=chains)
+    say("case gather", layout, storage, f"{n}^3 {steps} steps, chains {sizes}")
+    ob = case.oracle_box()
+    assert ob.step(steps) == 0
+    ctx = make_ctx(case, storage)
+    ctx.step(steps)
+    r = compare(ctx, ob, case, storage)
+    say(layout, storage, r)
+    assert r["u"] < TOL_U[storage] and r["bead_pos"] < TOL_U[storage]
 
 
 def test_edge_shapes_fp64():
