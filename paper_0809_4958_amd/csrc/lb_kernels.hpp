@@ -45,8 +45,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------- chain
-template <int S, bool PER>
-__global__ __launch_bounds__(WG) void k_chain(const BoxDesc* __restrict__ boxes,
+// CB threads per chain (one per bead): 64 when no chain has more than 64
+// beads (one wavefront, so the workgroup barriers are nearly free), else 256.
+template <int S, bool PER, int CB>
+__global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
                                               const ChainDesc* __restrict__ chains,
                                               const typename Store<S>::T* __restrict__ a0,
                                               const typename Store<S>::T* __restrict__ a1,
@@ -71,9 +73,9 @@ __global__ __launch_bounds__(WG) void k_chain(const BoxDesc* __restrict__ boxes,
   const bool act = j < c.nb;
   const int gj = c.first + j;
 
-  __shared__ R spx[WG], spy[WG], spz[WG];
-  __shared__ R bfx[WG], bfy[WG], bfz[WG];
-  __shared__ R red[3][WG];
+  __shared__ R spx[CB], spy[CB], spz[CB];
+  __shared__ R bfx[CB], bfy[CB], bfz[CB];
+  __shared__ R red[3][CB];
   __shared__ int sflag;
   __shared__ int sbox[6];
   if (j == 0) {
@@ -121,9 +123,10 @@ __global__ __launch_bounds__(WG) void k_chain(const BoxDesc* __restrict__ boxes,
   }
 
   // fluid velocity at the bead: sum over the 8 corners of weight x j/rho
+  // (unrolled, so the loads of all corners are in flight together)
   R ux = 0, uy = 0, uz = 0;
   if (act) {
-#pragma unroll 1
+#pragma unroll
     for (int cc = 0; cc < 8; cc++) {
       const int o0 = cc & 1, o1 = (cc >> 1) & 1, o2 = (cc >> 2) & 1;
       int qx = base[0] + o0, qy = base[1] + o1, qz = base[2] + o2;
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(WG) void k_chain(const BoxDesc* __restrict__ boxes,
         red[1][j] = act ? (pass ? ry : vy) : (R)0;
         red[2][j] = act ? (pass ? rz : vz) : (R)0;
         __syncthreads();
-        for (int o = WG / 2; o > 0; o >>= 1) {
+        for (int o = CB / 2; o > 0; o >>= 1) {
           if (j < o) {
             red[0][j] += red[0][j + o];
             red[1][j] += red[1][j + o];
@@ -892,8 +895,13 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
 
 // ----------------------------------------------------------- fused step
 
+// resident waves per SIMD the step kernel is compiled for: FP64 4; FP16 BGK 2
+// (its allocation needs 188 VGPRs, and 3 waves would spill); otherwise
+// LB_MIN_WAVES
+constexpr int lb_min_waves(int S, int COLL) { return S == 0 ? 4 : (S == 2 && COLL == 0 ? 2 : LB_MIN_WAVES); }
+
 template <int S, int COLL, bool PER, int BS = WG>
-__global__ __launch_bounds__(BS, (S == 0 ? 4 : LB_MIN_WAVES)) void k_lb(LbArgs A) {
+__global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;

@@ -23,8 +23,9 @@ using ChainLaunch = void (*)(int, hipStream_t, const lbdev::BoxDesc*, const lbde
 template <int S, int C>
 LbLaunch pick_lb(bool periodic);
 
-// chain kernel launcher for storage S
+// chain kernel launcher for storage S; one wavefront per chain when no chain
+// has more than 64 beads, else 256 threads
 template <int S>
-ChainLaunch pick_chain(bool periodic);
+ChainLaunch pick_chain(bool periodic, int max_beads);
 
 }  // namespace lbhost

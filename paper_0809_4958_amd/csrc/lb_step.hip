@@ -26,22 +26,23 @@ LbLaunch pick_lb(bool periodic) {
 template LbLaunch pick_lb<LB_S, LB_C>(bool);
 
 #if LB_C == 0
-template <int S, bool P>
+template <int S, bool P, int CB>
 void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc* chains,
                   const void* a0, const void* a1, void* pos, void* vel, int total, int4* rb,
                   void* rd, void* rp, int* bbox, DevState* st, double rho0, int pre) {
   using T = typename Store<S>::T;
   using R = typename Store<S>::R;
-  hipLaunchKernelGGL((k_chain<S, P>), dim3(nch), dim3(WG), 0, s, boxes, chains, (const T*)a0,
+  hipLaunchKernelGGL((k_chain<S, P, CB>), dim3(nch), dim3(CB), 0, s, boxes, chains, (const T*)a0,
                      (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox, st, rho0, pre);
 }
 
 template <int S>
-ChainLaunch pick_chain(bool periodic) {
-  return periodic ? launch_chain<S, true> : launch_chain<S, false>;
+ChainLaunch pick_chain(bool periodic, int max_beads) {
+  if (max_beads <= 64) return periodic ? launch_chain<S, true, 64> : launch_chain<S, false, 64>;
+  return periodic ? launch_chain<S, true, WG> : launch_chain<S, false, WG>;
 }
 
-template ChainLaunch pick_chain<LB_S>(bool);
+template ChainLaunch pick_chain<LB_S>(bool, int);
 #endif
 
 }  // namespace lbhost

@@ -653,6 +653,15 @@ lb_status upload_chains(lb_ctx* ctx) {
   HIPCHK(dzero(ctx, ctx->d_rec_base, nbd * sizeof(int4)));
   HIPCHK(dzero(ctx, ctx->d_rec_d, 3 * nbd * rb));
   HIPCHK(dzero(ctx, ctx->d_rec_dp, 3 * nbd * rb));
+  // chain kernel: one wavefront per chain when every chain fits in one
+  int max_nb = 0;
+  for (auto& c : ctx->ch) max_nb = std::max(max_nb, c.p.n_beads);
+  if (ctx->S == 0)
+    ctx->chain_fn = lbhost::pick_chain<0>(ctx->per, max_nb);
+  else if (ctx->S == 1)
+    ctx->chain_fn = lbhost::pick_chain<1>(ctx->per, max_nb);
+  else
+    ctx->chain_fn = lbhost::pick_chain<2>(ctx->per, max_nb);
   ctx->chains_ready = true;
   return upload_boxes(ctx);
 }
@@ -955,12 +964,6 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   }
   ctx->check_fn = ctx->S == 0 ? pick_check<0>(ctx->per)
                               : (ctx->S == 1 ? pick_check<1>(ctx->per) : pick_check<2>(ctx->per));
-  if (ctx->S == 0)
-    ctx->chain_fn = lbhost::pick_chain<0>(ctx->per);
-  else if (ctx->S == 1)
-    ctx->chain_fn = lbhost::pick_chain<1>(ctx->per);
-  else
-    ctx->chain_fn = lbhost::pick_chain<2>(ctx->per);
   load_tune_cache(ctx);
   if (upload_boxes(ctx) != LB_OK) {
     lb_free(ctx);

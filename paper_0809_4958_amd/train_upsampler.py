@@ -15,6 +15,9 @@ Evaluation on held-out trajectories:
     field (LEARNED ring refilled every window); relative L2 error of the
     interior velocity of the latter two against the first.
 
+Inference speed: one window of lbn_window_forward (6 faces x 20 steps of
+64 x 64 fields from resident samples), timed with HIP events.
+
 Usage:  python -m paper_0809_4958_amd.train_upsampler [--traj 2000] [--out PATH]
 Prints one JSON line; writes the parameter vector (float32, .npy) to --out.
 """
@@ -79,6 +82,25 @@ def face_fields(net, c, th, batch):
     torch.cuda.synchronize()
     plain.close()
     return out.cpu().numpy(), base.cpu().numpy()
+
+
+def time_window_inference(net, traj, dt=20, R=8, reps=200):
+    """Average time of one window of inference (lbn_window_forward: the 6 faces
+    x dt per-step fields of one window, 6 dt images of 64 x 64) on resident
+    samples, timed with HIP events on the network's stream."""
+    import torch
+    _, _, coarse = inputs.ks_box_inputs(CFG_LEARNED, traj, n=64, tau=0.6, n_steps=4 * dt, dt=dt, res=R)
+    hist = dev(coarse)
+    ring = torch.zeros((dt, 6, 64, 64, 3), device="cuda")
+    for _ in range(5):
+        net.window_forward(hist, 1, dt, ring)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.window_forward(hist, 1, dt, ring)
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps, 6 * dt
 
 
 def downstream(net, traj, n=64, tau=0.6, windows=3, dt=20, R=8):
@@ -149,6 +171,7 @@ def main():
     u_net, u_base = face_fields(net, ch, thh, 120)
     e_net, e_base = rel_l2(u_net, trh), rel_l2(u_base, trh)
     ds = [downstream(net, HELD_OUT_BASE + i) for i in range(args.downstream)]
+    win_ms, win_images = time_window_inference(net, HELD_OUT_BASE)
     p = net.params()
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, p)
@@ -166,6 +189,10 @@ def main():
         "train_seconds": round(t_train, 2), "data_seconds": round(t_data, 1),
         "train_ms_per_iter": round(t_train * 1e3 / args.iters, 3),
         "train_tflops_mfma": round(3.0 * flops_sample * args.batch * args.iters / t_train / 1e12, 2),
+        "infer_window_ms": round(win_ms, 4),
+        "infer_window_images": win_images,
+        "infer_tflops_mfma": round(flops_sample * win_images / (win_ms * 1e-3) / 1e12, 2),
+        "infer_mfma_frac_of_bf16_dense_peak": round(flops_sample * win_images / (win_ms * 1e-3) / 2.5e15, 4),
         "weights": os.path.relpath(args.out, os.path.dirname(PKG)),
     }
     print(json.dumps(out), flush=True)
