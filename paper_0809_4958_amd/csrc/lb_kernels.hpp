@@ -21,16 +21,12 @@ namespace lbdev {
 constexpr int WG = 256;
 constexpr int MAX_SLOTS = 4;   // tile plane positions per thread (ex*ey <= 1024)
 constexpr int MAX_BOX_CHAINS = 64;
-// minimum resident waves per SIMD of the FP32/FP16 step kernel (3 caps the
-// register allocation at 168 VGPRs without spills; left free, the allocator
-// lands just above and runs 2 waves, measured up to 11% slower), and the
-// cache-policy bits of the row items' population loads and stores (0, or the
+// Cache-policy bits of the row items' population loads and stores (0, or the
 // non-temporal hint 2): every population is written once per step and read
 // only in the next, so the stores stream past the caches (measured +6% on the
-// batched FP16 step); non-temporal loads measured slower.  Build-time choices.
-#ifndef LB_MIN_WAVES
-#define LB_MIN_WAVES 3
-#endif
+// batched FP16 step); non-temporal loads measured slower.  Build-time choices,
+// like LB_MIN_WAVES (when defined, it overrides the per-variant wave counts of
+// lb_min_waves for every FP32/FP16 step kernel).
 #ifndef LB_LOAD_POLICY
 #define LB_LOAD_POLICY 0
 #endif
@@ -895,10 +891,18 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
 
 // ----------------------------------------------------------- fused step
 
-// resident waves per SIMD the step kernel is compiled for: FP64 4; FP16 BGK 2
-// (its allocation needs 188 VGPRs, and 3 waves would spill); otherwise
-// LB_MIN_WAVES
-constexpr int lb_min_waves(int S, int COLL) { return S == 0 ? 4 : (S == 2 && COLL == 0 ? 2 : LB_MIN_WAVES); }
+// Resident waves per SIMD the step kernel is compiled for: the most that fit
+// without spilling (VGPRs per lane: 512 / waves).  FP64 4; FP32 MRT 4 (125-126
+// VGPRs), FP32 BGK 3 (152); FP16 MRT 3 (161-165), FP16 BGK 2 (188).  Left to
+// itself the allocator lands just above a boundary and runs one wave fewer,
+// measured 5-11% slower.
+constexpr int lb_min_waves(int S, int COLL) {
+#ifdef LB_MIN_WAVES
+  return S == 0 ? 4 : LB_MIN_WAVES;
+#else
+  return S == 0 ? 4 : (S == 1 ? (COLL == 0 ? 3 : 4) : (COLL == 0 ? 2 : 3));
+#endif
+}
 
 template <int S, int COLL, bool PER, int BS = WG>
 __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {

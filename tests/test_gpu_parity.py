@@ -249,6 +249,26 @@ def test_graph_replay_and_determinism_bitwise():
         assert np.array_equal(r[2], runs[0][2])
 
 
+def test_tune_cache_round_trip(tmp_path):
+    """The autotuner's launch shape (item sizes per box size, grid) written to
+    the cache is what a new context over the same boxes reads back, and the
+    two compute the same state bitwise."""
+    case = ks_case(32, 40, dt=20, res=9, n_beads=8, config_idx=2)
+    cache = str(tmp_path / "tune.jsonl")
+    a = make_ctx(case, "f16", tune_cache=cache)
+    a.autotune(1)
+    a.step(20)
+    desc_a = a.describe()
+    b = make_ctx(case, "f16", tune_cache=cache)
+    b.step(20)
+    desc_b = b.describe()
+    say("tuned:", desc_a, "| from cache:", desc_b)
+    assert desc_a == desc_b
+    assert np.array_equal(a.read(0, lbm.F_POP), b.read(0, lbm.F_POP))
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_checkpoint_resume_bitwise(storage):
     case = ks_case(20, 60, dt=20, res=9, n_beads=6, config_idx=4)
