@@ -153,22 +153,23 @@ lb_status prep_weights(lbn_ctx* ctx) {
   return LB_OK;
 }
 
-int conv_grid(int n_pairs, int per_cu) { return std::min(n_pairs, 256 * per_cu); }
+// persistent convolution grid: per_cu workgroups per compute unit (by LDS use)
+int conv_grid(int n_tiles, int per_cu) { return std::min(n_tiles, 256 * per_cu); }
 
 lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int batch) {
   lb_status s = prep_weights(ctx);
   if (s) return s;
-  const int pairs = batch * (IMG / 2);
+  const int tiles = batch * (IMG / TR);
   hipStream_t st = ctx->stream;
   const int R = ctx->cfg.coarse;
   hipLaunchKernelGGL(k_lift, dim3(batch), dim3(NB), 12 * R * R * sizeof(float), st, coarse, theta, R, ctx->x0,
                      ctx->base, ctx->scale);
-  hipLaunchKernelGGL((k_conv<CIN, CH, 0>), dim3(conv_grid(pairs, 2)), dim3(NB), 0, st, ctx->x0, ctx->w1f,
-                     ctx->p + OFF_B1, nullptr, (void*)ctx->a1, pairs);
-  hipLaunchKernelGGL((k_conv<CH, CH, 0>), dim3(conv_grid(pairs, 1)), dim3(NB), 0, st, ctx->a1, ctx->w2f,
-                     ctx->p + OFF_B2, nullptr, (void*)ctx->a2, pairs);
-  hipLaunchKernelGGL((k_conv<CH, COUT, 1>), dim3(conv_grid(pairs, 2)), dim3(NB), 0, st, ctx->a2, ctx->w3f,
-                     ctx->p + OFF_B3, nullptr, (void*)ctx->r, pairs);
+  hipLaunchKernelGGL((k_conv<CIN, CH, 0>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->x0, ctx->w1f,
+                     ctx->p + OFF_B1, nullptr, (void*)ctx->a1, tiles);
+  hipLaunchKernelGGL((k_conv<CH, CH, 0>), dim3(conv_grid(tiles, 1)), dim3(NBC), 0, st, ctx->a1, ctx->w2f,
+                     ctx->p + OFF_B2, nullptr, (void*)ctx->a2, tiles);
+  hipLaunchKernelGGL((k_conv<CH, COUT, 1>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->a2, ctx->w3f,
+                     ctx->p + OFF_B3, nullptr, (void*)ctx->r, tiles);
   HIPCHK(hipGetLastError());
   ctx->last_batch = batch;
   return LB_OK;
@@ -323,15 +324,15 @@ lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* thet
   hipLaunchKernelGGL(k_loss, dim3(lgrid), dim3(NB), 0, st, ctx->r, ctx->base, ctx->scale, truth_dev, n_px,
                      inv_count, ctx->dy, ctx->loss_part);
   HIPCHK(hipGetLastError());
-  const int pairs = batch * (IMG / 2);
+  const int tiles = batch * (IMG / TR);
   // layer 3: weights from (a2, dy); data gradient through ReLU(a2)
   if ((s = wgrad<CH, COUT>(ctx, ctx->a2, ctx->dy, batch, OFF_W3, OFF_B3))) return s;
-  hipLaunchKernelGGL((k_conv<COUT, CH, 2>), dim3(conv_grid(pairs, 2)), dim3(NB), 0, st, ctx->dy, ctx->w3t,
-                     nullptr, ctx->a2, (void*)ctx->dz2, pairs);
+  hipLaunchKernelGGL((k_conv<COUT, CH, 2>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->dy, ctx->w3t,
+                     nullptr, ctx->a2, (void*)ctx->dz2, tiles);
   // layer 2
   if ((s = wgrad<CH, CH>(ctx, ctx->a1, ctx->dz2, batch, OFF_W2, OFF_B2))) return s;
-  hipLaunchKernelGGL((k_conv<CH, CH, 2>), dim3(conv_grid(pairs, 1)), dim3(NB), 0, st, ctx->dz2, ctx->w2t,
-                     nullptr, ctx->a1, (void*)ctx->dz1, pairs);
+  hipLaunchKernelGGL((k_conv<CH, CH, 2>), dim3(conv_grid(tiles, 1)), dim3(NBC), 0, st, ctx->dz2, ctx->w2t,
+                     nullptr, ctx->a1, (void*)ctx->dz1, tiles);
   // layer 1
   if ((s = wgrad<CIN, CH>(ctx, ctx->x0, ctx->dz1, batch, OFF_W1, OFF_B1))) return s;
   HIPCHK(hipGetLastError());

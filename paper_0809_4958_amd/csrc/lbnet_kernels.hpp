@@ -42,6 +42,8 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 constexpr int NB = 256;     // threads per workgroup
+constexpr int NBC = 512;    // threads per convolution workgroup: one row of a tile per wave pair
+constexpr int TR = 4;       // image rows per convolution tile
 constexpr int IMG = 64;     // image edge (face nodes)
 constexpr int CIN = 16;     // lifted input channels (15 used)
 constexpr int CH = 64;      // hidden channels
@@ -127,46 +129,69 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
 }
 
 // ---------------------------------------------------------------- conv
-// Implicit-GEMM 3x3 convolution over pairs of image rows.  EPI: 0 = bias +
+// Implicit-GEMM 3x3 convolution over tiles of TR image rows.  EPI: 0 = bias +
 // ReLU -> bf16; 1 = bias -> fp32 (last layer, all CO channels); 2 = no bias,
 // times the mask (mask_src > 0) -> bf16 (backward data through a ReLU).
-// Persistent: workgroup g handles row pairs g, g + gridDim.x, ...
+// Persistent: workgroup g handles tiles g, g + gridDim.x, ...; eight waves
+// share one LDS copy of the weights, each computes 32 pixels x CO.
 template <int CI, int CO, int EPI>
-__global__ __launch_bounds__(NB) void k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
-                                             const float* __restrict__ bias,
-                                             const __bf16* __restrict__ mask_src,
-                                             void* __restrict__ out, int n_pairs) {
-  constexpr int CP = CI + 8;                 // padded channel stride in LDS
+__global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
+                                              const float* __restrict__ bias,
+                                              const __bf16* __restrict__ mask_src,
+                                              void* __restrict__ out, int n_tiles) {
+  constexpr int CP = CI + 8;                  // padded channel stride in LDS
   constexpr int KCH = (NTAP * CI + 31) / 32;  // K chunks of 32
-  constexpr int NBK = CO / 16;               // 16-column blocks
+  constexpr int NBK = CO / 16;                // 16-column blocks
+  constexpr int SR = TR + 2;                  // staged input rows per tile
+  constexpr int XV = SR * (IMG + 2) * (CI / 8);
+  constexpr int XS = (XV + NBC - 1) / NBC;    // 8-channel vectors per thread
   __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CP];
-  __shared__ __attribute__((aligned(16))) __bf16 sx[4 * (IMG + 2) * CP];
+  __shared__ __attribute__((aligned(16))) __bf16 sx[SR * (IMG + 2) * CP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // weights once per workgroup
-  for (int i = tid; i < NTAP * CO * (CI / 8); i += NB) {
+  for (int i = tid; i < NTAP * CO * (CI / 8); i += NBC) {
     const int row = i / (CI / 8), c8 = i - row * (CI / 8);
     *(uint4*)&sw[row * CP + 8 * c8] = *(const uint4*)&w[(size_t)row * CI + 8 * c8];
   }
+  // wave: row r of the tile, pixels px0 .. px0 + 31
   const int r = wave >> 1, px0 = (wave & 1) * 32;
-  for (int pair = blockIdx.x; pair < n_pairs; pair += gridDim.x) {
-    const int b = pair / (IMG / 2), y0 = 2 * (pair - b * (IMG / 2));
-    __syncthreads();  // previous tile's reads of sx are done
-    // rows y0-1 .. y0+2, columns -1 .. 64, zero outside the image
-    for (int i = tid; i < 4 * (IMG + 2) * (CI / 8); i += NB) {
-      const int c8 = i % (CI / 8), q = i / (CI / 8);
-      const int xx = q % (IMG + 2) - 1, rr = q / (IMG + 2), yy = y0 - 1 + rr;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
-        v = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
-      *(uint4*)&sx[q * CP + 8 * c8] = v;
+  // input rows y0-1 .. y0+TR, columns -1 .. 64 (zero outside the image); the
+  // next tile's rows travel in registers while the current tile computes
+  uint4 xr[XS];
+  auto load_tile = [&](int tile) {
+    const int b = tile / (IMG / TR), y0 = TR * (tile - b * (IMG / TR));
+#pragma unroll
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NBC;
+      xr[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (v < XV) {
+        const int c8 = v % (CI / 8), q = v / (CI / 8);
+        const int xx = q % (IMG + 2) - 1, rr = q / (IMG + 2), yy = y0 - 1 + rr;
+        if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
+          xr[j] = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
+      }
+    }
+  };
+  if ((int)blockIdx.x < n_tiles) load_tile(blockIdx.x);
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int b = tile / (IMG / TR), y0 = TR * (tile - b * (IMG / TR));
+    __syncthreads();  // the previous tile's reads of sx are done (and sw is complete)
+#pragma unroll
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NBC;
+      if (v < XV) {
+        const int c8 = v % (CI / 8), q = v / (CI / 8);
+        *(uint4*)&sx[q * CP + 8 * c8] = xr[j];
+      }
     }
     __syncthreads();
+    if (tile + (int)gridDim.x < n_tiles) load_tile(tile + gridDim.x);
     f32x4 acc[2][NBK];
 #pragma unroll
     for (int mb = 0; mb < 2; mb++)
 #pragma unroll
       for (int nb = 0; nb < NBK; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
+#pragma unroll 2
     for (int kc = 0; kc < KCH; kc++) {
       const int k0 = 32 * kc + 8 * (lane >> 4);
       const bool kv = k0 < NTAP * CI;
@@ -342,6 +367,9 @@ __global__ void k_reduce_parts(const float* __restrict__ part, int n_parts, int 
   const int per = (n_parts + gridDim.y - 1) / gridDim.y;
   const int g0 = blockIdx.y * per, g1 = min(n_parts, g0 + per);
   float s = 0.0f;
+  // unrolled so that the loads are in flight together; the sum stays in
+  // increasing g
+#pragma unroll 8
   for (int g = g0; g < g1; g++) s += part[(size_t)g * n + i];
   out[(size_t)blockIdx.y * n + i] = s;
 }
