@@ -28,6 +28,7 @@ constexpr size_t OFF_W1 = 0, OFF_B1 = OFF_W1 + W1N, OFF_W2 = OFF_B1 + CH, OFF_B2
                  OFF_W3 = OFF_B2 + CH, OFF_B3 = OFF_W3 + W3N, NDEV = OFF_B3 + COUT;
 constexpr int IN_USED = 15, OUT_USED = 3;
 constexpr int MAX_PART = 256;  // weight-gradient partials (workgroups)
+constexpr int LIFT_SLICES = 8;  // workgroups per image of the lift (8 rows each)
 constexpr int RSEG = 16;       // first-stage ranges of the partial reduction
 
 static_assert((size_t)CH * IN_USED * 9 + CH + (size_t)CH * CH * 9 + CH + (size_t)OUT_USED * CH * 9 +
@@ -162,7 +163,7 @@ lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int bat
   const int tiles = batch * (IMG / TR);
   hipStream_t st = ctx->stream;
   const int R = ctx->cfg.coarse;
-  hipLaunchKernelGGL(k_lift, dim3(batch), dim3(NB), 12 * R * R * sizeof(float), st, coarse, theta, R, ctx->x0,
+  hipLaunchKernelGGL(k_lift, dim3(batch, LIFT_SLICES), dim3(NB), 12 * R * R * sizeof(float), st, coarse, theta, R, ctx->x0,
                      ctx->base, ctx->scale);
   hipLaunchKernelGGL((k_conv<CIN, CH, 0>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->x0, ctx->w1f,
                      ctx->p + OFF_B1, nullptr, (void*)ctx->a1, tiles);

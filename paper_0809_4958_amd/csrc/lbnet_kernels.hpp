@@ -62,6 +62,8 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
                                              const float* __restrict__ theta, int R,
                                              __bf16* __restrict__ x0, float* __restrict__ base,
                                              float* __restrict__ scale) {
+  // workgroup (b, slice): rows slice * IMG / gridDim.y ... of image b; every
+  // slice recomputes the image's (few) coarse features
   const int b = blockIdx.x, tid = threadIdx.x;
   const float* c = coarse + (size_t)b * 12 * R * R;
   const int RR = R * R;
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
   }
   const double rms = sqrt(red[0] / (12.0 * RR));
   const float s = rms > 0.0 ? (float)rms : 1.0f;
-  if (tid == 0) scale[b] = s;
+  if (tid == 0 && blockIdx.y == 0) scale[b] = s;
   const float th = theta[b];
   // Sb and the temporal difference
   for (int i = tid; i < 3 * RR; i += NB) {
@@ -100,7 +102,8 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
         R >= 3 ? g[(vc + 1) * R + u] - 2.0f * g[vc * R + u] + g[(vc - 1) * R + u] : 0.0f;
   }
   __syncthreads();
-  for (int p = tid; p < IMG * IMG; p += NB) {
+  const int per = IMG * IMG / (int)gridDim.y, p_end = ((int)blockIdx.y + 1) * per;
+  for (int p = (int)blockIdx.y * per + tid; p < p_end; p += NB) {
     const int v = p / IMG, u = p - v * IMG;
     // corner-aligned bilinear weights (same integer mapping as the face grid)
     const int su = u * (R - 1), sv = v * (R - 1);
@@ -115,13 +118,19 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
       lifted[ch] = (1.0f - au) * (1.0f - av) * g[pv * R + pu] + au * (1.0f - av) * g[pv * R + pu1] +
                    (1.0f - au) * av * g[pv1 * R + pu] + au * av * g[pv1 * R + pu1];
     }
-    __bf16* xo = x0 + ((size_t)b * IMG * IMG + p) * CIN;
+    // the pixel's 16 channels as two 16-byte stores
+    bf16x8 lo, hi;
 #pragma unroll
-    for (int ch = 0; ch < 12; ch++) xo[ch] = to_bf16(lifted[ch] / s);
-    xo[12] = to_bf16(th);
-    xo[13] = to_bf16(4.0f * au * (1.0f - au));
-    xo[14] = to_bf16(4.0f * av * (1.0f - av));
-    xo[15] = to_bf16(0.0f);
+    for (int ch = 0; ch < 8; ch++) lo[ch] = to_bf16(lifted[ch] / s);
+#pragma unroll
+    for (int ch = 8; ch < 12; ch++) hi[ch - 8] = to_bf16(lifted[ch] / s);
+    hi[4] = to_bf16(th);
+    hi[5] = to_bf16(4.0f * au * (1.0f - au));
+    hi[6] = to_bf16(4.0f * av * (1.0f - av));
+    hi[7] = to_bf16(0.0f);
+    bf16x8* xo = (bf16x8*)(x0 + ((size_t)b * IMG * IMG + p) * CIN);
+    xo[0] = lo;
+    xo[1] = hi;
     float* bo = base + ((size_t)b * IMG * IMG + p) * 3;
 #pragma unroll
     for (int k = 0; k < 3; k++) bo[k] = lifted[k];
@@ -271,8 +280,9 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
       const int v = tid + j * NB;
       xr[j] = make_uint4(0u, 0u, 0u, 0u);
       if (v < XV) {
-        const int c8 = v % (CI / 8), q = v / (CI / 8);
-        const int xx = q % (IMG + 2) - 1, dyi = q / (IMG + 2), yy = y + dyi - 1;
+        // pixel fastest: neighbouring lanes fill neighbouring LDS columns
+        const int xx = v % (IMG + 2) - 1, q = v / (IMG + 2);
+        const int c8 = q % (CI / 8), dyi = q / (CI / 8), yy = y + dyi - 1;
         if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
           xr[j] = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
       }
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
       const int v = tid + j * NB;
       dr[j] = make_uint4(0u, 0u, 0u, 0u);
       if (v < DV) {
-        const int c8 = v % (CO / 8), px = v / (CO / 8);
+        const int px = v % IMG, c8 = v / IMG;
         dr[j] = *(const uint4*)&dz[(((size_t)b * IMG + y) * IMG + px) * CO + 8 * c8];
       }
     }
@@ -297,8 +307,8 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
     for (int j = 0; j < XS; j++) {
       const int v = tid + j * NB;
       if (v >= XV) continue;
-      const int c8 = v % (CI / 8), q = v / (CI / 8);
-      const int xx = q % (IMG + 2) - 1, dyi = q / (IMG + 2);
+      const int xx = v % (IMG + 2) - 1, q = v / (IMG + 2);
+      const int c8 = q % (CI / 8), dyi = q / (CI / 8);
       const __bf16* e = (const __bf16*)&xr[j];
 #pragma unroll
       for (int dxi = 0; dxi < 3; dxi++) {
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
     for (int j = 0; j < DS; j++) {
       const int v = tid + j * NB;
       if (v >= DV) continue;
-      const int c8 = v % (CO / 8), px = v / (CO / 8);
+      const int px = v % IMG, c8 = v / IMG;
       const __bf16* e = (const __bf16*)&dr[j];
 #pragma unroll
       for (int k = 0; k < 8; k++) sdz[(8 * c8 + k) * PP + px] = e[k];
