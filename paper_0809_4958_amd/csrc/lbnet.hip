@@ -182,7 +182,7 @@ lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size
   const int rows = batch * IMG;
   const int grid = std::min(rows, MAX_PART);
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NB), 0, st, x, dz, ctx->part, ctx->part_b, rows);
+  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NBC), 0, st, x, dz, ctx->part, ctx->part_b, rows);
   // two fixed-order stages: RSEG ranges of partials in parallel, then their sum
   const int nw = NTAP * CO * CI;
   hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, nw,

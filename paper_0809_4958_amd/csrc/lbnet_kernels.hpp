@@ -255,15 +255,16 @@ __global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, cons
 // workgroup (part[g][9][CO][CI], part_b[g][CO]), summed in a fixed order by
 // k_reduce_parts.
 template <int CI, int CO>
-__global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
+__global__ __launch_bounds__(NBC) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
                                               float* __restrict__ part, float* __restrict__ part_b,
                                               int n_rows) {
   constexpr int PP = IMG + 8;                       // padded pixel stride
   constexpr int TILES = NTAP * (CO / 16) * (CI / 16);
-  constexpr int TPW = (TILES + 3) / 4;              // tiles per wave
+  constexpr int NW = NBC / 64;                      // waves
+  constexpr int TPW = (TILES + NW - 1) / NW;        // tiles per wave
   constexpr int XV = 3 * (IMG + 2) * (CI / 8);      // 8-channel vectors of the three x rows
   constexpr int DV = IMG * (CO / 8);                // 8-channel vectors of the dz row
-  constexpr int XS = (XV + NB - 1) / NB, DS = (DV + NB - 1) / NB;
+  constexpr int XS = (XV + NBC - 1) / NBC, DS = (DV + NBC - 1) / NBC;
   __shared__ __attribute__((aligned(16))) __bf16 sdz[CO * PP];          // [co][px]
   __shared__ __attribute__((aligned(16))) __bf16 sxs[NTAP * CI * PP];  // [dx][dy][ci][px]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
     const int b = row / IMG, y = row - b * IMG;
 #pragma unroll
     for (int j = 0; j < XS; j++) {
-      const int v = tid + j * NB;
+      const int v = tid + j * NBC;
       xr[j] = make_uint4(0u, 0u, 0u, 0u);
       if (v < XV) {
         // pixel fastest: neighbouring lanes fill neighbouring LDS columns
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
     }
 #pragma unroll
     for (int j = 0; j < DS; j++) {
-      const int v = tid + j * NB;
+      const int v = tid + j * NBC;
       dr[j] = make_uint4(0u, 0u, 0u, 0u);
       if (v < DV) {
         const int px = v % IMG, c8 = v / IMG;
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
     // one source xx = px + dx in -1 .. 64
 #pragma unroll
     for (int j = 0; j < XS; j++) {
-      const int v = tid + j * NB;
+      const int v = tid + j * NBC;
       if (v >= XV) continue;
       const int xx = v % (IMG + 2) - 1, q = v / (IMG + 2);
       const int c8 = q % (CI / 8), dyi = q / (CI / 8);
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
     }
 #pragma unroll
     for (int j = 0; j < DS; j++) {
-      const int v = tid + j * NB;
+      const int v = tid + j * NBC;
       if (v >= DV) continue;
       const int px = v % IMG, c8 = v / IMG;
       const __bf16* e = (const __bf16*)&dr[j];
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
     }
 #pragma unroll
     for (int j = 0; j < TPW; j++) {
-      const int t = wave + 4 * j;
+      const int t = wave + NW * j;
       if (t >= TILES) break;
       const int tap = t / ((CO / 16) * (CI / 16));
       const int rem = t - tap * (CO / 16) * (CI / 16);
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(NB) void k_wgrad(const __bf16* __restrict__ x, cons
   float* pg = part + (size_t)blockIdx.x * NTAP * CO * CI;
 #pragma unroll
   for (int j = 0; j < TPW; j++) {
-    const int t = wave + 4 * j;
+    const int t = wave + NW * j;
     if (t >= TILES) break;
     const int tap = t / ((CO / 16) * (CI / 16));
     const int rem = t - tap * (CO / 16) * (CI / 16);
