@@ -1,6 +1,7 @@
 // lb_kernels.hpp -- gfx950 kernels of the fine-box lattice-Boltzmann step.
 //
-//   k_chain   one workgroup per chain: trilinear interpolation of the fluid
+//   k_chain   one workgroup per chain (one wavefront when the chains have at
+//             most 64 beads): trilinear interpolation of the fluid
 //             velocity at each bead from the pre-collision moments, the MD
 //             substeps (FENE, exact friction update, centre-of-mass pin) and
 //             the spreading records (stencil base, fractional offsets,

@@ -24,18 +24,28 @@ import argparse
 import csv
 import hashlib
 import os
+import re
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("lb_device.hpp", "lb_kernels.hpp", "lb_step.hip")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments, trailing blanks and blank lines, so that
+    editing a comment does not count as a change of the kernel."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash() -> str:
-    """SHA-1 (16 hex digits) of the step-kernel sources."""
+    """SHA-1 (16 hex digits) of the step-kernel sources' code (comments
+    excluded)."""
     h = hashlib.sha1()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(PKG, "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
