@@ -1,0 +1,83 @@
+"""Host-side measurement tools (no GPU): the kernel-source hash that ties a
+counter summary to the code it measured, the counter scaling of the traffic
+summary, the benchmark's use of a stale summary, and its one-GPU guard."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_0809_4958_amd import prof_summary  # noqa: E402
+
+
+def test_code_only_ignores_comments_and_blank_lines():
+    a = "int a = 1;  // one\n\n/* block\n   comment */ int b = 2;\n// whole line\nint c;\n"
+    b = "int a = 1;\nint b = 2;\nint c;  // edited comment\n"
+    assert prof_summary._code_only(a) == "int a = 1;\n int b = 2;\nint c;"
+    assert prof_summary._code_only(b) == "int a = 1;\nint b = 2;\nint c;"
+    # a change of code is a change
+    assert prof_summary._code_only("int a = 1;") != prof_summary._code_only("int a = 2;")
+
+
+def test_kernel_source_hash_is_stable():
+    h = prof_summary.kernel_source_hash()
+    assert len(h) == 16 and all(ch in "0123456789abcdef" for ch in h)
+    assert h == prof_summary.kernel_source_hash()
+
+
+def _write_counters(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+
+
+def test_traffic_scaling_by_the_copy_probe(tmp_path):
+    """Each counter is scaled by its own reading for the copy probe: a copy of
+    C bytes reads C and writes C, so FETCH_SIZE reading C/2 KiB-units gives a
+    factor 2 and WRITE_SIZE reading C gives 1 (the values seen on this GPU)."""
+    C = 1 << 28
+    fetch = tmp_path / "f.csv"
+    write = tmp_path / "w.csv"
+    lb = "void lbdev::k_lb<2, 2, false, 256>(lbdev::LbArgs)"
+    cp = "lbdev::k_copy(HIP_vector_type<unsigned int, 4u> const*, unsigned long)"
+    _write_counters(fetch, [(cp, "FETCH_SIZE", C / 2 / 1024), (cp, "FETCH_SIZE", C / 2 / 1024),
+                            (lb, "FETCH_SIZE", 3e9 / 2 / 1024)])
+    _write_counters(write, [(cp, "WRITE_SIZE", C / 1024), (lb, "WRITE_SIZE", 2e9 / 1024)])
+    out = tmp_path / "t.txt"
+    prof_summary.traffic(str(fetch), str(write), str(out), C, "cmd f", "cmd w", "test", "f16", 4e9)
+    vals = dict(ln.split(":", 1) for ln in out.read_text().splitlines() if ":" in ln and not ln.startswith("#"))
+    assert float(vals["fetch_scale"]) == pytest.approx(2.0)
+    assert float(vals["write_scale"]) == pytest.approx(1.0)
+    assert float(vals["hbm_read_bytes_per_launch"]) == pytest.approx(3e9)
+    assert float(vals["hbm_write_bytes_per_launch"]) == pytest.approx(2e9)
+    assert float(vals["traffic_over_algorithmic"]) == pytest.approx(5e9 / 4e9, rel=1e-4)
+    assert vals["kernel_sources_sha1"].strip() == prof_summary.kernel_source_hash()
+
+
+def test_bench_ignores_a_summary_of_other_kernel_sources(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    path = bench.traffic_file("f16", 256)
+    assert bench.committed_traffic("f16", 256) is None          # no summary
+    with open(path, "w") as fh:
+        fh.write(f"kernel_sources_sha1: {prof_summary.kernel_source_hash()}\nhbm_bytes_per_launch: 123.5\n")
+    assert bench.committed_traffic("f16", 256) == 123.5
+    with open(path, "w") as fh:
+        fh.write("kernel_sources_sha1: 0000000000000000\nhbm_bytes_per_launch: 123.5\n")
+    assert bench.committed_traffic("f16", 256) is None          # stale summary
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
