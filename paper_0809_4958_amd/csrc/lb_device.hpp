@@ -104,6 +104,7 @@ struct BoxDesc {
   int vec;              // interior rows handled as lane vectors (ITEM_ROWS) incl. the x-face nodes
   int ylog;             // log2 of the rows interleaved per population row (see aidx)
   int vw;               // row boxes: 32-bit words per lane vector (2 or 3)
+  int xf_off;           // row boxes: first float of the box's x-face velocities, else -1
 };
 
 struct Item {

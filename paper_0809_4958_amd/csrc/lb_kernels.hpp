@@ -372,6 +372,9 @@ struct LbArgs {
   const int4* check_items; // k_check workgroups: box, first plane, end plane
   const int* check_off;    // [n_boxes + 1] first k_check workgroup of each box
   double* mass_mom;        // [n_boxes][5]
+  float* xface;            // x-face velocities of the row boxes at t_n (k_xface)
+  const int4* xf_items;    // k_xface workgroups: box, first node, node count
+  int n_xf_items;
   int n_boxes;
   int reduce_every;
   double rho0, omega, om_bulk, om_ghost;
@@ -643,6 +646,18 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
       const int so = i * pib + (PRE ? ps : (1 - CZ[i]) * ps);
       vload<W>(rsrc, PRE ? voff : vo[1 - CY[i]], so, raw[i]);
     }
+    // boundary velocity of the lane's x-face node (first or last lane group of
+    // a row; L >= 2, so at most one), written by k_xface for this step and
+    // loaded together with the populations
+    const bool xface = act && (c == 0 || c == L - 1);
+    const int xside = c == 0 ? 0 : 1;
+    float xu[3] = {0.0f, 0.0f, 0.0f};
+    if (xface) {
+      const float* xf = A.xface + b.xf_off + 3 * ((xside * (b.nz - 2) + (z - 1)) * nyi + (y - 1));
+      xu[0] = xf[0];
+      xu[1] = xf[1];
+      xu[2] = xf[2];
+    }
     // neighbour elements of the populations shifted in x
     unsigned left[Q], right[Q];
 #pragma unroll
@@ -768,19 +783,21 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
       }
     }
     // x-face nodes of this row: boundary equilibrium at t_n (faces -x, +x)
-    if (act && (c == 0 || c == L - 1)) {
-#pragma unroll
-      for (int side = 0; side < 2; side++) {
-        if ((side == 0 && c != 0) || (side == 1 && c != L - 1)) continue;
-        const int qn[3] = {side == 0 ? 0 : nx - 1, y, z};
-        R u[3];
-        boundary_velocity<R>(b, side, qn, step, u);
-        R eq[Q];
-        eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
+    if (xface) {
+      R eq[Q];
+      eq_dev<R>((R)0, rho0, xu[0], xu[1], xu[2], eq);
+      // element indices stay compile-time constants (registers, not scratch)
+      if (xside == 0) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-          vput<S, W>(out[i], side == 0 ? 0 : V - 1, St::enc(eq[i], ke));
+          vput<S, W>(out[i], 0, St::enc(eq[i], ke));
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
+          vput<S, W>(out[i], V - 1, St::enc(eq[i], ke));
         }
       }
     }
@@ -1007,6 +1024,33 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
         }
       }
     }
+  }
+}
+
+// ----------------------------------------------------------- x-face velocities
+// Before the fused step: the boundary velocity u_b(y, t_n) of every x-face node
+// of the interior rows of the row boxes (faces -x and +x, interior y and z), so
+// that the row lanes that own those nodes read three floats instead of
+// evaluating the boundary source with dependent loads.  Node k of a box:
+// k = side (ny-2)(nz-2) + (z-1)(ny-2) + (y-1), velocity at xface[xf_off + 3k].
+template <int S>
+__global__ __launch_bounds__(WG) void k_xface(LbArgs A) {
+  using R = typename Store<S>::R;
+  if (__hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE) return;
+  const long long step = A.st->step;
+  const int4 w = A.xf_items[blockIdx.x];
+  const BoxDesc& b = A.boxes[w.x];
+  const int nyi = b.ny - 2, plane = nyi * (b.nz - 2);
+  for (int k = w.y + (int)threadIdx.x; k < w.y + w.z; k += WG) {
+    const int side = k / plane, r = k - side * plane;
+    const int zi = r / nyi, yi = r - zi * nyi;
+    const int q[3] = {side == 0 ? 0 : b.nx - 1, 1 + yi, 1 + zi};
+    R u[3];
+    boundary_velocity<R>(b, side, q, step, u);
+    float* o = A.xface + b.xf_off + 3 * k;
+    o[0] = (float)u[0];
+    o[1] = (float)u[1];
+    o[2] = (float)u[2];
   }
 }
 

@@ -53,6 +53,7 @@ struct BoxHost {
   int nbnd = 0;
   bool vec = false;  // interior rows as lane vectors (ITEM_ROWS), x-face nodes included
   int ylog = 0;      // log2 of the y lines interleaved per population row
+  int xf_off = -1;   // row boxes: first float of the x-face velocities
   int vw = 0;        // row boxes: 32-bit words per lane vector
 };
 
@@ -149,6 +150,9 @@ struct lb_ctx {
   double* d_partials = nullptr;    // [n_check][4]
   int n_check = 0;
   double* d_mass_mom = nullptr;
+  float* d_xface = nullptr;        // x-face velocities of the row boxes (k_xface)
+  int4* d_xf_items = nullptr;      // k_xface workgroups: box, first node, node count
+  int n_xf_items = 0;
   DevState* d_st = nullptr;
   ChainDesc* d_chains = nullptr;
   void* d_pos = nullptr;
@@ -547,6 +551,7 @@ lb_status upload_boxes(lb_ctx* ctx) {
     d.vec = b.vec ? 1 : 0;
     d.ylog = b.ylog;
     d.vw = b.vw;
+    d.xf_off = b.xf_off;
     for (int c = 0; c < 3; c++) {
       d.enc[c] = (float)(s2 / WD[c]);
       d.dec[c] = (float)(WD[c] / s2);
@@ -696,6 +701,9 @@ LbArgs make_args(lb_ctx* ctx, int pre, int advance, int reduce_every) {
   a.check_items = ctx->d_check_items;
   a.check_off = ctx->d_check_off;
   a.mass_mom = ctx->d_mass_mom;
+  a.xface = ctx->d_xface;
+  a.xf_items = ctx->d_xf_items;
+  a.n_xf_items = ctx->n_xf_items;
   a.n_boxes = (int)ctx->bx.size();
   a.reduce_every = reduce_every;
   a.rho0 = ctx->cfg.rho0;
@@ -719,12 +727,21 @@ hipEvent_t next_event(lb_ctx* ctx) {
 // One step on stream s: k_chain, k_lb, k_finalize.  ev3 (optional) receives
 // event records, st3 (optional) device timestamps, before k_chain, before
 // k_lb and after k_lb.
+// x-face velocities of the row boxes at the current device step
+void launch_xface(lb_ctx* ctx, hipStream_t s, const LbArgs& a) {
+  if (ctx->S == 1)
+    hipLaunchKernelGGL(k_xface<1>, dim3(ctx->n_xf_items), dim3(WG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_xface<2>, dim3(ctx->n_xf_items), dim3(WG), 0, s, a);
+}
+
 void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
                   long long* st3 = nullptr) {
   auto mark = [&](int k) {
     if (ev3) (void)hipEventRecord(ev3[k], s);
     if (st3) hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, st3 + k);
   };
+  if (ctx->n_xf_items) launch_xface(ctx, s, make_args(ctx, pre, 0, 0));
   mark(0);
   if (!ctx->ch.empty())
     ctx->chain_fn((int)ctx->ch.size(), s, ctx->d_boxes, ctx->d_chains, ctx->arena[0], ctx->arena[1],
@@ -923,6 +940,23 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     ctx->bx.push_back(b);
   }
   ctx->arena_elems = off;
+  // x-face velocity blocks of the row boxes (2 sides x interior y, z x 3
+  // floats) and the k_xface work list: chunks of at most 2048 nodes of a box
+  int64_t xf_floats = 0;
+  std::vector<int4> xf_items;
+  for (size_t bi = 0; bi < ctx->bx.size(); bi++) {
+    BoxHost& b = ctx->bx[bi];
+    if (!b.vec) continue;
+    const int64_t nodes = 2LL * (b.dim.ny - 2) * (b.dim.nz - 2);
+    if (xf_floats + 3 * nodes >= (1LL << 31)) {  // 32-bit offsets
+      lb_free(ctx);
+      return LB_ERR_ARG;
+    }
+    b.xf_off = (int)xf_floats;
+    xf_floats += 3 * nodes;
+    for (int64_t k = 0; k < nodes; k += 2048)
+      xf_items.push_back(make_int4((int)bi, (int)k, (int)std::min<int64_t>(2048, nodes - k), 0));
+  }
   // NULL is HIP's null stream (ordered with PyTorch's default stream)
   ctx->stream = (hipStream_t)cfg->stream;
   if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -936,9 +970,20 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   ctx->d_boxes = dalloc_t<BoxDesc>(ctx, ctx->bx.size(), &ok);
   ctx->d_mass_mom = dalloc_t<double>(ctx, 5 * ctx->bx.size(), &ok);
   ctx->d_st = dalloc_t<DevState>(ctx, 1, &ok);
+  if (!xf_items.empty()) {
+    ctx->d_xface = dalloc_t<float>(ctx, (size_t)xf_floats, &ok);
+    ctx->d_xf_items = dalloc_t<int4>(ctx, xf_items.size(), &ok);
+    ctx->n_xf_items = (int)xf_items.size();
+  }
   if (!ok) {
     lb_free(ctx);
     return LB_ERR_OOM;
+  }
+  if (!xf_items.empty() &&
+      (dzero(ctx, ctx->d_xface, (size_t)xf_floats * sizeof(float)) != hipSuccess ||
+       h2d(ctx, ctx->d_xf_items, xf_items.data(), xf_items.size() * sizeof(int4)) != hipSuccess)) {
+    lb_free(ctx);
+    return LB_ERR_HIP;
   }
   // rest state: all deviations zero, in both buffers
   if (dzero(ctx, ctx->arena[0], (size_t)off * sb) != hipSuccess ||
@@ -1439,6 +1484,7 @@ lb_status lb_autotune(lb_ctx* ctx, int32_t trials) {
   HIPCHK(hipEventCreate(&e1));
   auto time_now = [&](double* ms) -> lb_status {
     LbArgs a = make_args(ctx, 0, 0, 0);
+    if (ctx->n_xf_items) launch_xface(ctx, ctx->stream, a);  // x-face velocities of this step
     ctx->lb_fn(dim3(ctx->grid), ctx->stream, a);  // warm-up
     HIPCHK(hipEventRecord(e0, ctx->stream));
     for (int t = 0; t < trials; t++) ctx->lb_fn(dim3(ctx->grid), ctx->stream, a);
@@ -1574,6 +1620,8 @@ void lb_free(lb_ctx* ctx) {
   dfree(ctx, ctx->arena[1]);
   dfree(ctx, ctx->d_boxes);
   dfree(ctx, ctx->d_mass_mom);
+  dfree(ctx, ctx->d_xface);
+  dfree(ctx, ctx->d_xf_items);
   dfree(ctx, ctx->d_st);
   dfree(ctx, ctx->d_chains);
   dfree(ctx, ctx->d_pos);
