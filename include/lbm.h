@@ -122,7 +122,8 @@ typedef enum { LB_BC_AFFINE = 0, LB_BC_SAMPLED = 1, LB_BC_LEARNED = 2 } lb_bc_mo
  *            lower-index tangential axis), grid point p at node coordinate
  *            p (n-1)/(res-1) (corner aligned); u_b is bilinear on the face.
  *            A node on several faces takes the first face in the order above.
- *            FP64 if data_is_f64, else FP32.
+ *            FP64 if data_is_f64, else FP32.  2 <= res <= 8192 and
+ *            (largest box edge - 1)(res - 1) < 2^31, else LB_ERR_ARG.
  *   LEARNED: data = a DEVICE pointer the caller owns and keeps alive, FP32
  *            [n_samples][6][res][res][3] laid out as SAMPLED, used as a ring:
  *            step n reads slot ((n - t0) / dt) mod n_samples (and the next slot

@@ -283,9 +283,17 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
 // ----------------------------------------------------- boundary helpers
 // Velocity u_b of boundary node q on face f at step n (Sec. 2-3): affine
 // u_b = A(t_n)(q - x_c) or bilinear on the face x linear in time.
+// The time part, the same for every node of a box at step n: the samples k,
+// k1 and the weight th of the second (two = false: k alone).
 template <typename R>
-__device__ __forceinline__ void boundary_velocity(const BoxDesc& b, int f, const int q[3],
-                                                  long long n, R u[3]) {
+struct BcTime {
+  long long k, k1;
+  bool two;
+  R th;
+};
+
+template <typename R>
+__device__ __forceinline__ BcTime<R> bc_time(const BoxDesc& b, long long n) {
   long long rel = n - b.bc_t0;
   if (rel < 0) rel = 0;
   long long k = rel / b.bc_dt;
@@ -299,8 +307,21 @@ __device__ __forceinline__ void boundary_velocity(const BoxDesc& b, int f, const
     k = b.bc_ns - 1;
     rem = 0;
   }
-  bool two = rem > 0 && (b.bc_mode == 2 || k1 < b.bc_ns);
-  const R th = (R)rem / (R)b.bc_dt;
+  BcTime<R> tm;
+  tm.k = k;
+  tm.k1 = k1;
+  tm.two = rem > 0 && (b.bc_mode == 2 || k1 < b.bc_ns);
+  tm.th = (R)rem / (R)b.bc_dt;
+  return tm;
+}
+
+// The space part at node q of face f, given the time part of the step.
+template <typename R>
+__device__ __forceinline__ void boundary_velocity(const BoxDesc& b, int f, const int q[3],
+                                                  const BcTime<R>& tm, R u[3]) {
+  const long long k = tm.k, k1 = tm.k1;
+  const bool two = tm.two;
+  const R th = tm.th;
   if (b.bc_mode == 0) {
     const double* A0 = (const double*)b.bc + 9 * k;
     const double* A1 = A0 + 9;
@@ -325,26 +346,35 @@ __device__ __forceinline__ void boundary_velocity(const BoxDesc& b, int f, const
   const int n3[3] = {b.nx, b.ny, b.nz};
   const int nu = n3[au], nv = n3[av];
   const int Rr = b.bc_res;
-  const long long su = (long long)q[au] * (Rr - 1), sv = (long long)q[av] * (Rr - 1);
-  const int p = (int)(su / (nu - 1)), qq = (int)(sv / (nv - 1));
-  const R al = (R)(su - (long long)p * (nu - 1)) / (R)(nu - 1);
-  const R be = (R)(sv - (long long)qq * (nv - 1)) / (R)(nv - 1);
+  // cell and fraction in exact integer arithmetic, 32-bit (lb_set_boundary
+  // keeps (n - 1)(res - 1) below 2^31): a per-lane 64-bit division costs
+  // an order of magnitude more instructions
+  const unsigned du = (unsigned)(nu - 1), dv = (unsigned)(nv - 1);
+  const unsigned su = (unsigned)q[au] * (unsigned)(Rr - 1), sv = (unsigned)q[av] * (unsigned)(Rr - 1);
+  const unsigned pu = su / du, pv = sv / dv;
+  const int p = (int)pu, qq = (int)pv;
+  const R al = (R)(int)(su - pu * du) / (R)(nu - 1);
+  const R be = (R)(int)(sv - pv * dv) / (R)(nv - 1);
   const int p1 = p + 1 < Rr ? p + 1 : p, q1 = qq + 1 < Rr ? qq + 1 : qq;
-  const R* Sb = (const R*)b.bc;
-  const size_t fs = (size_t)Rr * Rr * 3;
+  // the three components of a grid point are adjacent: one vector load per
+  // corner (scattered gathers are limited by the address rate, not bytes)
+  struct V3 {
+    R c[3];
+  };
+  const V3* Sb = (const V3*)b.bc;
+  const size_t fs = (size_t)Rr * Rr;
   R v0[3], v1[3] = {0, 0, 0};
 #pragma unroll
   for (int t = 0; t < 2; t++) {
     if (t == 1 && !two) break;
-    const R* Sk = Sb + ((size_t)(t ? k1 : k) * 6 + f) * fs;
+    const V3* Sk = Sb + ((size_t)(t ? k1 : k) * 6 + f) * fs;
     R* out = t ? v1 : v0;
+    const V3 s00 = Sk[(size_t)qq * Rr + p], s01 = Sk[(size_t)qq * Rr + p1];
+    const V3 s10 = Sk[(size_t)q1 * Rr + p], s11 = Sk[(size_t)q1 * Rr + p1];
 #pragma unroll
-    for (int cmp = 0; cmp < 3; cmp++) {
-      const R s00 = Sk[((size_t)qq * Rr + p) * 3 + cmp], s01 = Sk[((size_t)qq * Rr + p1) * 3 + cmp];
-      const R s10 = Sk[((size_t)q1 * Rr + p) * 3 + cmp], s11 = Sk[((size_t)q1 * Rr + p1) * 3 + cmp];
-      out[cmp] = ((R)1 - al) * ((R)1 - be) * s00 + al * ((R)1 - be) * s01 + ((R)1 - al) * be * s10 +
-                 al * be * s11;
-    }
+    for (int cmp = 0; cmp < 3; cmp++)
+      out[cmp] = ((R)1 - al) * ((R)1 - be) * s00.c[cmp] + al * ((R)1 - be) * s01.c[cmp] +
+                 ((R)1 - al) * be * s10.c[cmp] + al * be * s11.c[cmp];
   }
 #pragma unroll
   for (int cmp = 0; cmp < 3; cmp++) u[cmp] = two ? ((R)1 - th) * v0[cmp] + th * v1[cmp] : v0[cmp];
@@ -830,6 +860,7 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
   const long long pib = nxb << yl, bkb = Q * pib;
   const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
   const int q_end = it.x0 + it.ex;
+  const BcTime<R> tm = bc_time<R>(b, step);
 #pragma unroll 1
   for (int q = it.x0 + (int)threadIdx.x; q < q_end; q += BS) {
     const int fr = q / L;
@@ -854,7 +885,7 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
       const int f = x == 0 ? 0 : (x == nx - 1 ? 1 : (y == 0 ? 2 : (y == ny - 1 ? 3 : (z == 0 ? 4 : 5))));
       const int qn[3] = {x, y, z};
       R u[3];
-      boundary_velocity<R>(b, f, qn, step, u);
+      boundary_velocity<R>(b, f, qn, tm, u);
       R eq[Q];
       eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
 #pragma unroll
@@ -995,6 +1026,7 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
     } else {
       // boundary chunk: equilibrium at rho0 and u_b(t_n) for the populations
       // that stream into the interior
+      const BcTime<R> tm = bc_time<R>(b, step);
       for (int k = it.x0 + tid; k < it.x0 + it.ex; k += BS) {
         int r = 0, kk = k;
         while (r < b.n_rect - 1 && kk >= b.rect_cnt[r]) {
@@ -1008,7 +1040,7 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
         q[1] = b.rect_start[r][1] + (kk / lx) % ly;
         q[2] = b.rect_start[r][2] + kk / (lx * ly);
         R u[3];
-        boundary_velocity<R>(b, f, q, step, u);
+        boundary_velocity<R>(b, f, q, tm, u);
         R eq[Q];
         eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
 #pragma unroll
@@ -1033,6 +1065,8 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
 // that the row lanes that own those nodes read three floats instead of
 // evaluating the boundary source with dependent loads.  Node k of a box:
 // k = side (ny-2)(nz-2) + (z-1)(ny-2) + (y-1), velocity at xface[xf_off + 3k].
+constexpr int XF_NODES = 4;  // x-face nodes per k_xface thread
+
 template <int S>
 __global__ __launch_bounds__(WG) void k_xface(LbArgs A) {
   using R = typename Store<S>::R;
@@ -1041,16 +1075,23 @@ __global__ __launch_bounds__(WG) void k_xface(LbArgs A) {
   const int4 w = A.xf_items[blockIdx.x];
   const BoxDesc& b = A.boxes[w.x];
   const int nyi = b.ny - 2, plane = nyi * (b.nz - 2);
-  for (int k = w.y + (int)threadIdx.x; k < w.y + w.z; k += WG) {
+  const BcTime<R> tm = bc_time<R>(b, step);
+  // XF_NODES independent nodes per thread, unrolled so that their sample loads
+  // are in flight together
+#pragma unroll
+  for (int j = 0; j < XF_NODES; j++) {
+    const int k = w.y + (int)threadIdx.x + j * WG;
+    if (k >= w.y + w.z) break;
     const int side = k / plane, r = k - side * plane;
     const int zi = r / nyi, yi = r - zi * nyi;
     const int q[3] = {side == 0 ? 0 : b.nx - 1, 1 + yi, 1 + zi};
     R u[3];
-    boundary_velocity<R>(b, side, q, step, u);
-    float* o = A.xface + b.xf_off + 3 * k;
-    o[0] = (float)u[0];
-    o[1] = (float)u[1];
-    o[2] = (float)u[2];
+    boundary_velocity<R>(b, side, q, tm, u);
+    // one 12-byte store per lane: a wavefront writes 768 contiguous bytes
+    struct F3 {
+      float c[3];
+    };
+    *(F3*)(A.xface + b.xf_off + 3 * k) = F3{{(float)u[0], (float)u[1], (float)u[2]}};
   }
 }
 

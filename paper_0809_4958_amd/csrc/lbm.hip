@@ -724,9 +724,6 @@ hipEvent_t next_event(lb_ctx* ctx) {
   return ctx->ev[ctx->ev_used++];
 }
 
-// One step on stream s: k_chain, k_lb, k_finalize.  ev3 (optional) receives
-// event records, st3 (optional) device timestamps, before k_chain, before
-// k_lb and after k_lb.
 // x-face velocities of the row boxes at the current device step
 void launch_xface(lb_ctx* ctx, hipStream_t s, const LbArgs& a) {
   if (ctx->S == 1)
@@ -735,6 +732,9 @@ void launch_xface(lb_ctx* ctx, hipStream_t s, const LbArgs& a) {
     hipLaunchKernelGGL(k_xface<2>, dim3(ctx->n_xf_items), dim3(WG), 0, s, a);
 }
 
+// One step on stream s: k_xface, k_chain, k_lb, k_check, k_finalize.  ev3
+// (optional) receives event records, st3 (optional) device timestamps, before
+// k_chain, before k_lb and after k_lb.
 void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
                   long long* st3 = nullptr) {
   auto mark = [&](int k) {
@@ -941,7 +941,8 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   }
   ctx->arena_elems = off;
   // x-face velocity blocks of the row boxes (2 sides x interior y, z x 3
-  // floats) and the k_xface work list: chunks of at most 2048 nodes of a box
+  // floats) and the k_xface work list: chunks of at most XF_NODES x 256 nodes
+  // of a box (each thread evaluates XF_NODES nodes with their loads overlapped)
   int64_t xf_floats = 0;
   std::vector<int4> xf_items;
   for (size_t bi = 0; bi < ctx->bx.size(); bi++) {
@@ -954,8 +955,8 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     }
     b.xf_off = (int)xf_floats;
     xf_floats += 3 * nodes;
-    for (int64_t k = 0; k < nodes; k += 2048)
-      xf_items.push_back(make_int4((int)bi, (int)k, (int)std::min<int64_t>(2048, nodes - k), 0));
+    for (int64_t k = 0; k < nodes; k += XF_NODES * WG)
+      xf_items.push_back(make_int4((int)bi, (int)k, (int)std::min<int64_t>(XF_NODES * WG, nodes - k), 0));
   }
   // NULL is HIP's null stream (ordered with PyTorch's default stream)
   ctx->stream = (hipStream_t)cfg->stream;
@@ -1056,6 +1057,12 @@ lb_status lb_set_boundary(lb_ctx* ctx, int32_t box, const lb_boundary* bc) {
   if (bc->mode != LB_BC_AFFINE && (bc->res < 2 || bc->res > 8192))
     return fail(ctx, LB_ERR_ARG, "sampled boundary needs res >= 2");
   BoxHost& b = ctx->bx[box];
+  if (bc->mode != LB_BC_AFFINE) {
+    // the face-grid cell is found in 32-bit integer arithmetic
+    const int64_t nmax = std::max(b.dim.nx, std::max(b.dim.ny, b.dim.nz));
+    if ((nmax - 1) * (int64_t)(bc->res - 1) >= (int64_t)1 << 31)
+      return fail(ctx, LB_ERR_ARG, "(box edge - 1) * (res - 1) must stay below 2^31");
+  }
   if (bc->mode == LB_BC_LEARNED) {
     // caller-owned device ring, read in place
     if (ctx->S == LB_STORE_F64 || bc->data_is_f64)
