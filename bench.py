@@ -7,13 +7,13 @@ kinematic-simulation tracer boundary history (sampled faces, 17x17 corner-aligne
 grid every 20 steps), each with one 32-bead FENE chain, D3Q19 MRT tau = 0.6,
 FP32 compute with FP16-deviation population storage, all boxes advanced by one
 fused launch per step, steps replayed from captured HIP graphs.  A step is one
-pass of the whole path: chain kernel (interpolation, MD substeps, spreading
-records) + fused collide/stream over every box and boundary face + the
-mass/momentum finalisation.
+pass of the whole path: x-face boundary velocities + chain kernel
+(interpolation, MD substeps, spreading records) + fused collide/stream over
+every box and boundary face + the mass/momentum check and finalisation.
 
 Prints one JSON line: MLUPS over interior nodes; the HBM roofline of the fused
-kernel (its average duration from HIP events recorded inside the replayed
-graphs, the measured copy ceiling, and the HBM traffic of the committed
+kernel (its average duration from device timestamps that the kernels record
+inside the replayed graphs, the measured copy ceiling, and the HBM traffic of the committed
 counter run when it was taken on the current kernel sources); the same boxes
 run one by one as plain FP32 single-box contexts for the gain; and the oracle
 leg: the FP64 oracle's own throughput on the host cores and the FP16 velocity
@@ -165,7 +165,7 @@ def main():
     ctx.step(args.warmup)
     ctx.sync()
     torch.cuda.synchronize()
-    # timed region: exactly K steps; HIP events inside the replayed graphs
+    # timed region: exactly K steps; device timestamps inside the replayed graphs
     elapsed, tm = time_steps(ctx, args.steps, torch)
     ms_step = elapsed * 1e3 / args.steps
     mlups = interior * args.steps / elapsed / 1e6
@@ -210,7 +210,8 @@ def main():
             "traffic": traffic,
             "kernel": "k_lb (fused collide-stream + boundary faces + spreading gather)",
             "kernel_ms": round(lb_ms, 4),
-            "chain_kernel_ms": round(tm[2], 4),
+            # x-face boundary velocities + chain kernel, per step
+            "pre_lb_kernels_ms": round(tm[2], 4),
             "algorithmic_bytes_per_launch": alg_bytes,
             "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1),
             "kernel_sources_sha1": kernel_source_hash(),

@@ -202,11 +202,16 @@ lb_status lb_sync(lb_ctx* ctx);
  * the state), keeps the fastest and records it in lb_config.tune_cache. */
 lb_status lb_autotune(lb_ctx* ctx, int32_t trials);
 
-/* Averages of the last lb_step call measured with HIP events on the context
- * stream: [0] ms per step of the whole step, [1] ms per launch of the fused
- * collide-stream kernel, [2] ms per launch of the chain kernel (0 if none),
- * [3] algorithmic bytes per collide-stream launch (2*19*bytes per population
- * per interior node).  Requires lb_set_timing(ctx, 1) before the lb_step. */
+/* Averages of the last lb_step call: [0] ms per step of the whole step, [1] ms
+ * per launch of the fused collide-stream kernel, [2] ms per step of the
+ * kernels that precede it (x-face boundary velocities and chains; 0 if
+ * neither), [3] algorithmic bytes per collide-stream launch (2*19*bytes per
+ * population per interior node).  Steps launched one by one are timed with
+ * HIP events on the context stream; inside graph-replayed chunks the kernels
+ * themselves record the device wall clock at their start (one store by the
+ * first thread of the first workgroup), so each figure runs from the start of
+ * one kernel to the start of the next.  Requires lb_set_timing(ctx, 1) before
+ * the lb_step. */
 lb_status lb_set_timing(lb_ctx* ctx, int32_t on);
 lb_status lb_get_timing(lb_ctx* ctx, double out[4]);
 

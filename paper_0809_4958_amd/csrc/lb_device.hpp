@@ -147,8 +147,17 @@ template <> struct Store<1> {
 template <> struct Store<2> {
   using T = _Float16;
   using R = float;
-  __device__ static R dec(T v, float k) { return (float)v * k; }
-  __device__ static T enc(R v, float k) { return (_Float16)(v * k); }
+  // product rounded to FP32 in both directions, never fused into a
+  // neighbouring add or conversion: every kernel (pulled or in-place reads,
+  // state upload, readout) then decodes and encodes a value identically
+  __device__ static R dec(T v, float k) {
+#pragma clang fp contract(off)
+    return (float)v * k;
+  }
+  __device__ static T enc(R v, float k) {
+#pragma clang fp contract(off)
+    return (_Float16)(v * k);
+  }
 };
 
 template <typename R>

@@ -6,7 +6,6 @@
 //   k_set_pre / k_read / k_read_sites / k_read_beads   state upload and readout.
 //   k_copy      16-byte stream copy in contiguous per-workgroup chunks (HBM
 //               ceiling probe).
-//   k_stamp     device wall-clock timestamp (timing inside captured graphs).
 #pragma once
 #include "lb_kernels.hpp"
 
@@ -17,6 +16,7 @@ namespace lbdev {
 // its own launch so that the fused kernel needs no device-wide fences.
 __global__ __launch_bounds__(WG) void k_finalize(LbArgs A) {
   const int tid = threadIdx.x;
+  put_stamp(A.stamp_after);
   if (A.st->err_key != ERR_NONE) return;
   const long long step = A.st->step;
   const bool check = A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0;
@@ -195,12 +195,6 @@ __global__ __launch_bounds__(WG) void k_copy(const uint4* __restrict__ src_, uin
     __builtin_nontemporal_store(d, &dst[i + 3 * WG]);
   }
   for (; i < b1; i += WG) __builtin_nontemporal_store(src[i], &dst[i]);
-}
-
-// one constant-rate device timestamp (hipDeviceAttributeWallClockRate kHz),
-// stored with a vector store
-__global__ void k_stamp(long long* slot) {
-  if (threadIdx.x == 0) *slot = wall_clock64();
 }
 
 }  // namespace lbdev

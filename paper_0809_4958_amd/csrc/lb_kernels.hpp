@@ -35,6 +35,13 @@ constexpr int MAX_BOX_CHAINS = 64;
 #define LB_STORE_POLICY 2
 #endif
 
+// Timing inside captured graphs: thread 0 of workgroup 0 (dispatched first)
+// records the constant-rate device clock (hipDeviceAttributeWallClockRate kHz)
+// when its kernel starts, with a vector store; p = NULL records nothing.
+__device__ __forceinline__ void put_stamp(long long* p) {
+  if (p && blockIdx.x == 0 && threadIdx.x == 0) *p = wall_clock64();
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -55,13 +62,15 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
                                               typename Store<S>::R* __restrict__ rec_d,
                                               typename Store<S>::R* __restrict__ rec_dp,
                                               int* __restrict__ bbox, DevState* __restrict__ st,
-                                              double rho0_d, int pre) {
+                                              double rho0_d, int pre, long long* stamp) {
   using R = typename Store<S>::R;
   const int ci = blockIdx.x;
+  // inputs read before the timestamp store (see k_check)
   const ChainDesc c = chains[ci];
-  const BoxDesc& b = boxes[c.box];
-  if (__hip_atomic_load(&st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE)
-    return;
+  const BoxDesc b = boxes[c.box];
+  const bool latched = __hip_atomic_load(&st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
+  put_stamp(stamp);
+  if (latched) return;
   const R rho0 = (R)rho0_d;
   const long long step = st->step;
   const int par = (int)(step & 1);
@@ -402,6 +411,9 @@ struct LbArgs {
   const int4* check_items; // k_check workgroups: box, first plane, end plane
   const int* check_off;    // [n_boxes + 1] first k_check workgroup of each box
   double* mass_mom;        // [n_boxes][5]
+  long long* stamp_first;  // timed graphs: start of the step's first kernel,
+  long long* stamp_lb;     // of k_lb,
+  long long* stamp_after;  // and of the first kernel after k_lb (else NULL)
   float* xface;            // x-face velocities of the row boxes at t_n (k_xface)
   const int4* xf_items;    // k_xface workgroups: box, first node, node count
   int n_xf_items;
@@ -941,15 +953,16 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
 // ----------------------------------------------------------- fused step
 
 // Resident waves per SIMD the step kernel is compiled for: the most that fit
-// without spilling (VGPRs per lane: 512 / waves).  FP64 4; FP32 MRT 4 (125-126
-// VGPRs), FP32 BGK 3 (152); FP16 MRT 3 (161-165), FP16 BGK 2 (188).  Left to
-// itself the allocator lands just above a boundary and runs one wave fewer,
-// measured 5-11% slower.
+// without spilling (VGPRs per lane: 512 / waves).  FP64 BGK 2 (189 VGPRs), MRT
+// 3 (135), MRT with ghost rate 1 4 (125); FP32 MRT 4 (118-126), FP32 BGK 3;
+// FP16 MRT 3 (153-165), FP16 BGK 2 (186-188).  Left to itself the allocator
+// lands just above a boundary and runs one wave fewer, measured 5-11% slower.
 constexpr int lb_min_waves(int S, int COLL) {
+  return S == 0 ? (COLL == 0 ? 2 : (COLL == 1 ? 3 : 4))
 #ifdef LB_MIN_WAVES
-  return S == 0 ? 4 : LB_MIN_WAVES;
+                : LB_MIN_WAVES;
 #else
-  return S == 0 ? 4 : (S == 1 ? (COLL == 0 ? 3 : 4) : (COLL == 0 ? 2 : 3));
+                : (S == 1 ? (COLL == 0 ? 3 : 4) : (COLL == 0 ? 2 : 3));
 #endif
 }
 
@@ -960,6 +973,8 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
   using R = typename St::R;
 
   const int tid = threadIdx.x;
+  put_stamp(A.stamp_first);
+  put_stamp(A.stamp_lb);
   const bool skip =
       __hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
   if (skip) return;  // uniform: the latch is set before this launch or not at all
@@ -1070,10 +1085,14 @@ constexpr int XF_NODES = 4;  // x-face nodes per k_xface thread
 template <int S>
 __global__ __launch_bounds__(WG) void k_xface(LbArgs A) {
   using R = typename Store<S>::R;
-  if (__hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE) return;
+  // inputs read before the timestamp store (see k_check)
+  const bool latched =
+      __hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
   const long long step = A.st->step;
   const int4 w = A.xf_items[blockIdx.x];
-  const BoxDesc& b = A.boxes[w.x];
+  const BoxDesc b = A.boxes[w.x];
+  put_stamp(A.stamp_first);
+  if (latched) return;
   const int nyi = b.ny - 2, plane = nyi * (b.nz - 2);
   const BcTime<R> tm = bc_time<R>(b, step);
   // XF_NODES independent nodes per thread, unrolled so that their sample loads
@@ -1109,38 +1128,55 @@ __global__ __launch_bounds__(WG) void k_check(LbArgs A) {
   using T = typename St::T;
   __shared__ double sred[4][WG / 64];
   const int tid = threadIdx.x, w = blockIdx.x;
-  if (__hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE) return;
+  // everything read before the timestamp store, which the compiler cannot
+  // tell apart from the descriptor tables (after it, they would be re-read per
+  // lane instead of through scalar loads)
+  const bool latched =
+      __hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
   const long long step = A.st->step;
+  const int4 cw = A.check_items[w];  // box, first plane, end plane
+  const BoxDesc b = A.boxes[cw.x];
+  put_stamp(A.stamp_after);
+  if (latched) return;
   if (!(A.reduce_every > 0 && ((step + 1) % A.reduce_every) == 0)) return;
   const int par = (int)(step & 1);
-  const int4 cw = A.check_items[w];  // box, first plane, end plane
-  const BoxDesc& b = A.boxes[cw.x];
   const T* __restrict__ arena = (const T*)(par ? A.a0 : A.a1) + b.off;  // written by this step
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (!PER && b.nx % 8 == 0) {
     // chunks of 8 consecutive nodes of a row, every population read as
     // 16-byte vectors (rows start 16-byte aligned: box offsets are multiples
-    // of 128 elements and 8 nodes span 16 bytes or a multiple of it)
+    // of 128 elements and 8 nodes span 16 bytes or a multiple of it).  The
+    // node's own populations are always inside the box, so all of them are
+    // loaded before any is tested (no load waits behind a branch); selects,
+    // not products, drop the ones that stream out of the fluid, so that
+    // whatever a boundary node holds in them never enters a sum.
+    constexpr int NV = 8 * (int)sizeof(T) / 16;
     const int cpr = b.nx / 8;
     const int n_chunks = (cw.z - cw.y) * b.ny * cpr;
     for (int p = tid; p < n_chunks; p += WG) {
       const int row = p / cpr, c = p - row * cpr;
       const int zz = row / b.ny, y = row - zz * b.ny, z = cw.y + zz;
       const int x0 = 8 * c;
+      uint4 raw[Q][NV];
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const uint4* src = (const uint4*)(arena + aidx(b, i, x0, y, z));
+#pragma unroll
+        for (int q = 0; q < NV; q++) raw[i][q] = src[q];
+      }
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const int ty = y + CY[i], tz = z + CZ[i];
-        if (ty < 1 || ty > b.ny - 2 || tz < 1 || tz > b.nz - 2) continue;
-        T v[8];
-        const uint4* src = (const uint4*)(arena + aidx(b, i, x0, y, z));
-#pragma unroll
-        for (int q = 0; q < 8 * (int)sizeof(T) / 16; q++) ((uint4*)v)[q] = src[q];
+        const bool row_in = ty >= 1 && ty <= b.ny - 2 && tz >= 1 && tz <= b.nz - 2;
+        const T* v = (const T*)raw[i];
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < 8; k++) {
           const int tx = x0 + k + CX[i];
-          if (tx >= 1 && tx <= b.nx - 2) sum += (double)St::dec(v[k], b.dec[WCLS[i]]);
+          const double d = (double)St::dec(v[k], b.dec[WCLS[i]]);
+          sum += (tx >= 1 && tx <= b.nx - 2) ? d : 0.0;
         }
+        sum = row_in ? sum : 0.0;
         acc[0] += sum;
         if (CX[i]) acc[1] += CX[i] * sum;
         if (CY[i]) acc[2] += CY[i] * sum;
@@ -1148,11 +1184,15 @@ __global__ __launch_bounds__(WG) void k_check(LbArgs A) {
       }
     }
   } else {
-    // node by node; a slab holds fewer than 2^31 nodes (32-bit indices)
+    // node by node; a slab holds fewer than 2^31 nodes (32-bit indices);
+    // loads first and selects after, as above
     const int n_slab = (cw.z - cw.y) * b.ny * b.nx;
     for (int p = tid; p < n_slab; p += WG) {
       const int row = p / b.nx, x = p - row * b.nx;
       const int zz = row / b.ny, y = row - zz * b.ny, z = cw.y + zz;
+      T raw[Q];
+#pragma unroll
+      for (int i = 0; i < Q; i++) raw[i] = arena[aidx(b, i, x, y, z)];
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
@@ -1161,8 +1201,8 @@ __global__ __launch_bounds__(WG) void k_check(LbArgs A) {
           if (b.pmask & 2) ty = wrapc(ty, b.ny);
           if (b.pmask & 4) tz = wrapc(tz, b.nz);
         }
-        if (!is_interior(b, tx, ty, tz)) continue;
-        const double v = (double)St::dec(arena[aidx(b, i, x, y, z)], b.dec[WCLS[i]]);
+        const double d = (double)St::dec(raw[i], b.dec[WCLS[i]]);
+        const double v = is_interior(b, tx, ty, tz) ? d : 0.0;
         acc[0] += v;
         if (CX[i]) acc[1] += CX[i] * v;
         if (CY[i]) acc[2] += CY[i] * v;

@@ -16,7 +16,7 @@ namespace lbhost {
 using LbLaunch = void (*)(dim3, hipStream_t, const lbdev::LbArgs&);
 using ChainLaunch = void (*)(int, hipStream_t, const lbdev::BoxDesc*, const lbdev::ChainDesc*,
                              const void*, const void*, void*, void*, int, int4*, void*, void*, int*,
-                             lbdev::DevState*, double, int);
+                             lbdev::DevState*, double, int, long long*);
 
 // fused step launcher: storage S (0 FP64, 1 FP32, 2 FP16 deviations), collision
 // C (0 BGK, 1 MRT, 2 MRT with ghost rate 1), periodic or not

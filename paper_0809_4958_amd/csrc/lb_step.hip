@@ -29,11 +29,13 @@ template LbLaunch pick_lb<LB_S, LB_C>(bool);
 template <int S, bool P, int CB>
 void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc* chains,
                   const void* a0, const void* a1, void* pos, void* vel, int total, int4* rb,
-                  void* rd, void* rp, int* bbox, DevState* st, double rho0, int pre) {
+                  void* rd, void* rp, int* bbox, DevState* st, double rho0, int pre,
+                  long long* stamp) {
   using T = typename Store<S>::T;
   using R = typename Store<S>::R;
   hipLaunchKernelGGL((k_chain<S, P, CB>), dim3(nch), dim3(CB), 0, s, boxes, chains, (const T*)a0,
-                     (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox, st, rho0, pre);
+                     (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox, st, rho0, pre,
+                     stamp);
 }
 
 template <int S>

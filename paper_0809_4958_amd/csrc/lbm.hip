@@ -733,26 +733,42 @@ void launch_xface(lb_ctx* ctx, hipStream_t s, const LbArgs& a) {
 }
 
 // One step on stream s: k_xface, k_chain, k_lb, k_check, k_finalize.  ev3
-// (optional) receives event records, st3 (optional) device timestamps, before
-// k_chain, before k_lb and after k_lb.
+// (optional) receives event records before the first kernel, before k_lb and
+// after k_lb; st3 (optional, inside captured graphs) receives device
+// timestamps from the kernels themselves: the start of the step's first
+// kernel, of k_lb, and of the kernel after k_lb.
 void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
                   long long* st3 = nullptr) {
-  auto mark = [&](int k) {
-    if (ev3) (void)hipEventRecord(ev3[k], s);
-    if (st3) hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, st3 + k);
-  };
-  if (ctx->n_xf_items) launch_xface(ctx, s, make_args(ctx, pre, 0, 0));
-  mark(0);
-  if (!ctx->ch.empty())
+  const bool xf = ctx->n_xf_items > 0, chains = !ctx->ch.empty();
+  if (ev3) (void)hipEventRecord(ev3[0], s);
+  if (xf) {
+    LbArgs xa = make_args(ctx, pre, 0, 0);
+    if (st3) xa.stamp_first = st3;
+    launch_xface(ctx, s, xa);
+  }
+  if (chains)
     ctx->chain_fn((int)ctx->ch.size(), s, ctx->d_boxes, ctx->d_chains, ctx->arena[0], ctx->arena[1],
                   ctx->d_pos, ctx->d_vel, ctx->total_beads, ctx->d_rec_base, ctx->d_rec_d,
-                  ctx->d_rec_dp, ctx->d_bbox, ctx->d_st, ctx->cfg.rho0, pre);
-  mark(1);
-  const LbArgs a = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
+                  ctx->d_rec_dp, ctx->d_bbox, ctx->d_st, ctx->cfg.rho0, pre,
+                  (st3 && !xf) ? st3 : nullptr);
+  if (ev3) (void)hipEventRecord(ev3[1], s);
+  LbArgs a = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
+  if (st3) {
+    a.stamp_lb = st3 + 1;
+    if (!xf && !chains) a.stamp_first = st3;
+  }
   ctx->lb_fn(dim3(ctx->grid), s, a);
-  mark(2);
-  if (ctx->cfg.reduce_every > 0) ctx->check_fn(ctx->n_check, s, a);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, s, a);
+  if (ev3) (void)hipEventRecord(ev3[2], s);
+  LbArgs t = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
+  const bool check = ctx->cfg.reduce_every > 0;
+  if (check) {
+    if (st3) t.stamp_after = st3 + 2;
+    ctx->check_fn(ctx->n_check, s, t);
+    t.stamp_after = nullptr;
+  } else if (st3) {
+    t.stamp_after = st3 + 2;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, s, t);
 }
 
 void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed) {
@@ -1174,8 +1190,8 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
   }
   const int gs = ctx->cfg.graph_steps;
   if (gs > 0 && timed && left >= gs) {
-    // HIP events recorded inside a graph cannot be timed: the timed graphs
-    // carry timestamp kernels instead
+    // HIP events recorded inside a graph cannot be timed: in the timed graphs
+    // the kernels record device timestamps themselves
     if (!ctx->gexec_t[0] || ctx->gsteps_t != gs) {
       drop_graph(ctx);
       drop_stamps(ctx);
