@@ -48,9 +48,20 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// x-face boundary velocities of one work item by one wavefront (defined with
+// k_xface below)
+template <int S>
+__device__ __forceinline__ void xface_wave(const BoxDesc* __restrict__ boxes,
+                                           const int4* __restrict__ items, int item,
+                                           float* __restrict__ xface, DevState* __restrict__ st,
+                                           long long* stamp);
+
 // ---------------------------------------------------------------- chain
 // CB threads per chain (one per bead): 64 when no chain has more than 64
 // beads (one wavefront, so the workgroup barriers are nearly free), else 256.
+// Workgroups n_chains and up compute the x-face boundary velocities of the
+// step instead (CB / 64 work items each), so the two independent pieces of
+// work before the fused step share one launch and run side by side.
 template <int S, bool PER, int CB>
 __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
                                               const ChainDesc* __restrict__ chains,
@@ -62,9 +73,17 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
                                               typename Store<S>::R* __restrict__ rec_d,
                                               typename Store<S>::R* __restrict__ rec_dp,
                                               int* __restrict__ bbox, DevState* __restrict__ st,
-                                              double rho0_d, int pre, long long* stamp) {
+                                              double rho0_d, int pre, long long* stamp,
+                                              int n_chains, const int4* __restrict__ xf_items,
+                                              int n_xf_items, float* __restrict__ xface) {
   using R = typename Store<S>::R;
   const int ci = blockIdx.x;
+  if (ci >= n_chains) {
+    const int item = (ci - n_chains) * (CB / 64) +
+                     __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    if (item < n_xf_items) xface_wave<S>(boxes, xf_items, item, xface, st, nullptr);
+    return;
+  }
   // inputs read before the timestamp store (see k_check)
   const ChainDesc c = chains[ci];
   const BoxDesc b = boxes[c.box];
@@ -415,7 +434,7 @@ struct LbArgs {
   long long* stamp_lb;     // of k_lb,
   long long* stamp_after;  // and of the first kernel after k_lb (else NULL)
   float* xface;            // x-face velocities of the row boxes at t_n (k_xface)
-  const int4* xf_items;    // k_xface workgroups: box, first node, node count
+  const int4* xf_items;    // x-face work items (one wavefront each): box, first node, count
   int n_xf_items;
   int n_boxes;
   int reduce_every;
@@ -1080,26 +1099,31 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
 // that the row lanes that own those nodes read three floats instead of
 // evaluating the boundary source with dependent loads.  Node k of a box:
 // k = side (ny-2)(nz-2) + (z-1)(ny-2) + (y-1), velocity at xface[xf_off + 3k].
-constexpr int XF_NODES = 4;  // x-face nodes per k_xface thread
+constexpr int XF_NODES = 4;  // x-face nodes per lane
+constexpr int XF_ITEM = XF_NODES * 64;  // nodes per x-face work item (one wavefront)
 
 template <int S>
-__global__ __launch_bounds__(WG) void k_xface(LbArgs A) {
+__device__ __forceinline__ void xface_wave(const BoxDesc* __restrict__ boxes,
+                                           const int4* __restrict__ items, int item,
+                                           float* __restrict__ xface, DevState* __restrict__ st,
+                                           long long* stamp) {
   using R = typename Store<S>::R;
   // inputs read before the timestamp store (see k_check)
   const bool latched =
-      __hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
-  const long long step = A.st->step;
-  const int4 w = A.xf_items[blockIdx.x];
-  const BoxDesc b = A.boxes[w.x];
-  put_stamp(A.stamp_first);
+      __hip_atomic_load(&st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
+  const long long step = st->step;
+  const int4 w = items[item];  // box, first node, node count
+  const BoxDesc b = boxes[w.x];
+  put_stamp(stamp);
   if (latched) return;
+  const int lane = (int)threadIdx.x & 63;
   const int nyi = b.ny - 2, plane = nyi * (b.nz - 2);
   const BcTime<R> tm = bc_time<R>(b, step);
-  // XF_NODES independent nodes per thread, unrolled so that their sample loads
+  // XF_NODES independent nodes per lane, unrolled so that their sample loads
   // are in flight together
 #pragma unroll
   for (int j = 0; j < XF_NODES; j++) {
-    const int k = w.y + (int)threadIdx.x + j * WG;
+    const int k = w.y + lane + j * 64;
     if (k >= w.y + w.z) break;
     const int side = k / plane, r = k - side * plane;
     const int zi = r / nyi, yi = r - zi * nyi;
@@ -1110,8 +1134,17 @@ __global__ __launch_bounds__(WG) void k_xface(LbArgs A) {
     struct F3 {
       float c[3];
     };
-    *(F3*)(A.xface + b.xf_off + 3 * k) = F3{{(float)u[0], (float)u[1], (float)u[2]}};
+    *(F3*)(xface + b.xf_off + 3 * k) = F3{{(float)u[0], (float)u[1], (float)u[2]}};
   }
+}
+
+// x-face velocities alone (boxes without chains, readout, autotuner trials):
+// WG / 64 work items per workgroup, one per wavefront
+template <int S>
+__global__ __launch_bounds__(WG) void k_xface(LbArgs A) {
+  const int item = (int)blockIdx.x * (WG / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (item >= A.n_xf_items) return;
+  xface_wave<S>(A.boxes, A.xf_items, item, A.xface, A.st, A.stamp_first);
 }
 
 // ----------------------------------------------------------- mass / momentum

@@ -16,7 +16,8 @@ namespace lbhost {
 using LbLaunch = void (*)(dim3, hipStream_t, const lbdev::LbArgs&);
 using ChainLaunch = void (*)(int, hipStream_t, const lbdev::BoxDesc*, const lbdev::ChainDesc*,
                              const void*, const void*, void*, void*, int, int4*, void*, void*, int*,
-                             lbdev::DevState*, double, int, long long*);
+                             lbdev::DevState*, double, int, long long*, const int4*, int,
+                             float*);
 
 // fused step launcher: storage S (0 FP64, 1 FP32, 2 FP16 deviations), collision
 // C (0 BGK, 1 MRT, 2 MRT with ghost rate 1), periodic or not
@@ -24,7 +25,8 @@ template <int S, int C>
 LbLaunch pick_lb(bool periodic);
 
 // chain kernel launcher for storage S; one wavefront per chain when no chain
-// has more than 64 beads, else 256 threads
+// has more than 64 beads, else 256 threads; the same launch computes the
+// x-face velocities of the step in workgroups after the chains
 template <int S>
 ChainLaunch pick_chain(bool periodic, int max_beads);
 

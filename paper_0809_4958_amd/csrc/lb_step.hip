@@ -30,12 +30,14 @@ template <int S, bool P, int CB>
 void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc* chains,
                   const void* a0, const void* a1, void* pos, void* vel, int total, int4* rb,
                   void* rd, void* rp, int* bbox, DevState* st, double rho0, int pre,
-                  long long* stamp) {
+                  long long* stamp, const int4* xf_items, int n_xf, float* xface) {
   using T = typename Store<S>::T;
   using R = typename Store<S>::R;
-  hipLaunchKernelGGL((k_chain<S, P, CB>), dim3(nch), dim3(CB), 0, s, boxes, chains, (const T*)a0,
-                     (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox, st, rho0, pre,
-                     stamp);
+  // one workgroup per chain, then CB / 64 x-face work items per workgroup
+  const int nxb = (n_xf + CB / 64 - 1) / (CB / 64);
+  hipLaunchKernelGGL((k_chain<S, P, CB>), dim3(nch + nxb), dim3(CB), 0, s, boxes, chains,
+                     (const T*)a0, (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox,
+                     st, rho0, pre, stamp, nch, xf_items, n_xf, xface);
 }
 
 template <int S>

@@ -151,7 +151,7 @@ struct lb_ctx {
   int n_check = 0;
   double* d_mass_mom = nullptr;
   float* d_xface = nullptr;        // x-face velocities of the row boxes (k_xface)
-  int4* d_xf_items = nullptr;      // k_xface workgroups: box, first node, node count
+  int4* d_xf_items = nullptr;      // x-face work items (one wavefront each): box, first node, count
   int n_xf_items = 0;
   DevState* d_st = nullptr;
   ChainDesc* d_chains = nullptr;
@@ -724,15 +724,19 @@ hipEvent_t next_event(lb_ctx* ctx) {
   return ctx->ev[ctx->ev_used++];
 }
 
-// x-face velocities of the row boxes at the current device step
+// x-face velocities of the row boxes at the current device step, on their own
+// (with chains, k_chain's extra workgroups compute them)
 void launch_xface(lb_ctx* ctx, hipStream_t s, const LbArgs& a) {
+  const dim3 g((unsigned)((ctx->n_xf_items + WG / 64 - 1) / (WG / 64)));
   if (ctx->S == 1)
-    hipLaunchKernelGGL(k_xface<1>, dim3(ctx->n_xf_items), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_xface<1>, g, dim3(WG), 0, s, a);
   else
-    hipLaunchKernelGGL(k_xface<2>, dim3(ctx->n_xf_items), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_xface<2>, g, dim3(WG), 0, s, a);
 }
 
-// One step on stream s: k_xface, k_chain, k_lb, k_check, k_finalize.  ev3
+// One step on stream s: k_chain (whose workgroups after the chains compute the
+// x-face velocities; k_xface alone when there are no chains), k_lb, k_check,
+// k_finalize.  ev3
 // (optional) receives event records before the first kernel, before k_lb and
 // after k_lb; st3 (optional, inside captured graphs) receives device
 // timestamps from the kernels themselves: the start of the step's first
@@ -741,16 +745,16 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
                   long long* st3 = nullptr) {
   const bool xf = ctx->n_xf_items > 0, chains = !ctx->ch.empty();
   if (ev3) (void)hipEventRecord(ev3[0], s);
-  if (xf) {
+  if (chains) {  // chains and x-face velocities in one launch
+    ctx->chain_fn((int)ctx->ch.size(), s, ctx->d_boxes, ctx->d_chains, ctx->arena[0], ctx->arena[1],
+                  ctx->d_pos, ctx->d_vel, ctx->total_beads, ctx->d_rec_base, ctx->d_rec_d,
+                  ctx->d_rec_dp, ctx->d_bbox, ctx->d_st, ctx->cfg.rho0, pre, st3,
+                  ctx->d_xf_items, ctx->n_xf_items, ctx->d_xface);
+  } else if (xf) {
     LbArgs xa = make_args(ctx, pre, 0, 0);
     if (st3) xa.stamp_first = st3;
     launch_xface(ctx, s, xa);
   }
-  if (chains)
-    ctx->chain_fn((int)ctx->ch.size(), s, ctx->d_boxes, ctx->d_chains, ctx->arena[0], ctx->arena[1],
-                  ctx->d_pos, ctx->d_vel, ctx->total_beads, ctx->d_rec_base, ctx->d_rec_d,
-                  ctx->d_rec_dp, ctx->d_bbox, ctx->d_st, ctx->cfg.rho0, pre,
-                  (st3 && !xf) ? st3 : nullptr);
   if (ev3) (void)hipEventRecord(ev3[1], s);
   LbArgs a = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
   if (st3) {
@@ -957,8 +961,9 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   }
   ctx->arena_elems = off;
   // x-face velocity blocks of the row boxes (2 sides x interior y, z x 3
-  // floats) and the k_xface work list: chunks of at most XF_NODES x 256 nodes
-  // of a box (each thread evaluates XF_NODES nodes with their loads overlapped)
+  // floats) and the x-face work list: chunks of at most XF_ITEM nodes of a box,
+  // one per wavefront (each lane evaluates XF_NODES nodes with their loads
+  // overlapped)
   int64_t xf_floats = 0;
   std::vector<int4> xf_items;
   for (size_t bi = 0; bi < ctx->bx.size(); bi++) {
@@ -971,8 +976,8 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     }
     b.xf_off = (int)xf_floats;
     xf_floats += 3 * nodes;
-    for (int64_t k = 0; k < nodes; k += XF_NODES * WG)
-      xf_items.push_back(make_int4((int)bi, (int)k, (int)std::min<int64_t>(XF_NODES * WG, nodes - k), 0));
+    for (int64_t k = 0; k < nodes; k += XF_ITEM)
+      xf_items.push_back(make_int4((int)bi, (int)k, (int)std::min<int64_t>(XF_ITEM, nodes - k), 0));
   }
   // NULL is HIP's null stream (ordered with PyTorch's default stream)
   ctx->stream = (hipStream_t)cfg->stream;
@@ -1492,7 +1497,7 @@ lb_status lb_get_timing(lb_ctx* ctx, double out[4]) {
   for (auto& b : ctx->bx) bytes += 2.0 * Q * store_bytes(ctx->S) * (double)b.interior;
   out[0] = n_step > 0 ? step_ms / n_step : (n ? (ch_ms + lb_ms) / n : 0);
   out[1] = n ? lb_ms / n : 0;
-  out[2] = (n && !ctx->ch.empty()) ? ch_ms / n : 0;
+  out[2] = (n && (!ctx->ch.empty() || ctx->n_xf_items > 0)) ? ch_ms / n : 0;
   out[3] = bytes;
   return LB_OK;
 }
