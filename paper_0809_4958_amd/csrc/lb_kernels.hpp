@@ -6,11 +6,13 @@
 //             substeps (FENE, exact friction update, centre-of-mass pin) and
 //             the spreading records (stencil base, fractional offsets,
 //             friction impulse) plus the chain's stencil bounding box.
-//   k_lb      the fused step over a work list: interior tiles do pull
-//             streaming, gather the spread force from the records of the
-//             chains whose box overlaps the tile (fixed bead order, no
-//             atomics), collide and store; boundary items store the boundary
-//             equilibrium populations that point into the interior.
+//   k_lb      the fused step over a work list: interior rows and tiles do
+//             pull streaming, collide and store (periodic boxes also gather
+//             the spread force of their chains); boundary items store the
+//             boundary equilibrium populations that point into the interior.
+//   k_force   after k_lb, one workgroup per chain of a non-periodic box: the
+//             nodes of the chain's stencil box collide again with the spread
+//             force gathered from the records (fixed bead order, no atomics).
 //   k_check   on check steps: FP64 partial sums of the interior's mass and
 //             momentum at t_{n+1} from the arena k_lb wrote; k_finalize
 //             (lb_io_kernels.hpp) adds them per box.
@@ -467,6 +469,9 @@ __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
     if (z < bb[2] || z > bb[5]) continue;
     if (!(x >= bb[0] && x <= bb[3] && y >= bb[1] && y <= bb[4])) continue;
     const ChainDesc& ch = A.chains[gc];
+    // no branch per bead (a bead whose stencil misses the node subtracts a
+    // selected zero), so the record loads of consecutive beads overlap
+#pragma unroll 4
     for (int jb = ch.first; jb < ch.first + ch.nb; jb++) {
       const int4 bs = A.rec_base[jb];
       int ox = x - bs.x, oy = y - bs.y, oz = z - bs.z;
@@ -475,13 +480,14 @@ __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
         if ((b.pmask & 2) && oy < 0) oy += b.ny;
         if ((b.pmask & 4) && oz < 0) oz += b.nz;
       }
-      if ((unsigned)ox > 1u || (unsigned)oy > 1u || (unsigned)oz > 1u) continue;
+      const bool hit = (unsigned)ox <= 1u && (unsigned)oy <= 1u && (unsigned)oz <= 1u;
       const R w = (ox ? rd[3 * jb] : (R)1 - rd[3 * jb]) *
                   (oy ? rd[3 * jb + 1] : (R)1 - rd[3 * jb + 1]) *
                   (oz ? rd[3 * jb + 2] : (R)1 - rd[3 * jb + 2]);
-      gx -= w * rp[3 * jb];
-      gy -= w * rp[3 * jb + 1];
-      gz -= w * rp[3 * jb + 2];
+      const R px = rp[3 * jb], py = rp[3 * jb + 1], pz = rp[3 * jb + 2];
+      gx -= hit ? w * px : (R)0;
+      gy -= hit ? w * py : (R)0;
+      gz -= hit ? w * pz : (R)0;
     }
   }
 }
@@ -489,11 +495,11 @@ __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
 // Interior tile of a non-periodic box whose population groups (0..9 and
 // 10..18) each span less than 4 GiB: every load is one 32-bit offset add on
 // a per-thread node offset plus a scalar (uniform) group base.
-template <int S, int COLL, bool GATHER, int BS>
+template <int S, int COLL, int BS>
 __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, const Item& it,
                                           const typename Store<S>::T* src,
                                           typename Store<S>::T* dst, bool pre,
-                                          unsigned long long cmask, typename Store<S>::R rho0,
+                                          typename Store<S>::R rho0,
                                           typename Store<S>::R omega, typename Store<S>::R omb,
                                           typename Store<S>::R omg) {
   using St = Store<S>;
@@ -529,9 +535,7 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
         const float k = WCLS[i] == 0 ? dc0 : (WCLS[i] == 1 ? dc1 : dc2);
         d[i] = St::dec(v, k);
       }
-      R gx = 0, gy = 0, gz = 0;
-      if (GATHER) gather_force<R, false>(A, b, cmask, x, y, z, gx, gy, gz);
-      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+      collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float k = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
@@ -650,11 +654,11 @@ __device__ __forceinline__ void vput(unsigned (&w)[W], int e, typename Store<S>:
   }
 }
 
-template <int S, int W, int COLL, bool GATHER, bool PRE, int BS>
+template <int S, int W, int COLL, bool PRE, int BS>
 __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, const Item& it,
                                           const typename Store<S>::T* src,
                                           typename Store<S>::T* dst, long long step,
-                                          unsigned long long cmask, typename Store<S>::R rho0,
+                                          typename Store<S>::R rho0,
                                           typename Store<S>::R omega, typename Store<S>::R omb,
                                           typename Store<S>::R omg) {
   using St = Store<S>;
@@ -757,73 +761,6 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
         }
       }
     }
-    // spread force of the lane's V nodes: chains whose stencil box holds the
-    // row, beads in fixed order
-    R g[GATHER ? V : 1][3];
-#pragma unroll
-    for (int k = 0; k < (GATHER ? V : 1); k++) g[k][0] = g[k][1] = g[k][2] = (R)0;
-    if (GATHER) {
-      static_assert(sizeof(R) == 4, "row items compute in FP32");
-      // the wavefront loads up to 64 spreading records at once (one per
-      // lane), keeps those whose 2x2 (y, z) stencil meets the wavefront's own
-      // rows and walks them in increasing bead order, reading each from its
-      // lane
-      const R* rd = (const R*)A.rec_d;
-      const R* rp = (const R*)A.rec_dp;
-      const int qw0 = qb + (int)(threadIdx.x & ~63u);
-      const int qw1 = min(min(qw0 + 63, q_end - 1), g_last);
-      const int rw0 = qw0 / L, rw1 = qw1 / L;
-      const int zw0 = 1 + rw0 / nyi, zw1 = 1 + rw1 / nyi;
-      const bool one_plane = zw0 == zw1;
-      const int iy0 = one_plane ? rw0 - (zw0 - 1) * nyi : 0;          // lowest row y, minus 1
-      const int iy1 = one_plane ? 1 + rw1 - (zw1 - 1) * nyi : nyi;    // highest row y
-      const int iz0 = zw0 - 1, iz1 = zw1;
-      for (int ci = 0; ci < b.chain_count && ci < MAX_BOX_CHAINS && qw0 < q_end; ci++) {
-        if (!((cmask >> ci) & 1ull)) continue;
-        const ChainDesc& ch = A.chains[b.chain_first + ci];
-        const int jend = ch.first + ch.nb;
-        for (int j0 = ch.first; j0 < jend; j0 += 64) {
-          const int jb = j0 + lane;
-          int4 bs = make_int4(0, 0, 0, 0);
-          R dx = (R)0, dy = (R)0, dz = (R)0, px = (R)0, py = (R)0, pz = (R)0;
-          bool hit = false;
-          if (jb < jend) {
-            bs = A.rec_base[jb];
-            dx = rd[3 * jb];
-            dy = rd[3 * jb + 1];
-            dz = rd[3 * jb + 2];
-            px = rp[3 * jb];
-            py = rp[3 * jb + 1];
-            pz = rp[3 * jb + 2];
-            hit = bs.y >= iy0 && bs.y <= iy1 && bs.z >= iz0 && bs.z <= iz1;
-          }
-          unsigned long long m = __ballot(hit);
-          while (m) {
-            const int sl = __builtin_ctzll(m);
-            m &= m - 1;
-            const int by = __builtin_amdgcn_readlane(bs.y, sl), bz = __builtin_amdgcn_readlane(bs.z, sl);
-            const int oy = y - by, oz = z - bz;
-            if (!act || (unsigned)oy > 1u || (unsigned)oz > 1u) continue;
-            const int bx = __builtin_amdgcn_readlane(bs.x, sl);
-            const R wdx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dx), sl));
-            const R wdy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dy), sl));
-            const R wdz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dz), sl));
-            const R wpx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(px), sl));
-            const R wpy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(py), sl));
-            const R wpz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pz), sl));
-#pragma unroll
-            for (int k = 0; k < V; k++) {
-              const int ox = x0 + k - bx;
-              if ((unsigned)ox > 1u) continue;
-              const R w = (ox ? wdx : (R)1 - wdx) * (oy ? wdy : (R)1 - wdy) * (oz ? wdz : (R)1 - wdz);
-              g[k][0] -= w * wpx;
-              g[k][1] -= w * wpy;
-              g[k][2] -= w * wpz;
-            }
-          }
-        }
-      }
-    }
     unsigned out[Q][W];
 #pragma unroll
     for (int k = 0; k < V; k++) {
@@ -835,8 +772,7 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
         d[i] = St::dec(velem<S, W>(raw[i], left[i], right[i], e), kd);
       }
       const int x = x0 + k;
-      collide_any<R, COLL>(d, GATHER ? g[k][0] : (R)0, GATHER ? g[k][1] : (R)0,
-                           GATHER ? g[k][2] : (R)0, rho0, omega, omb, omg);
+      collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
@@ -1013,28 +949,17 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
     T* __restrict__ dst = dstA + b.off;
 
     if (it.kind == ITEM_ROWS) {
-      unsigned long long cmask = 0;
-      for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
-        const int* bb = A.bbox + 6 * (b.chain_first + c);
-        const bool ov = bb[1] <= it.y0 + it.ey - 1 && bb[4] >= it.y0 && bb[2] <= it.z0 + it.ez - 1 &&
-                        bb[5] >= it.z0;
-        if (ov) cmask |= 1ull << c;
-      }
+      // row boxes are never periodic: their chains couple in k_force
       if constexpr (S != 0 && !PER) {
-#define LB_ROWS(GA, PR)                                                                      \
-  do {                                                                                       \
-    if (b.vw == 3)                                                                           \
-      tile_rows<S, 3, COLL, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg); \
-    else                                                                                     \
-      tile_rows<S, 2, COLL, GA, PR, BS>(A, b, it, src, dst, step, cmask, rho0, omega, omb, omg); \
+#define LB_ROWS(PR)                                                                    \
+  do {                                                                                 \
+    if (b.vw == 3)                                                                     \
+      tile_rows<S, 3, COLL, PR, BS>(A, b, it, src, dst, step, rho0, omega, omb, omg);  \
+    else                                                                               \
+      tile_rows<S, 2, COLL, PR, BS>(A, b, it, src, dst, step, rho0, omega, omb, omg);  \
   } while (0)
-        if (pre) {
-          if (cmask) LB_ROWS(true, true);
-          else LB_ROWS(false, true);
-        } else {
-          if (cmask) LB_ROWS(true, false);
-          else LB_ROWS(false, false);
-        }
+        if (pre) LB_ROWS(true);
+        else LB_ROWS(false);
 #undef LB_ROWS
       }
     } else if (it.kind == ITEM_FACE_ROWS) {
@@ -1043,17 +968,17 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
         else face_rows<S, 2, BS>(b, it, dst, step, rho0);
       }
     } else if (it.kind == ITEM_TILE) {
-      // chains whose stencil box overlaps this tile
+      // chains whose stencil box overlaps this tile, periodic boxes only (the
+      // chains of the other boxes couple in k_force)
       unsigned long long cmask = 0;
-      for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
+      for (int c = 0; PER && b.pmask && c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
         const int* bb = A.bbox + 6 * (b.chain_first + c);
         const bool ov = bb[0] <= it.x0 + it.ex - 1 && bb[3] >= it.x0 && bb[1] <= it.y0 + it.ey - 1 &&
                         bb[4] >= it.y0 && bb[2] <= it.z0 + it.ez - 1 && bb[5] >= it.z0;
         if (ov) cmask |= 1ull << c;
       }
       if (!PER && b.fast) {
-        if (cmask) tile_fast<S, COLL, true, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg);
-        else tile_fast<S, COLL, false, BS>(A, b, it, src, dst, pre, 0, rho0, omega, omb, omg);
+        tile_fast<S, COLL, BS>(A, b, it, src, dst, pre, rho0, omega, omb, omg);
       } else {
         tile_generic<S, COLL, PER, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg);
       }
@@ -1099,6 +1024,56 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
 // that the row lanes that own those nodes read three floats instead of
 // evaluating the boundary source with dependent loads.  Node k of a box:
 // k = side (ny-2)(nz-2) + (z-1)(ny-2) + (y-1), velocity at xface[xf_off + 3k].
+// ------------------------------------------------------------ chain forcing
+// Chains of non-periodic boxes couple to the fluid in a pass of their own,
+// right after the fused step: the interior nodes of each chain's stencil box
+// collide again from the same pre-collision populations (the fused step reads
+// one buffer and writes the other, so they are intact), now with the spread
+// force of every chain of the box whose stencil box holds the node (Guo
+// forcing, the same collision), and overwrite what the fused step stored
+// there.  The fused step then never gathers spread force for these boxes.
+// Where the stencil boxes of two chains overlap, both workgroups compute the
+// node and store the same values.  One workgroup per chain.
+template <int S, int COLL, bool PER>
+__global__ __launch_bounds__(WG) void k_force(LbArgs A) {
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  const int gc = blockIdx.x;
+  // inputs read before the timestamp store (see k_check)
+  const bool latched =
+      __hip_atomic_load(&A.st->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ERR_NONE;
+  const long long step = A.st->step;
+  const ChainDesc ch = A.chains[gc];
+  const BoxDesc b = A.boxes[ch.box];
+  int bb[6];
+#pragma unroll
+  for (int a = 0; a < 6; a++) bb[a] = A.bbox[6 * gc + a];
+  put_stamp(A.stamp_after);
+  if (latched || b.pmask) return;  // periodic boxes gather inside the fused step
+  const int par = (int)(step & 1);
+  const T* __restrict__ src = (const T*)(par ? A.a1 : A.a0) + b.off;
+  T* __restrict__ dst = (T*)(par ? A.a0 : A.a1) + b.off;
+  const R rho0 = (R)A.rho0, omega = (R)A.omega, omb = (R)A.om_bulk, omg = (R)A.om_ghost;
+  const unsigned long long all =
+      b.chain_count >= MAX_BOX_CHAINS ? ~0ull : (1ull << b.chain_count) - 1ull;
+  const int lx = bb[3] - bb[0] + 1, ly = bb[4] - bb[1] + 1, lz = bb[5] - bb[2] + 1;
+  if (lx <= 0 || ly <= 0 || lz <= 0) return;
+  const int n = lx * ly * lz;
+#pragma unroll 1
+  for (int p = threadIdx.x; p < n; p += WG) {
+    const int x = bb[0] + p % lx, y = bb[1] + (p / lx) % ly, z = bb[2] + p / (lx * ly);
+    if (!is_interior(b, x, y, z)) continue;
+    R d[Q];
+    load_pre<S, PER>(src, b, x, y, z, A.pre != 0, d);
+    R gx = 0, gy = 0, gz = 0;
+    gather_force<R, PER>(A, b, all, x, y, z, gx, gy, gz);
+    collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+#pragma unroll
+    for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+  }
+}
+
 constexpr int XF_NODES = 4;  // x-face nodes per lane
 constexpr int XF_ITEM = XF_NODES * 64;  // nodes per x-face work item (one wavefront)
 

@@ -24,6 +24,10 @@ using ChainLaunch = void (*)(int, hipStream_t, const lbdev::BoxDesc*, const lbde
 template <int S, int C>
 LbLaunch pick_lb(bool periodic);
 
+// chain forcing pass after the fused step (grid: one workgroup per chain)
+template <int S, int C>
+LbLaunch pick_force(bool periodic);
+
 // chain kernel launcher for storage S; one wavefront per chain when no chain
 // has more than 64 beads, else 256 threads; the same launch computes the
 // x-face velocities of the step in workgroups after the chains

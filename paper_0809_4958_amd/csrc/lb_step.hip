@@ -25,6 +25,18 @@ LbLaunch pick_lb(bool periodic) {
 
 template LbLaunch pick_lb<LB_S, LB_C>(bool);
 
+template <int S, int C, bool P>
+void launch_force(dim3 g, hipStream_t s, const LbArgs& a) {
+  hipLaunchKernelGGL((k_force<S, C, P>), g, dim3(WG), 0, s, a);
+}
+
+template <int S, int C>
+LbLaunch pick_force(bool periodic) {
+  return periodic ? launch_force<S, C, true> : launch_force<S, C, false>;
+}
+
+template LbLaunch pick_force<LB_S, LB_C>(bool);
+
 #if LB_C == 0
 template <int S, bool P, int CB>
 void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc* chains,

@@ -107,6 +107,13 @@ LbLaunch pick_lb(int coll, bool per) {
   return lbhost::pick_lb<S, 2>(per);
 }
 
+template <int S>
+LbLaunch pick_force(int coll, bool per) {
+  if (coll == 0) return lbhost::pick_force<S, 0>(per);
+  if (coll == 1) return lbhost::pick_force<S, 1>(per);
+  return lbhost::pick_force<S, 2>(per);
+}
+
 size_t store_bytes(int s) { return s == LB_STORE_F64 ? 8 : (s == LB_STORE_F32 ? 4 : 2); }
 size_t real_bytes(int s) { return s == LB_STORE_F64 ? 8 : 4; }
 // nodes per lane of the row items with w 32-bit words per lane
@@ -181,6 +188,7 @@ struct lb_ctx {
   double clock_khz = 0;
   int gsteps_t = 0;
   LbLaunch lb_fn = nullptr;
+  LbLaunch force_fn = nullptr;
   ChainLaunch chain_fn = nullptr;
   CheckLaunch check_fn = nullptr;
   // timing
@@ -735,8 +743,8 @@ void launch_xface(lb_ctx* ctx, hipStream_t s, const LbArgs& a) {
 }
 
 // One step on stream s: k_chain (whose workgroups after the chains compute the
-// x-face velocities; k_xface alone when there are no chains), k_lb, k_check,
-// k_finalize.  ev3
+// x-face velocities; k_xface alone when there are no chains), k_lb, k_force
+// (chains), k_check, k_finalize.  ev3
 // (optional) receives event records before the first kernel, before k_lb and
 // after k_lb; st3 (optional, inside captured graphs) receives device
 // timestamps from the kernels themselves: the start of the step's first
@@ -764,13 +772,14 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
   ctx->lb_fn(dim3(ctx->grid), s, a);
   if (ev3) (void)hipEventRecord(ev3[2], s);
   LbArgs t = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
-  const bool check = ctx->cfg.reduce_every > 0;
-  if (check) {
-    if (st3) t.stamp_after = st3 + 2;
+  if (st3) t.stamp_after = st3 + 2;  // by the first kernel after k_lb
+  if (chains) {  // spread force of the chains of non-periodic boxes
+    ctx->force_fn(dim3((unsigned)ctx->ch.size()), s, t);
+    t.stamp_after = nullptr;
+  }
+  if (ctx->cfg.reduce_every > 0) {
     ctx->check_fn(ctx->n_check, s, t);
     t.stamp_after = nullptr;
-  } else if (st3) {
-    t.stamp_after = st3 + 2;
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, s, t);
 }
@@ -1024,9 +1033,9 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   {
     const int kc = ctx->coll == LB_BGK ? 0 : (ctx->cfg.ghost_rate == 1.0 ? 2 : 1);
     switch (ctx->S) {
-      case 0: ctx->lb_fn = pick_lb<0>(kc, ctx->per); break;
-      case 1: ctx->lb_fn = pick_lb<1>(kc, ctx->per); break;
-      default: ctx->lb_fn = pick_lb<2>(kc, ctx->per); break;
+      case 0: ctx->lb_fn = pick_lb<0>(kc, ctx->per); ctx->force_fn = pick_force<0>(kc, ctx->per); break;
+      case 1: ctx->lb_fn = pick_lb<1>(kc, ctx->per); ctx->force_fn = pick_force<1>(kc, ctx->per); break;
+      default: ctx->lb_fn = pick_lb<2>(kc, ctx->per); ctx->force_fn = pick_force<2>(kc, ctx->per); break;
     }
   }
   ctx->check_fn = ctx->S == 0 ? pick_check<0>(ctx->per)
