@@ -208,7 +208,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_lb (fused collide-stream + boundary faces + spreading gather)",
+            "kernel": "k_lb (fused collide-stream + boundary faces)",
             "kernel_ms": round(lb_ms, 4),
             # x-face boundary velocities + chain kernel, per step
             "pre_lb_kernels_ms": round(tm[2], 4),

@@ -456,7 +456,9 @@ __device__ __forceinline__ void collide_any(R d[Q], R gx, R gy, R gz, R rho0, R 
 
 // Spread force g(x) = - sum_j w_jx dP_j at node (x, y, z): chains whose stencil
 // box overlaps the tile (cmask), beads in fixed order, no atomics.
-template <typename R, bool PER>
+// UNROLL: beads whose records are loaded together (1 inside the fused step,
+// where registers are short)
+template <typename R, bool PER, int UNROLL>
 __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
                                              unsigned long long cmask, int x, int y, int z, R& gx,
                                              R& gy, R& gz) {
@@ -471,7 +473,7 @@ __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
     const ChainDesc& ch = A.chains[gc];
     // no branch per bead (a bead whose stencil misses the node subtracts a
     // selected zero), so the record loads of consecutive beads overlap
-#pragma unroll 4
+#pragma unroll UNROLL
     for (int jb = ch.first; jb < ch.first + ch.nb; jb++) {
       const int4 bs = A.rec_base[jb];
       int ox = x - bs.x, oy = y - bs.y, oz = z - bs.z;
@@ -897,7 +899,7 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
       R d[Q];
       load_pre<S, PER>(src, b, x, y, z, pre, d);
       R gx = 0, gy = 0, gz = 0;
-      if (cmask) gather_force<R, PER>(A, b, cmask, x, y, z, gx, gy, gz);
+      if (cmask) gather_force<R, PER, 1>(A, b, cmask, x, y, z, gx, gy, gz);
       collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
 #pragma unroll
       for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
@@ -908,10 +910,10 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
 // ----------------------------------------------------------- fused step
 
 // Resident waves per SIMD the step kernel is compiled for: the most that fit
-// without spilling (VGPRs per lane: 512 / waves).  FP64 BGK 2 (189 VGPRs), MRT
-// 3 (135), MRT with ghost rate 1 4 (125); FP32 MRT 4 (118-126), FP32 BGK 3;
-// FP16 MRT 3 (153-165), FP16 BGK 2 (186-188).  Left to itself the allocator
-// lands just above a boundary and runs one wave fewer, measured 5-11% slower.
+// without spilling (VGPRs per lane: 512 / waves).  FP64 BGK 2 (197-228 VGPRs),
+// MRT 3 (147-150), MRT with ghost rate 1 4 (124-127); FP32 3-4 (94-122); FP16
+// MRT 3 (101-144), FP16 BGK 2 (127-178).  Left to itself the allocator lands
+// just above a boundary and runs one wave fewer, measured 5-11% slower.
 constexpr int lb_min_waves(int S, int COLL) {
   return S == 0 ? (COLL == 0 ? 2 : (COLL == 1 ? 3 : 4))
 #ifdef LB_MIN_WAVES
@@ -1067,7 +1069,7 @@ __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
     R d[Q];
     load_pre<S, PER>(src, b, x, y, z, A.pre != 0, d);
     R gx = 0, gy = 0, gz = 0;
-    gather_force<R, PER>(A, b, all, x, y, z, gx, gy, gz);
+    gather_force<R, PER, 4>(A, b, all, x, y, z, gx, gy, gz);
     collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
 #pragma unroll
     for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
