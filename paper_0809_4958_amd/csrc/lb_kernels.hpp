@@ -50,6 +50,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over the 64 lanes with the pairings of a shared-memory tree (lane j adds
+// lane j + o for o = 32, 16, ..., 1, so the same sum bit for bit), returned
+// to every lane.  Called with every lane active.
+template <typename R>
+__device__ __forceinline__ R wave_tree_sum(R v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return __shfl(v, 0, 64);
+}
+
 // x-face boundary velocities of one work item by one wavefront (defined with
 // k_xface below)
 template <int S>
@@ -181,48 +191,78 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
     }
   }
 
-  // MD substeps
+  // MD substeps.  With one wavefront per chain (CB = 64) the neighbour's
+  // position, the neighbour's bond force, the FENE overflow flag and the
+  // centre-of-mass sums move between lanes by cross-lane operations, with no
+  // barriers; otherwise through LDS.  Both take the same sums in the same
+  // order.
+  constexpr bool WAVE = CB == 64;
   const R h = (R)1 / (R)c.substeps;
   const R decay = (R)c.decay;
   const R zeta = (R)c.zeta, mass = (R)c.mass, fk = (R)c.fene_k;
   const R r02 = (R)(c.fene_r0 * c.fene_r0);
+  // FENE force of the bond to the next bead (separation e); false when the
+  // bond has reached its maximum extension
+  auto fene = [&](R ex, R ey, R ez, R& fx, R& fy, R& fz) -> bool {
+    const R r2 = ex * ex + ey * ey + ez * ez;
+    if (r2 >= r02) return false;
+    R fac;
+    if (S != 0 && r2 > (R)0.8 * r02) {
+      // near full extension: evaluate the FENE factor in FP64
+      const double r2d = (double)ex * ex + (double)ey * ey + (double)ez * ez;
+      fac = (R)(c.fene_k / (1.0 - r2d / (c.fene_r0 * c.fene_r0)));
+    } else {
+      fac = fk / ((R)1 - r2 / r02);
+    }
+    fx = fac * ex;
+    fy = fac * ey;
+    fz = fac * ez;
+    return true;
+  };
   R dpx = 0, dpy = 0, dpz = 0;
+  bool overflow = false;
   for (int s = 0; s < c.substeps; s++) {
-    spx[j] = rx;
-    spy[j] = ry;
-    spz[j] = rz;
-    __syncthreads();
-    R fx = 0, fy = 0, fz = 0;
-    if (act && j + 1 < c.nb) {
-      const R ex = spx[j + 1] - rx, ey = spy[j + 1] - ry, ez = spz[j + 1] - rz;
-      const R r2 = ex * ex + ey * ey + ez * ez;
-      if (r2 >= r02) {
+    R fx = 0, fy = 0, fz = 0;  // bond j -> j+1
+    R gx = 0, gy = 0, gz = 0;  // bond j-1 -> j
+    if constexpr (WAVE) {
+      const R qx = __shfl_down(rx, 1, 64), qy = __shfl_down(ry, 1, 64),
+              qz = __shfl_down(rz, 1, 64);
+      bool bad = false;
+      if (act && j + 1 < c.nb) bad = !fene(qx - rx, qy - ry, qz - rz, fx, fy, fz);
+      if (__any(bad)) {
+        overflow = true;
+        break;
+      }
+      gx = __shfl_up(fx, 1, 64);
+      gy = __shfl_up(fy, 1, 64);
+      gz = __shfl_up(fz, 1, 64);
+    } else {
+      spx[j] = rx;
+      spy[j] = ry;
+      spz[j] = rz;
+      __syncthreads();
+      if (act && j + 1 < c.nb && !fene(spx[j + 1] - rx, spy[j + 1] - ry, spz[j + 1] - rz, fx, fy, fz))
         atomicOr(&sflag, 2);
-      } else {
-        R fac;
-        if (S != 0 && r2 > (R)0.8 * r02) {
-          // near full extension: evaluate the FENE factor in FP64
-          const double r2d = (double)ex * ex + (double)ey * ey + (double)ez * ez;
-          fac = (R)(c.fene_k / (1.0 - r2d / (c.fene_r0 * c.fene_r0)));
-        } else {
-          fac = fk / ((R)1 - r2 / r02);
-        }
-        fx = fac * ex;
-        fy = fac * ey;
-        fz = fac * ez;
+      bfx[j] = fx;
+      bfy[j] = fy;
+      bfz[j] = fz;
+      __syncthreads();
+      if (sflag) {
+        overflow = true;
+        break;
+      }
+      if (j > 0) {
+        gx = bfx[j - 1];
+        gy = bfy[j - 1];
+        gz = bfz[j - 1];
       }
     }
-    bfx[j] = fx;
-    bfy[j] = fy;
-    bfz[j] = fz;
-    __syncthreads();
-    if (sflag) break;
     if (act) {
-      R Fx = bfx[j], Fy = bfy[j], Fz = bfz[j];
+      R Fx = fx, Fy = fy, Fz = fz;
       if (j > 0) {
-        Fx -= bfx[j - 1];
-        Fy -= bfy[j - 1];
-        Fz -= bfz[j - 1];
+        Fx -= gx;
+        Fy -= gy;
+        Fz -= gz;
       }
       const R tx = ux + Fx / zeta, ty = uy + Fy / zeta, tz = uz + Fz / zeta;
       const R nvx = tx + (vx - tx) * decay, nvy = ty + (vy - ty) * decay,
@@ -241,21 +281,33 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
       // fixed-order tree sums of velocity and relative position
 #pragma unroll 1
       for (int pass = 0; pass < 2; pass++) {
-        red[0][j] = act ? (pass ? rx : vx) : (R)0;
-        red[1][j] = act ? (pass ? ry : vy) : (R)0;
-        red[2][j] = act ? (pass ? rz : vz) : (R)0;
-        __syncthreads();
-        for (int o = CB / 2; o > 0; o >>= 1) {
-          if (j < o) {
-            red[0][j] += red[0][j + o];
-            red[1][j] += red[1][j + o];
-            red[2][j] += red[2][j + o];
+        R sx = act ? (pass ? rx : vx) : (R)0;
+        R sy = act ? (pass ? ry : vy) : (R)0;
+        R sz = act ? (pass ? rz : vz) : (R)0;
+        if constexpr (WAVE) {
+          sx = wave_tree_sum(sx);
+          sy = wave_tree_sum(sy);
+          sz = wave_tree_sum(sz);
+        } else {
+          red[0][j] = sx;
+          red[1][j] = sy;
+          red[2][j] = sz;
+          __syncthreads();
+          for (int o = CB / 2; o > 0; o >>= 1) {
+            if (j < o) {
+              red[0][j] += red[0][j + o];
+              red[1][j] += red[1][j + o];
+              red[2][j] += red[2][j + o];
+            }
+            __syncthreads();
           }
+          sx = red[0][0];
+          sy = red[1][0];
+          sz = red[2][0];
           __syncthreads();
         }
         const R inb = (R)1 / (R)c.nb;
-        const R mx = red[0][0] * inb, my = red[1][0] * inb, mz = red[2][0] * inb;
-        __syncthreads();
+        const R mx = sx * inb, my = sy * inb, mz = sz * inb;
         if (pass == 0) {
           vx -= mx;
           vy -= my;
@@ -267,9 +319,9 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
         }
       }
     }
-    __syncthreads();
+    if constexpr (!WAVE) __syncthreads();
   }
-  if (sflag) {
+  if (overflow) {
     if (j == 0) atomicMin(&st->err_key, (ci << 4) | EC_FENE);
     return;
   }
