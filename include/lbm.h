@@ -96,7 +96,9 @@ typedef struct {
   void* alloc_user;
   const char* tune_cache;  /* path of the autotuner cache (JSON lines: item sizes per box-size
                               class, grid per set of classes), read by lb_init, or NULL */
-  int32_t graph_steps;     /* > 0: lb_step replays a HIP graph of this many steps; 0 = eager launches */
+  int32_t graph_steps;     /* > 0: lb_step replays a HIP graph of this many steps; 0 = eager launches.
+                              A multiple of reduce_every lets the graphs leave the check pass out of
+                              the steps that are not check steps (captured once per check phase). */
 } lb_config;
 
 /* Creates a context: validates the configuration, allocates two population

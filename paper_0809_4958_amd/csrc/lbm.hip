@@ -179,6 +179,7 @@ struct lb_ctx {
   lb_status latched = LB_OK;
   hipGraphExec_t gexec = nullptr;
   int gsteps = 0;
+  int gphase = -1;  // check phase the graphs were captured for (-1: checks decided on the device)
   // timed graphs: two instances with their own event-record nodes, replayed
   // alternately so the host reads one chunk's events while the next runs
   hipGraphExec_t gexec_t[2] = {nullptr, nullptr};
@@ -750,7 +751,7 @@ void launch_xface(lb_ctx* ctx, hipStream_t s, const LbArgs& a) {
 // timestamps from the kernels themselves: the start of the step's first
 // kernel, of k_lb, and of the kernel after k_lb.
 void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
-                  long long* st3 = nullptr) {
+                  long long* st3, int chk) {
   const bool xf = ctx->n_xf_items > 0, chains = !ctx->ch.empty();
   if (ev3) (void)hipEventRecord(ev3[0], s);
   if (chains) {  // chains and x-face velocities in one launch
@@ -777,18 +778,36 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
     ctx->force_fn(dim3((unsigned)ctx->ch.size()), s, t);
     t.stamp_after = nullptr;
   }
-  if (ctx->cfg.reduce_every > 0) {
+  if (ctx->cfg.reduce_every > 0 && chk != 0) {
     ctx->check_fn(ctx->n_check, s, t);
     t.stamp_after = nullptr;
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, s, t);
 }
 
-void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed) {
+void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, bool timed, int chk) {
   hipEvent_t ev3[3];
   if (timed)
     for (auto& e : ev3) e = next_event(ctx);
-  enqueue_step(ctx, s, pre, timed ? ev3 : nullptr);
+  enqueue_step(ctx, s, pre, timed ? ev3 : nullptr, nullptr, chk);
+}
+
+// Whether the step that starts at time index n is a check step: 1 or 0 (its
+// k_check launch is left out; the kernel would find nothing to do).  The
+// host's step count follows the device's until an error latches, after which
+// every kernel returns at once.
+int check_mode(const lb_ctx* ctx, int64_t n) {
+  const int K = ctx->cfg.reduce_every;
+  return K > 0 && (n + 1) % K == 0 ? 1 : 0;
+}
+
+// Check phase of a graph of gs steps starting at time index n: replays of it
+// start at n + j gs, the same phase when K divides gs; otherwise -1 (every
+// step launches k_check, which decides on the device)
+int graph_phase(const lb_ctx* ctx, int64_t n, int gs) {
+  const int K = ctx->cfg.reduce_every;
+  if (K <= 0) return 0;
+  return gs % K == 0 ? (int)(n % K) : -1;
 }
 
 // add the timestamps of one finished timed graph chunk x (copied to pinned
@@ -1195,14 +1214,19 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
     ctx->acc_lb = ctx->acc_ch = ctx->acc_step = 0;
     ctx->acc_n = ctx->acc_step_n = 0;
   }
+  int64_t hs = ctx->host_step;  // time index of the next step enqueued
   if (ctx->state_pre) {
-    enqueue_step(ctx, ctx->stream, 1, timed);
+    enqueue_step(ctx, ctx->stream, 1, timed, check_mode(ctx, hs));
     HIPCHK(hipGetLastError());
     ctx->state_pre = false;
     left--;
+    hs++;
     if (timed) ctx->t_steps++;
   }
   const int gs = ctx->cfg.graph_steps;
+  const int phase = gs > 0 ? graph_phase(ctx, hs, gs) : -1;
+  auto graph_chk = [&](int k) { return phase < 0 ? -1 : check_mode(ctx, (int64_t)phase + k); };
+  if (gs > 0 && ctx->gphase != phase) drop_graph(ctx);
   if (gs > 0 && timed && left >= gs) {
     // HIP events recorded inside a graph cannot be timed: in the timed graphs
     // the kernels record device timestamps themselves
@@ -1224,16 +1248,18 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
         for (int k = 0; k < gs; k++)
-          enqueue_step(ctx, ctx->cap_stream, 0, nullptr, ctx->d_stamps + (size_t)x * 3 * gs + 3 * k);
+          enqueue_step(ctx, ctx->cap_stream, 0, nullptr, ctx->d_stamps + (size_t)x * 3 * gs + 3 * k,
+                       graph_chk(k));
         HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
         HIPCHK(hipGraphInstantiate(&ctx->gexec_t[x], g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
       }
       ctx->gsteps_t = gs;
+      ctx->gphase = phase;
     }
     const size_t nb = 3 * (size_t)gs * sizeof(long long);
     int j = 0;
-    for (; left >= gs; j++, left -= gs) {
+    for (; left >= gs; j++, left -= gs, hs += gs) {
       const int x = j & 1;
       if (j >= 2) {  // chunk j-2 used the same buffers: its stamps must be read first
         lb_status st = accumulate_chunk(ctx, x);
@@ -1255,19 +1281,22 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
         drop_graph(ctx);
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
-        for (int k = 0; k < gs; k++) enqueue_step(ctx, ctx->cap_stream, 0, false);
+        for (int k = 0; k < gs; k++) enqueue_step(ctx, ctx->cap_stream, 0, false, graph_chk(k));
         HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
         HIPCHK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
         ctx->gsteps = gs;
+        ctx->gphase = phase;
       }
       HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
       left -= gs;
+      hs += gs;
     }
   }
   while (left > 0) {
-    enqueue_step(ctx, ctx->stream, 0, timed);
+    enqueue_step(ctx, ctx->stream, 0, timed, check_mode(ctx, hs));
     left--;
+    hs++;
     if (timed) ctx->t_steps++;
   }
   HIPCHK(hipGetLastError());

@@ -249,6 +249,45 @@ def test_graph_replay_and_determinism_bitwise():
         assert np.array_equal(r[2], runs[0][2])
 
 
+def test_check_steps_with_graph_phases_bitwise():
+    """Mass/momentum checks fall on the same steps whether the steps run one
+    by one or from graphs captured for one check phase (graph length a
+    multiple of the check interval, leaving the other steps' check launches
+    out), with the starting phase changing between calls; the state and
+    every check record are bitwise the same, and each record belongs to the
+    last check step."""
+    case = ks_case(20, 60, dt=20, res=9, n_beads=6, config_idx=4)
+    case.reduce_every = 5
+    calls = (3, 20, 4, 10, 13)  # starting phases 0, 3, 3, 2, 2 (mod 5)
+    runs = []
+    for gs in (0, 10, 5):
+        ctx = make_ctx(case, "f16", graph_steps=gs)
+        recs, done = [], 0
+        for n in calls:
+            ctx.step(n)
+            done += n
+            mm = ctx.read(0, lbm.F_MASS_MOM)
+            recs.append(mm)
+            if done >= 5:
+                assert mm[0] == 5 * (done // 5), (gs, done, mm[0])
+        runs.append((recs, ctx.read(0, lbm.F_POP), ctx.sync_status()))
+        ctx.close()
+    assert runs[0][2] == lbm.OK
+    for recs, pop, status in runs[1:]:
+        assert status == lbm.OK
+        for a, b in zip(recs, runs[0][0]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(pop, runs[0][1])
+    # and the last record is the oracle's mass and momentum at that step (FP16
+    # storage: the state itself differs from the FP64 one at the 1e-4 level)
+    ob = case.oracle_box()
+    assert ob.step(sum(calls)) == 0
+    mm_o, mm_g = ob.mass_mom(), runs[0][0][-1]
+    assert mm_o[0] == mm_g[0] == 50
+    assert abs(mm_g[1] - mm_o[1]) / mm_o[1] < 1e-5
+    assert np.abs(mm_g[2:] - mm_o[2:]).max() < 1e-2 * np.abs(mm_o[2:]).max() + 1e-9
+
+
 def test_tune_cache_round_trip(tmp_path):
     """The autotuner's launch shape (item sizes per box size, grid) written to
     the cache is what a new context over the same boxes reads back, and the
