@@ -124,7 +124,7 @@ struct ChainDesc {
 struct DevState {
   long long step;       // time index n of the current state
   int err_key;          // 0x7fffffff when no error; else min over (owner << 4 | code index)
-  int pad;
+  int tickets;          // k_force workgroups finished in the current step (0 between steps)
   long long pad2;
 };
 

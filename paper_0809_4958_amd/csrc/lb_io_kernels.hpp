@@ -1,8 +1,10 @@
 // lb_io_kernels.hpp -- gfx950 kernels around the fused step: the per-step
 // finalisation, state upload and readout, and the stream-copy probe.
 //
-//   k_finalize  one workgroup after k_lb: reduces the item partials in a fixed
-//               order per box, checks finiteness, advances the step counter.
+//   k_finalize  one workgroup at the end of a step (check steps, or contexts
+//               without chains; otherwise k_force ends the step): reduces the
+//               check partials in a fixed order per box, checks finiteness,
+//               advances the step counter.
 //   k_set_pre / k_read / k_read_sites / k_read_beads   state upload and readout.
 //   k_copy      16-byte stream copy in contiguous per-workgroup chunks (HBM
 //               ceiling probe).

@@ -12,7 +12,8 @@
 //             boundary equilibrium populations that point into the interior.
 //   k_force   after k_lb, one workgroup per chain of a non-periodic box: the
 //             nodes of the chain's stencil box collide again with the spread
-//             force gathered from the records (fixed bead order, no atomics).
+//             force gathered from the records (fixed bead order, no atomics);
+//             on steps without a check pass its last workgroup ends the step.
 //   k_check   on check steps: FP64 partial sums of the interior's mass and
 //             momentum at t_{n+1} from the arena k_lb wrote; k_finalize
 //             (lb_io_kernels.hpp) adds them per box.
@@ -1093,7 +1094,9 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
 // forcing, the same collision), and overwrite what the fused step stored
 // there.  The fused step then never gathers spread force for these boxes.
 // Where the stencil boxes of two chains overlap, both workgroups compute the
-// node and store the same values.  One workgroup per chain.
+// node and store the same values.  One workgroup per chain.  On steps that
+// have no check pass it also ends the step (step index advance), which then
+// needs no launch of its own.
 template <int S, int COLL, bool PER>
 __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
   using St = Store<S>;
@@ -1110,27 +1113,39 @@ __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
 #pragma unroll
   for (int a = 0; a < 6; a++) bb[a] = A.bbox[6 * gc + a];
   put_stamp(A.stamp_after);
-  if (latched || b.pmask) return;  // periodic boxes gather inside the fused step
-  const int par = (int)(step & 1);
-  const T* __restrict__ src = (const T*)(par ? A.a1 : A.a0) + b.off;
-  T* __restrict__ dst = (T*)(par ? A.a0 : A.a1) + b.off;
-  const R rho0 = (R)A.rho0, omega = (R)A.omega, omb = (R)A.om_bulk, omg = (R)A.om_ghost;
-  const unsigned long long all =
-      b.chain_count >= MAX_BOX_CHAINS ? ~0ull : (1ull << b.chain_count) - 1ull;
-  const int lx = bb[3] - bb[0] + 1, ly = bb[4] - bb[1] + 1, lz = bb[5] - bb[2] + 1;
-  if (lx <= 0 || ly <= 0 || lz <= 0) return;
-  const int n = lx * ly * lz;
+  if (latched) return;  // uniform: set before this launch or not at all
+  if (!b.pmask) {       // periodic boxes gather inside the fused step
+    const int par = (int)(step & 1);
+    const T* __restrict__ src = (const T*)(par ? A.a1 : A.a0) + b.off;
+    T* __restrict__ dst = (T*)(par ? A.a0 : A.a1) + b.off;
+    const R rho0 = (R)A.rho0, omega = (R)A.omega, omb = (R)A.om_bulk, omg = (R)A.om_ghost;
+    const unsigned long long all =
+        b.chain_count >= MAX_BOX_CHAINS ? ~0ull : (1ull << b.chain_count) - 1ull;
+    const int lx = bb[3] - bb[0] + 1, ly = bb[4] - bb[1] + 1, lz = bb[5] - bb[2] + 1;
+    const int n = (lx > 0 && ly > 0 && lz > 0) ? lx * ly * lz : 0;
 #pragma unroll 1
-  for (int p = threadIdx.x; p < n; p += WG) {
-    const int x = bb[0] + p % lx, y = bb[1] + (p / lx) % ly, z = bb[2] + p / (lx * ly);
-    if (!is_interior(b, x, y, z)) continue;
-    R d[Q];
-    load_pre<S, PER>(src, b, x, y, z, A.pre != 0, d);
-    R gx = 0, gy = 0, gz = 0;
-    gather_force<R, PER, 4>(A, b, all, x, y, z, gx, gy, gz);
-    collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+    for (int p = threadIdx.x; p < n; p += WG) {
+      const int x = bb[0] + p % lx, y = bb[1] + (p / lx) % ly, z = bb[2] + p / (lx * ly);
+      if (!is_interior(b, x, y, z)) continue;
+      R d[Q];
+      load_pre<S, PER>(src, b, x, y, z, A.pre != 0, d);
+      R gx = 0, gy = 0, gz = 0;
+      gather_force<R, PER, 4>(A, b, all, x, y, z, gx, gy, gz);
+      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
 #pragma unroll
-    for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+      for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+    }
+  }
+  // On steps without a check pass (advance set) the last workgroup to take a
+  // ticket ends the step instead of a separate launch: every workgroup has
+  // read the step index before its ticket, and nothing is published for
+  // another workgroup, so no fence is needed.
+  if (A.advance) {
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(&A.st->tickets, 1) == (int)gridDim.x - 1) {
+      atomicExch(&A.st->tickets, 0);
+      A.st->step = step + 1;
+    }
   }
 }
 

@@ -774,10 +774,15 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
   if (ev3) (void)hipEventRecord(ev3[2], s);
   LbArgs t = make_args(ctx, pre, 1, ctx->cfg.reduce_every);
   if (st3) t.stamp_after = st3 + 2;  // by the first kernel after k_lb
+  // on a step known to have no check pass, k_force's last workgroup ends it
+  const bool force_ends = chains && chk == 0;
   if (chains) {  // spread force of the chains of non-periodic boxes
-    ctx->force_fn(dim3((unsigned)ctx->ch.size()), s, t);
+    LbArgs f = t;
+    f.advance = force_ends ? 1 : 0;
+    ctx->force_fn(dim3((unsigned)ctx->ch.size()), s, f);
     t.stamp_after = nullptr;
   }
+  if (force_ends) return;
   if (ctx->cfg.reduce_every > 0 && chk != 0) {
     ctx->check_fn(ctx->n_check, s, t);
     t.stamp_after = nullptr;
