@@ -51,14 +51,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum over the 64 lanes with the pairings of a shared-memory tree (lane j adds
-// lane j + o for o = 32, 16, ..., 1, so the same sum bit for bit), returned
-// to every lane.  Called with every lane active.
-template <typename R>
-__device__ __forceinline__ R wave_tree_sum(R v) {
+// Value of lane 0, wave-uniform (every lane active)
+__device__ __forceinline__ float lane0(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double lane0(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// N sums over the 64 lanes at once (their shuffles interleaved), each with
+// the pairings of a shared-memory tree (lane j adds lane j + o for o = 32, 16,
+// ..., 1, so the same sums bit for bit), returned to every lane.  Called with
+// every lane active.
+template <typename R, int N>
+__device__ __forceinline__ void wave_tree_sums(R (&v)[N]) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return __shfl(v, 0, 64);
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < N; k++) v[k] += __shfl_down(v[k], o, 64);
+  }
+#pragma unroll
+  for (int k = 0; k < N; k++) v[k] = lane0(v[k]);
 }
 
 // x-face boundary velocities of one work item by one wavefront (defined with
@@ -284,35 +300,42 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
       ry += h * vy;
       rz += h * vz;
     }
-    if (c.fix_com) {
+    if (c.fix_com && WAVE) {
+      // fixed-order tree sums of velocity and relative position, all six at
+      // once (the position sum does not depend on the velocity correction)
+      R t[6] = {act ? vx : (R)0, act ? vy : (R)0, act ? vz : (R)0,
+                act ? rx : (R)0, act ? ry : (R)0, act ? rz : (R)0};
+      wave_tree_sums(t);
+      const R inb = (R)1 / (R)c.nb;
+      vx -= t[0] * inb;
+      vy -= t[1] * inb;
+      vz -= t[2] * inb;
+      rx -= t[3] * inb;
+      ry -= t[4] * inb;
+      rz -= t[5] * inb;
+    } else if (c.fix_com) {
       // fixed-order tree sums of velocity and relative position
 #pragma unroll 1
       for (int pass = 0; pass < 2; pass++) {
         R sx = act ? (pass ? rx : vx) : (R)0;
         R sy = act ? (pass ? ry : vy) : (R)0;
         R sz = act ? (pass ? rz : vz) : (R)0;
-        if constexpr (WAVE) {
-          sx = wave_tree_sum(sx);
-          sy = wave_tree_sum(sy);
-          sz = wave_tree_sum(sz);
-        } else {
-          red[0][j] = sx;
-          red[1][j] = sy;
-          red[2][j] = sz;
-          __syncthreads();
-          for (int o = CB / 2; o > 0; o >>= 1) {
-            if (j < o) {
-              red[0][j] += red[0][j + o];
-              red[1][j] += red[1][j + o];
-              red[2][j] += red[2][j + o];
-            }
-            __syncthreads();
+        red[0][j] = sx;
+        red[1][j] = sy;
+        red[2][j] = sz;
+        __syncthreads();
+        for (int o = CB / 2; o > 0; o >>= 1) {
+          if (j < o) {
+            red[0][j] += red[0][j + o];
+            red[1][j] += red[1][j + o];
+            red[2][j] += red[2][j + o];
           }
-          sx = red[0][0];
-          sy = red[1][0];
-          sz = red[2][0];
           __syncthreads();
         }
+        sx = red[0][0];
+        sy = red[1][0];
+        sz = red[2][0];
+        __syncthreads();
         const R inb = (R)1 / (R)c.nb;
         const R mx = sx * inb, my = sy * inb, mz = sz * inb;
         if (pass == 0) {
