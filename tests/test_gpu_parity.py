@@ -141,6 +141,47 @@ def test_fully_periodic_conservation_fp64():
     assert r["u"] < 1e-12 and r["pop"] < TOL_POP_F64 and r["bead_pos"] < 1e-12
 
 
+def test_periodic_and_walled_boxes_with_chains_fp64():
+    """One context holding a fully periodic box, whose chain's spread force the
+    step kernel gathers, and a walled box, whose chain couples through the
+    force pass (which skips the periodic box's chain but still ends the
+    step): each box against its own oracle box at 1e-12, check records
+    included."""
+    rng = np.random.default_rng(11)
+    dp = (12, 10, 14)
+    posp, _ = inputs.chain_init(6, [5.5, 4.5, 6.5], rng)
+    per = Case(dp, collision=oracle.BGK, tau=0.9, periodic_mask=7,
+               u0=1e-2 * rng.standard_normal(dp[::-1] + (3,)),
+               chains=[dict(pos=posp, vel=1e-2 * rng.standard_normal((6, 3)), fix_com=False,
+                            zeta=3.0, anchor=[5.5, 4.5, 6.5])], reduce_every=5)
+    dw = (16, 14, 12)
+    xc = [7.5, 6.5, 5.5]
+    posw, velw = inputs.chain_init(8, xc, rng, bond=CHAIN_BOND)
+    walled = Case(dw, collision=oracle.BGK, tau=0.9,
+                  bc=(oracle.BC_AFFINE, inputs.ou_strain(41, rng, corr_steps=20.0, rms=1e-3), 0, 1, 0),
+                  u0=1e-3 * rng.standard_normal(dw[::-1] + (3,)),
+                  chains=[dict(pos=posw, vel=velw, anchor=xc)], reduce_every=5)
+    cases = [per, walled]
+    say("case periodic + walled boxes with chains, fp64")
+    ctx = lbm.Context([c.dims + (c.pmask,) for c in cases], collision=oracle.BGK, tau=0.9,
+                      tau_bulk=0.9, storage=STORE["f64"], reduce_every=5)
+    for k, c in enumerate(cases):
+        c.add_to(ctx, k)
+    ctx.step(40)
+    assert ctx.sync_status() == lbm.OK
+    assert ctx.read(0, lbm.F_STEP) == 40
+    for k, c in enumerate(cases):
+        ob = c.oracle_box()
+        assert ob.step(40) == 0
+        r = compare(ctx, ob, c, "f64", box=k)
+        say("box", k, c.dims, r)
+        assert r["u"] < 1e-12 and r["pop"] < TOL_POP_F64 and r["bead_pos"] < 1e-12
+        mm_o, mm_g = ob.mass_mom(), ctx.read(k, lbm.F_MASS_MOM)
+        assert mm_g[0] == mm_o[0] == 40
+        assert abs(mm_g[1] - mm_o[1]) < 1e-12 * mm_o[1]
+    ctx.close()
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_reduced_precision_storage(storage):
     """FP32 compute with FP32 / FP16-deviation storage vs the FP64 oracle."""
