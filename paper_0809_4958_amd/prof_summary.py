@@ -51,7 +51,7 @@ def kernel_source_hash() -> str:
 
 def short_name(name: str) -> str:
     """Readable kernel name: template arguments of the step kernels kept."""
-    for k in ("k_lb", "k_chain", "k_check", "k_finalize", "k_copy", "k_stamp", "k_set_pre", "k_read_sites",
+    for k in ("k_lb", "k_chain", "k_force", "k_check", "k_finalize", "k_copy", "k_set_pre", "k_read_sites",
               "k_read_beads", "k_read"):
         if k in name:
             i = name.find(k)
