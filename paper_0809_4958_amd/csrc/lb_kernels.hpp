@@ -87,7 +87,8 @@ __device__ __forceinline__ void xface_wave(const BoxDesc* __restrict__ boxes,
 
 // ---------------------------------------------------------------- chain
 // CB threads per chain (one per bead): 64 when no chain has more than 64
-// beads (one wavefront, so the workgroup barriers are nearly free), else 256.
+// beads (one wavefront: the MD substeps exchange values by cross-lane
+// operations, with no barriers), else 256 (through LDS).
 // Workgroups n_chains and up compute the x-face boundary velocities of the
 // step instead (CB / 64 work items each), so the two independent pieces of
 // work before the fused step share one launch and run side by side.
