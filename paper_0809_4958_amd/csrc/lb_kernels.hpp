@@ -51,30 +51,52 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Value of lane 0, wave-uniform (every lane active)
-__device__ __forceinline__ float lane0(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+// Value of another lane through a DPP move: CTRL the pattern, ROWS the
+// 16-lane rows written; lanes whose source is outside the pattern, and rows
+// not written, read 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_get(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
 }
-__device__ __forceinline__ double lane0(double v) {
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_get(double v) {
   const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xffffffffll));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWS, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// N sums over the 64 lanes at once (their shuffles interleaved), each with
-// the pairings of a shared-memory tree (lane j adds lane j + o for o = 32, 16,
-// ..., 1, so the same sums bit for bit), returned to every lane.  Called with
-// every lane active.
+// N sums over the 64 lanes at once, returned to every lane, in one fixed
+// order with register-to-register lane moves (DPP): within each 16-lane row
+// lane i adds lane i-1, i-2, i-4, i-8 (shifts in, zero at the row start), so
+// lane 15 of a row holds the row's sum; then rows 1 and 3 add lane 15 of the
+// row before, rows 2 and 3 add lane 31, and lane 63 holds the total.  Called
+// with every lane active.
 template <typename R, int N>
-__device__ __forceinline__ void wave_tree_sums(R (&v)[N]) {
+__device__ __forceinline__ void wave_sums(R (&v)[N]) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int k = 0; k < N; k++) v[k] += dpp_get<0x111, 0xf>(v[k]);  // row_shr:1
 #pragma unroll
-    for (int k = 0; k < N; k++) v[k] += __shfl_down(v[k], o, 64);
-  }
+  for (int k = 0; k < N; k++) v[k] += dpp_get<0x112, 0xf>(v[k]);  // row_shr:2
 #pragma unroll
-  for (int k = 0; k < N; k++) v[k] = lane0(v[k]);
+  for (int k = 0; k < N; k++) v[k] += dpp_get<0x114, 0xf>(v[k]);  // row_shr:4
+#pragma unroll
+  for (int k = 0; k < N; k++) v[k] += dpp_get<0x118, 0xf>(v[k]);  // row_shr:8
+#pragma unroll
+  for (int k = 0; k < N; k++) v[k] += dpp_get<0x142, 0xa>(v[k]);  // row_bcast:15
+#pragma unroll
+  for (int k = 0; k < N; k++) v[k] += dpp_get<0x143, 0xc>(v[k]);  // row_bcast:31
+#pragma unroll
+  for (int k = 0; k < N; k++) v[k] = lane63(v[k]);
 }
 
 // x-face boundary velocities of one work item by one wavefront (defined with
@@ -218,8 +240,8 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
   // MD substeps.  With one wavefront per chain (CB = 64) the neighbour's
   // position, the neighbour's bond force, the FENE overflow flag and the
   // centre-of-mass sums move between lanes by cross-lane operations, with no
-  // barriers; otherwise through LDS.  Both take the same sums in the same
-  // order.
+  // barriers (the sums in the fixed DPP order of wave_sums); otherwise
+  // through LDS (a fixed-order tree).
   constexpr bool WAVE = CB == 64;
   const R h = (R)1 / (R)c.substeps;
   const R decay = (R)c.decay;
@@ -302,11 +324,11 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
       rz += h * vz;
     }
     if (c.fix_com && WAVE) {
-      // fixed-order tree sums of velocity and relative position, all six at
-      // once (the position sum does not depend on the velocity correction)
+      // fixed-order sums of velocity and relative position, all six at once
+      // (the position sum does not depend on the velocity correction)
       R t[6] = {act ? vx : (R)0, act ? vy : (R)0, act ? vz : (R)0,
                 act ? rx : (R)0, act ? ry : (R)0, act ? rz : (R)0};
-      wave_tree_sums(t);
+      wave_sums(t);
       const R inb = (R)1 / (R)c.nb;
       vx -= t[0] * inb;
       vy -= t[1] * inb;
