@@ -271,17 +271,19 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
     R fx = 0, fy = 0, fz = 0;  // bond j -> j+1
     R gx = 0, gy = 0, gz = 0;  // bond j-1 -> j
     if constexpr (WAVE) {
-      const R qx = __shfl_down(rx, 1, 64), qy = __shfl_down(ry, 1, 64),
-              qz = __shfl_down(rz, 1, 64);
+      // next bead's position (wave_shl:1: lane j reads lane j+1)
+      const R qx = dpp_get<0x130, 0xf>(rx), qy = dpp_get<0x130, 0xf>(ry),
+              qz = dpp_get<0x130, 0xf>(rz);
       bool bad = false;
       if (act && j + 1 < c.nb) bad = !fene(qx - rx, qy - ry, qz - rz, fx, fy, fz);
       if (__any(bad)) {
         overflow = true;
         break;
       }
-      gx = __shfl_up(fx, 1, 64);
-      gy = __shfl_up(fy, 1, 64);
-      gz = __shfl_up(fz, 1, 64);
+      // previous bead's bond force (wave_shr:1: lane j reads lane j-1)
+      gx = dpp_get<0x138, 0xf>(fx);
+      gy = dpp_get<0x138, 0xf>(fy);
+      gz = dpp_get<0x138, 0xf>(fz);
     } else {
       spx[j] = rx;
       spy[j] = ry;
