@@ -55,18 +55,23 @@ def parse():
     return p.parse_args()
 
 
-def batch_inputs(n_boxes, n_steps, tau, dt=20, res=17, n_beads=32, config_idx=2):
+def batch_inputs(n_boxes, n_steps, tau, dt=20, res=17, n_beads=32, config_idx=2, only=None):
+    """Inputs of the batched workload; ``only`` lists the box indices to build
+    (the rest are skipped; every box's inputs depend on its index alone)."""
     from paper_0809_4958_amd import inputs
     sizes = inputs.box_sizes(n_boxes, inputs.rng(config_idx, 3))
     boxes = []
     for b, n in enumerate(sizes):
+        if only is not None and b not in only:
+            continue
         units, u0, faces = inputs.ks_box_inputs(config_idx, b, n=int(n), tau=tau,
                                                 n_steps=n_steps, dt=dt, res=res)
         xc = np.full(3, (n - 1) / 2.0)
         pos, _ = inputs.chain_init(n_beads, xc, np.random.Generator(np.random.PCG64(
             np.random.SeedSequence(entropy=inputs.ENTROPY, spawn_key=(config_idx, 2, b)))),
             bond=CHAIN_BOND)
-        boxes.append(dict(n=int(n), u0=u0, faces=faces.astype(np.float32), pos=pos, anchor=xc))
+        boxes.append(dict(n=int(n), u0=u0, faces=faces.astype(np.float32), pos=pos, anchor=xc,
+                          index=b))
     return boxes
 
 

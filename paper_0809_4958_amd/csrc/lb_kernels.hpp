@@ -254,9 +254,13 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
     if (r2 >= r02) return false;
     R fac;
     if (S != 0 && r2 > (R)0.8 * r02) {
-      // near full extension: evaluate the FENE factor in FP64
+      // near full extension: evaluate the FENE factor in FP64, and decide
+      // the range there too (within a few float ulps of R0 the FP32 test can
+      // pass while the FP64 separation has already reached R0)
       const double r2d = (double)ex * ex + (double)ey * ey + (double)ez * ez;
-      fac = (R)(c.fene_k / (1.0 - r2d / (c.fene_r0 * c.fene_r0)));
+      const double r02d = c.fene_r0 * c.fene_r0;
+      if (r2d >= r02d) return false;
+      fac = (R)(c.fene_k / (1.0 - r2d / r02d));
     } else {
       fac = fk / ((R)1 - r2 / r02);
     }

@@ -934,6 +934,11 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
   ctx->S = cfg->storage;
   ctx->coll = cfg->collision;
   ctx->fp16_exp = cfg->fp16_exp ? cfg->fp16_exp : 10;
+  // one periodic box makes the whole context take the periodic kernel
+  // instantiations, which carry only the tile items: no box of such a
+  // context may then be a row box
+  for (int i = 0; i < cfg->n_boxes; i++)
+    if (cfg->boxes[i].periodic_mask & 7u) ctx->per = true;
   int64_t off = 0;
   for (int i = 0; i < cfg->n_boxes; i++) {
     BoxHost b;
@@ -967,7 +972,6 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     off = (off + 127) / 128 * 128;
     b.off = off;
     off += nn * Q;
-    if (pm) ctx->per = true;
     {
       b.vw = cfg->storage == LB_STORE_F64 ? 0 : pick_row_words(cfg->storage, n3[0]);
       const int V = b.vw ? row_nodes(cfg->storage, b.vw) : 1;
@@ -975,7 +979,7 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
       // 32-bit buffer offsets: the planes one workgroup iteration touches
       const double plane = (double)Q * n3[0] * n3[1] * (double)store_bytes(cfg->storage);
       const double span = (WG / ((double)(n3[0] / V) * (n3[1] - 2)) + 4.0) * plane;
-      b.vec = b.vw != 0 && pm == 0u && groups < 2.0e9 && span < 2147483648.0 && !getenv("LBM_NO_VEC");
+      b.vec = b.vw != 0 && !ctx->per && groups < 2.0e9 && span < 2147483648.0 && !getenv("LBM_NO_VEC");
       // interleave Y = 2^ylog lines per population row so that a row of a
       // block spans whole 128-byte lines (row boxes only)
       b.ylog = 0;

@@ -35,6 +35,49 @@ def rel_l2(a, b, mask=None):
     return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
 
 
+def max_rel(a, b):
+    """Per-node max-norm: the largest |a - b| over every node and component,
+    relative to the largest |b| (the field's own scale; a per-node quotient
+    is ill-defined where the field crosses zero)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max() if b.size else 0.0
+    d = np.abs(a - b).max() if b.size else 0.0
+    return float(d / den) if den > 0 else float(d)
+
+
+def bead_errors(p_g, v_g, p_o, v_o, chains, u_scale):
+    """Bead errors, element by element and as norms.
+
+    Positions are compared relative to each chain's anchor and scaled by the
+    chain's size: the rms distance of the initial beads from the anchor, or
+    (a single free bead) of the oracle's final beads from it.  The kT = 0
+    chain collapses toward its anchor, so R - anchor shrinks and a plain
+    relative norm of it is ill-conditioned.  Velocities are scaled by the
+    problem's velocity scale: the larger of the largest fluid velocity of the
+    interior ``u_scale`` and the largest bead velocity.  A pinned chain's V is
+    the small difference between the fluid velocity at each bead and its
+    chain average, so its own magnitude would amplify rounding by |u|/|V|.
+      bead_pos      rms |R_g - R_o| / size
+      bead_pos_max  largest |R_g - R_o| of any bead and axis / size
+      bead_vel      rms |V_g - V_o| / u_scale
+      bead_vel_max  largest |V_g - V_o| of any bead and axis / u_scale
+    """
+    anc = np.concatenate([np.broadcast_to(c["anchor"], (len(c["pos"]), 3)) for c in chains])
+    p0 = np.concatenate([np.asarray(c["pos"]) for c in chains])
+    size = np.sqrt(np.mean(np.sum((p0 - anc) ** 2, axis=1)))
+    if not size > 0:
+        size = np.sqrt(np.mean(np.sum((np.asarray(p_o) - anc) ** 2, axis=1)))
+    u_scale = max(float(u_scale), float(np.abs(v_o).max()))
+    dp = np.asarray(p_g) - np.asarray(p_o)
+    dv = np.asarray(v_g) - np.asarray(v_o)
+    nb = len(p0)
+    return {"bead_pos": float(np.sqrt(np.sum(dp ** 2) / nb) / size),
+            "bead_pos_max": float(np.abs(dp).max() / size),
+            "bead_vel": float(np.sqrt(np.sum(dv ** 2) / nb) / u_scale),
+            "bead_vel_max": float(np.abs(dv).max() / u_scale)}
+
+
 class Case:
     """Inputs of one box: dims, collision, boundary, chains, initial field."""
 

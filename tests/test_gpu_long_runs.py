@@ -1,0 +1,140 @@
+"""Parity over the workloads' full lengths and at the large box's full size.
+
+The FP64 oracle needs hours (or ~95 GB of host memory) for these runs, so its
+values were computed beforehand by ``tests/golden/make_long_runs.py`` (which
+runs only the oracle) at the sampled interior sites of ``tests/longrun.py``:
+rows next to every face and through the middle, columns next to the x faces,
+8^3 cubes around every chain anchor and random interior nodes.  Here the HIP
+library runs the same seeded inputs and is compared with them node by node
+(rel-L2 and per-node max-norm of u and of the population deviations), bead by
+bead, and on the mass/momentum record, which sums the whole interior.
+
+* batch16: 16 boxes of the batched workload (4 of each edge), 5,000 steps, in
+  the benchmark's launch configuration (autotuned work list, graph-replayed
+  100-step chunks, check every 100 steps), FP16 and FP32 storage.
+* ks128: the 128^3 single box, one 64-bead chain, 10,000 steps, FP32 and FP16.
+* big128: the large-box setup (32 chains of 256 beads) at 128^3, 2,000 steps.
+* big512: the large box itself, 512^3 FP16, 32 x 256-bead chains, 50 steps.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import longrun
+from lbcase import bead_errors, max_rel, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+from paper_0809_4958_amd import lbm  # noqa: E402
+
+STORE = {"f32": lbm.STORE_F32, "f16": lbm.STORE_F16DEV}
+TOL = {"f32": 1e-5, "f16": 1e-3}            # rel-L2, record sums
+TOL_MAX = {"f32": 1e-4, "f16": 4e-3}        # per-node max-norms (derived in test_gpu_parity.py)
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def golden(name):
+    path = longrun.golden_path(name)
+    if not os.path.exists(path):
+        pytest.skip(f"oracle values not generated: python tests/golden/make_long_runs.py {name}")
+    return np.load(path, allow_pickle=False)
+
+
+def run(name, storage, graph_steps=100, tune=True):
+    spec = longrun.CASES[name]
+    bxs = longrun.boxes(name)
+    ctx = lbm.Context([(b["n"],) * 3 for b in bxs], collision=lbm.MRT, tau=longrun.TAU,
+                      tau_bulk=longrun.TAU, ghost_rate=1.0, storage=STORE[storage],
+                      reduce_every=spec["reduce_every"], torch_alloc=True,
+                      graph_steps=graph_steps)
+    for k, b in enumerate(bxs):
+        ctx.set_initial(k, b.pop("u0"))
+        ctx.set_boundary(k, lbm.BC_SAMPLED, b["faces"], t0=0, dt=longrun.DT, res=longrun.RES)
+        for c in b["chains"]:
+            ctx.couple_chain(k, c["pos"], None, substeps=10, fix_com=True, zeta=5.0,
+                             mass=longrun.bead_mass(len(c["pos"])), fene_k=1.0, fene_r0=2.0,
+                             anchor=c["anchor"])
+    if tune:
+        ctx.autotune(2)
+    say(f"{name} {storage}: {ctx.describe()}")
+    ctx.step(spec["steps"])
+    assert ctx.sync_status() == lbm.OK
+    assert ctx.read(0, lbm.F_STEP) == spec["steps"]
+    return ctx, bxs
+
+
+def compare_box(ctx, k, b, g, storage, label):
+    spec = longrun.CASES[label.split()[0]]
+    n = b["n"]
+    s = longrun.sites(n, [c["anchor"] for c in b["chains"]], spec["site_seed"] + b["index"])
+    x, y, z = s[:, 0], s[:, 1], s[:, 2]
+    u_g = ctx.read(k, lbm.F_U)[z, y, x]
+    dev_g = ctx.read_sites(k, s) - W[None, :]
+    u_o = g[f"u_{k}"].astype(np.float64)
+    dev_o = g[f"dev_{k}"].astype(np.float64)
+    nb = sum(len(c["pos"]) for c in b["chains"])
+    p_g = ctx.read(k, lbm.F_BEAD_POS, n_beads=nb)
+    v_g = ctx.read(k, lbm.F_BEAD_VEL, n_beads=nb)
+    r = {"u": rel_l2(u_g, u_o), "u_max": max_rel(u_g, u_o),
+         "pop": rel_l2(dev_g, dev_o), "pop_max": max_rel(dev_g, dev_o)}
+    r.update(bead_errors(p_g, v_g, g[f"bpos_{k}"], g[f"bvel_{k}"], b["chains"],
+                         float(g[f"umax_{k}"])))
+    mm_g, mm_o = ctx.read(k, lbm.F_MASS_MOM), g[f"mm_{k}"]
+    # momentum sums bounded by sqrt(interior nodes) x ||u||_2 over the interior
+    p_scale = np.sqrt((n - 2) ** 3) * float(g[f"unorm_{k}"])
+    r["mass"] = abs(mm_g[1] - mm_o[1]) / mm_o[1]
+    r["mom"] = float(np.abs(mm_g[2:] - mm_o[2:]).max() / p_scale)
+    say(f"{label} box {k} (index {b['index']}, edge {n}, {len(s)} sites):",
+        {a: f"{v:.3e}" for a, v in r.items()})
+    assert mm_g[0] == mm_o[0]
+    bad = {a: v for a, v in r.items()
+           if not v < (TOL_MAX[storage] if a.endswith("_max") else TOL[storage])}
+    assert not bad, f"{label} box {k}: over the bound: {bad}"
+    return r
+
+
+@pytest.mark.parametrize("storage", ["f16", "f32"])
+def test_batch16_full_length(storage):
+    g = golden("batch16")
+    say(f"case batch16 {storage}: 16 boxes of the batch, 5000 steps, bench launch shape")
+    ctx, bxs = run("batch16", storage)
+    assert [b["index"] for b in bxs] == list(g["indices"])
+    worst = {}
+    for k, b in enumerate(bxs):
+        r = compare_box(ctx, k, b, g, storage, f"batch16 {storage}")
+        for a, v in r.items():
+            worst[a] = max(worst.get(a, 0.0), v)
+    say(f"batch16 {storage} worst over boxes:", {a: f"{v:.3e}" for a, v in worst.items()})
+    ctx.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_ks128_full_length(storage):
+    g = golden("ks128")
+    say(f"case ks128 {storage}: 128^3, one 64-bead chain, 10000 steps")
+    ctx, bxs = run("ks128", storage)
+    compare_box(ctx, 0, bxs[0], g, storage, f"ks128 {storage}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "f32"])
+def test_big128_full_length(storage):
+    g = golden("big128")
+    say(f"case big128 {storage}: 128^3, 32 chains of 256 beads, 2000 steps")
+    ctx, bxs = run("big128", storage)
+    compare_box(ctx, 0, bxs[0], g, storage, f"big128 {storage}")
+    ctx.close()
+
+
+def test_big512_fp16():
+    g = golden("big512")
+    say("case big512 f16: 512^3, 32 chains of 256 beads, 50 steps")
+    ctx, bxs = run("big512", "f16", graph_steps=10)
+    compare_box(ctx, 0, bxs[0], g, "f16", "big512 f16")
+    ctx.close()

@@ -81,3 +81,37 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_long_run_sites_and_subset():
+    """Sites of the long-run comparisons are unique interior nodes that include
+    the rows next to every face and the cube around each anchor; the 16-box
+    subset holds four boxes of every edge, and building only those boxes
+    gives the inputs the whole batch gives them."""
+    import numpy as np
+
+    import bench
+    import longrun
+    for n in (32, 48, 96):
+        anc = [np.array([n / 3.0, n / 2.0 + 0.3, 2 * n / 3.0])]
+        s = longrun.sites(n, anc, 7)
+        assert s.min() >= 1 and s.max() <= n - 2
+        lin = (s[:, 2].astype(np.int64) * n + s[:, 1]) * n + s[:, 0]
+        assert np.all(np.diff(lin) > 0)
+        have = set(map(tuple, s.tolist()))
+        for y, z in ((1, 1), (n - 2, n - 2), (1, n - 2)):
+            assert all((x, y, z) in have for x in range(1, n - 1))
+        c = np.floor(anc[0]).astype(int)
+        assert all((c[0] + dx, c[1] + dy, c[2] + dz) in have
+                   for dx in range(-3, 5) for dy in range(-3, 5) for dz in range(-3, 5))
+    idx = longrun.batch16_indices()
+    sizes = bench.batch_inputs(256, 1, 0.6, only=set())
+    assert sizes == []
+    sub = bench.batch_inputs(256, 40, 0.6, only=set(idx[:2] + idx[-2:]))
+    full = bench.batch_inputs(256, 40, 0.6)
+    assert len(idx) == 16 and sorted(b["n"] for b in bench.batch_inputs(256, 20, 0.6, only=set(idx))) \
+        == [32] * 4 + [48] * 4 + [64] * 4 + [96] * 4
+    for b in sub:
+        f = full[b["index"]]
+        assert f["n"] == b["n"] and np.array_equal(f["faces"], b["faces"])
+        assert np.array_equal(f["u0"], b["u0"]) and np.array_equal(f["pos"], b["pos"])
