@@ -13,11 +13,21 @@ every box and boundary face + the mass/momentum check and finalisation.
 
 Prints one JSON line: MLUPS over interior nodes; the HBM roofline of the fused
 kernel (its average duration from device timestamps that the kernels record
-inside the replayed graphs, the measured copy ceiling, and the HBM traffic of the committed
+inside the replayed graphs, the measured copy ceilings -- this library's copy
+kernel and the runtime's hipMemcpyAsync -- and the HBM traffic of the committed
 counter run when it was taken on the current kernel sources); the same boxes
 run one by one as plain FP32 single-box contexts for the gain; and the oracle
 leg: the FP64 oracle's own throughput on the host cores and the FP16 velocity
 error of one box of the batch against it.
+
+Windows.  The timed region is exactly --steps steps.  The mass/momentum check
+runs every K steps, K the largest divisor of --steps up to 100, so the window
+holds --steps / K check steps whatever the warmup; the steps are replayed from
+HIP graphs whose length is a multiple of K dividing --steps, so every timed
+step is graph-replayed (both recorded in the output).  The plain-FP32 leg
+times 200 graph-replayed steps per box size after 20 warmup steps, and the
+oracle-error leg runs the workload's full 5,000 steps on one box, whatever
+--steps is.
 """
 import argparse
 import json
@@ -138,6 +148,31 @@ def time_steps(ctx, steps, torch):
     return elapsed, tm
 
 
+def check_interval(steps, cap=100):
+    """Steps between mass/momentum checks: the largest divisor of the timed
+    step count not above ``cap``, so that every timed window holds whole check
+    periods (steps / K check steps, whatever the warmup's phase)."""
+    return max(d for d in range(1, min(cap, steps) + 1) if steps % d == 0)
+
+
+def graph_length(steps, k, cap):
+    """Steps per replayed HIP graph: the largest multiple of the check interval
+    k that divides the timed step count and is at most max(cap, k), so the
+    whole timed region is graph-replayed (lb_step replays a graph only while
+    at least its length is left) and each graph holds its check steps."""
+    best, m = k, k
+    while m <= max(cap, k):
+        if steps % m == 0:
+            best = m
+        m += k
+    return best
+
+
+# fixed windows of the side legs, independent of --steps
+PLAIN_WARMUP, PLAIN_STEPS, PLAIN_GRAPH = 20, 200, 100
+ORACLE_ERR_STEPS = 5000
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -160,9 +195,12 @@ def main():
     storage = lbm.STORE_F16DEV if args.storage == "f16" else lbm.STORE_F32
     stream = torch.cuda.current_stream().cuda_stream
     copy_gbs = lbm.copy_probe(args.copy_mib << 20, 20) if args.copy_mib > 0 else None
+    memcpy_gbs = lbm.memcpy_probe(4 << 30, 10) if args.copy_mib > 0 else None
+    check_every = check_interval(args.steps)
+    gs = graph_length(args.steps, check_every, args.graph_steps) if args.graph_steps > 0 else 0
     cached = bool(args.tune_cache) and os.path.exists(args.tune_cache)
-    ctx = make_ctx(lbm, boxes, storage, tau, reduce_every=100, stream=stream,
-                   graph_steps=args.graph_steps, tune_cache=args.tune_cache)
+    ctx = make_ctx(lbm, boxes, storage, tau, reduce_every=check_every, stream=stream,
+                   graph_steps=gs, tune_cache=args.tune_cache)
     t_tune = time.time()
     if not args.no_tune and not cached:
         ctx.autotune(3)
@@ -178,6 +216,7 @@ def main():
     alg_bytes = tm[3]
     achieved = alg_bytes / (lb_ms * 1e-3) / 1e9
     traffic = committed_traffic(args.storage, args.boxes)
+    checks = sum(1 for n in range(args.warmup, total_steps) if (n + 1) % check_every == 0)
     from paper_0809_4958_amd.prof_summary import kernel_source_hash
     out = {
         "metric": METRIC,
@@ -200,7 +239,10 @@ def main():
             "boxes": args.boxes,
             "interior_nodes": int(interior),
             "storage": args.storage,
-            "graph_steps": args.graph_steps,
+            "graph_steps": gs,
+            "graph_replayed": gs > 0 and args.steps % gs == 0,
+            "check_every": check_every,
+            "check_steps_timed": checks,
             "autotuned": not args.no_tune and not cached,
             "tune_cache": args.tune_cache if cached else None,
             "autotune_s": round(t_tune, 2),
@@ -219,6 +261,7 @@ def main():
             "pre_lb_kernels_ms": round(tm[2], 4),
             "algorithmic_bytes_per_launch": alg_bytes,
             "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+            "memcpy_d2d_gbs": None if memcpy_gbs is None else round(memcpy_gbs, 1),
             "kernel_sources_sha1": kernel_source_hash(),
         },
         "input_generation_s": round(t_in, 1),
@@ -228,44 +271,44 @@ def main():
                       "k_lb_ms": round(lb_ms, 4)}), file=sys.stderr, flush=True)
 
     if not args.no_baselines:
-        # plain FP32: one single-box context per box size (graph-replayed too),
-        # timed per box-step; the batch's time is the sum over its boxes
+        # plain FP32: one single-box context per box size, each timed over a
+        # fixed graph-replayed window; the batch's time is the sum over its boxes
         sizes = sorted({b["n"] for b in boxes})
+        first = {n: next(b["index"] for b in boxes if b["n"] == n) for n in sizes}
+        singles = batch_inputs(args.boxes, PLAIN_WARMUP + PLAIN_STEPS, tau, only=set(first.values()))
         per_size_ms = {}
-        for n in sizes:
-            b = next(bb for bb in boxes if bb["n"] == n)
+        for b in singles:
             single = make_ctx(lbm, [b], lbm.STORE_F32, tau, reduce_every=100, stream=stream,
-                              graph_steps=args.graph_steps)
-            single.step(20)
+                              graph_steps=PLAIN_GRAPH)
+            single.step(PLAIN_WARMUP)
             single.sync()
-            k = min(400, total_steps - 20)
-            t, _ = time_steps(single, k, torch)
-            per_size_ms[n] = t * 1e3 / k
+            t, _ = time_steps(single, PLAIN_STEPS, torch)
+            per_size_ms[b["n"]] = t * 1e3 / PLAIN_STEPS
             single.close()
         plain_ms = sum(per_size_ms[b["n"]] for b in boxes)
         plain_mlups = interior / (plain_ms * 1e-3) / 1e6
         out["plain_fp32_single_box"] = {"mlups": round(plain_mlups, 1),
                                         "ms_per_step_all_boxes": round(plain_ms, 3),
                                         "ms_per_box_step": {str(k): round(v, 4)
-                                                            for k, v in per_size_ms.items()}}
+                                                            for k, v in per_size_ms.items()},
+                                        "window": f"{PLAIN_WARMUP} + {PLAIN_STEPS} steps, "
+                                                  f"{PLAIN_GRAPH}-step graphs"}
         out["gain_vs_plain_fp32"] = round(mlups / plain_mlups, 2)
         print(json.dumps({"progress": "plain FP32 leg done"}), file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline_leg(args, lbm, boxes, tau, storage, total_steps, stream,
-                                               torch)
+        out["cpu_baseline"] = cpu_baseline_leg(args, lbm, singles, tau, storage, stream, torch)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_leg(args, lbm, boxes, tau, storage, total_steps, stream, torch):
+def cpu_baseline_leg(args, lbm, sample_boxes, tau, storage, stream, torch):
     """The FP64 oracle on the host cores: its throughput on a bounded sample of
-    the workload, and the error of the GPU path's velocity on one 32^3 box of
-    the batch after the whole run against it."""
+    the workload (one box of each edge), and the error of the GPU path's
+    velocity on the first 32^3 box of the batch against it over the
+    workload's full 5,000 steps."""
     import oracle
-    sizes = sorted({b["n"] for b in boxes})
-    sample = [next(i for i, bb in enumerate(boxes) if bb["n"] == n) for n in sizes]
+    sizes = [b["n"] for b in sample_boxes]
     lups = 0.0
     t1 = time.perf_counter()
-    for i in sample:
-        bb = boxes[i]
+    for bb in sample_boxes:
         n = bb["n"]
         o2 = oracle.OracleBox((n, n, n), collision=oracle.MRT, tau=tau, tau_bulk=tau)
         o2.set_initial(bb["u0"])
@@ -273,7 +316,8 @@ def cpu_baseline_leg(args, lbm, boxes, tau, storage, total_steps, stream, torch)
         o2.add_chain(bb["pos"], None, mass=bead_mass(32), anchor=bb["anchor"])
         k = 0
         ts = time.perf_counter()
-        while time.perf_counter() - ts < args.cpu_seconds / len(sample) and k + 5 <= total_steps:
+        while (time.perf_counter() - ts < args.cpu_seconds / len(sample_boxes)
+               and k + 5 <= PLAIN_WARMUP + PLAIN_STEPS):
             if o2.step(5) != 0:
                 raise RuntimeError("oracle stopped with status %d" % o2.error()[0])
             k += 5
@@ -285,19 +329,19 @@ def cpu_baseline_leg(args, lbm, boxes, tau, storage, total_steps, stream, torch)
                       f"about {args.cpu_seconds:.0f} s of stepping ({lups:.3g} lattice updates)")}
     # accuracy: the first 32^3 box of the batch, alone in a context of the
     # benchmarked storage (batched and single contexts are bitwise identical),
-    # against the oracle over the whole run
-    k32 = next(i for i, b in enumerate(boxes) if b["n"] == 32)
-    b = boxes[k32]
+    # against the oracle over the workload's 5,000 steps
+    k32 = next(b["index"] for b in sample_boxes if b["n"] == 32)
+    b = batch_inputs(args.boxes, ORACLE_ERR_STEPS, tau, only={k32})[0]
     ob = oracle.OracleBox((32, 32, 32), collision=oracle.MRT, tau=tau, tau_bulk=tau, ghost_rate=1.0)
     ob.set_initial(b["u0"])
     ob.set_boundary(oracle.BC_SAMPLED, b["faces"].astype(np.float64), t0=0, dt=20, res=17)
     ob.add_chain(b["pos"], None, substeps=10, fix_com=True, zeta=5.0, mass=bead_mass(32),
                  fene_k=1.0, fene_r0=2.0, anchor=b["anchor"])
     t2 = time.perf_counter()
-    st = ob.step(total_steps)
+    st = ob.step(ORACLE_ERR_STEPS)
     t_or = time.perf_counter() - t2
-    g = make_ctx(lbm, [b], storage, tau, reduce_every=100, stream=stream)
-    g.step(total_steps)
+    g = make_ctx(lbm, [b], storage, tau, reduce_every=100, stream=stream, graph_steps=100)
+    g.step(ORACLE_ERR_STEPS)
     g.sync()
     torch.cuda.synchronize()
     _, uo = ob.rho_u()
@@ -305,9 +349,10 @@ def cpu_baseline_leg(args, lbm, boxes, tau, storage, total_steps, stream, torch)
     g.close()
     m = ob.interior_mask()
     err = float(np.linalg.norm(ug[m] - uo[m]) / np.linalg.norm(uo[m]))
-    res["rel_err_u_vs_oracle"] = {"value": err, "storage": args.storage, "box": k32, "edge": 32,
-                                  "steps": total_steps, "oracle_status": int(st),
-                                  "oracle_seconds": round(t_or, 2)}
+    err_max = float(np.abs(ug[m] - uo[m]).max() / np.abs(uo[m]).max())
+    res["rel_err_u_vs_oracle"] = {"value": err, "max_norm": err_max, "storage": args.storage,
+                                  "box": k32, "edge": 32, "steps": ORACLE_ERR_STEPS,
+                                  "oracle_status": int(st), "oracle_seconds": round(t_or, 2)}
     return res
 
 

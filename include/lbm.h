@@ -224,6 +224,13 @@ lb_status lb_get_timing(lb_ctx* ctx, double out[4]);
  * its two buffers with hipMalloc; runs on the current device's null stream. */
 lb_status lb_copy_probe(size_t bytes, int32_t iters, double* gbs);
 
+/* Independent HBM ceiling: the runtime's own device-to-device copy
+ * (hipMemcpyAsync) of `bytes` between two hipMalloc buffers, `iters` times,
+ * timed with HIP events on the null stream of the current device; returns
+ * in gbs the (read + write) bytes per second / 1e9.  Allocates and frees its
+ * two buffers. */
+lb_status lb_memcpy_probe(size_t bytes, int32_t iters, double* gbs);
+
 /* Description of the chosen launch configuration (tile shapes, grid size). */
 const char* lb_describe(const lb_ctx* ctx);
 const char* lb_last_error(const lb_ctx* ctx);

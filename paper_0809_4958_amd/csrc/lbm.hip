@@ -1681,6 +1681,38 @@ lb_status lb_copy_probe(size_t bytes, int32_t iters, double* gbs) {
   return st;
 }
 
+lb_status lb_memcpy_probe(size_t bytes, int32_t iters, double* gbs) {
+  if (!gbs || iters < 1 || bytes < 16) return LB_ERR_ARG;
+  void *a = nullptr, *b = nullptr;
+  if (hipMalloc(&a, bytes) != hipSuccess) return LB_ERR_OOM;
+  if (hipMalloc(&b, bytes) != hipSuccess) {
+    (void)hipFree(a);
+    return LB_ERR_OOM;
+  }
+  hipEvent_t e0, e1;
+  lb_status st = LB_OK;
+  if (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    st = LB_ERR_HIP;
+  } else {
+    bool ok = hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, nullptr) == hipSuccess;
+    ok = ok && hipEventRecord(e0, nullptr) == hipSuccess;
+    for (int k = 0; ok && k < iters; k++)
+      ok = hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, nullptr) == hipSuccess;
+    ok = ok && hipEventRecord(e1, nullptr) == hipSuccess;
+    float ms = 0;
+    if (!ok || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      st = LB_ERR_HIP;
+    else
+      *gbs = 2.0 * (double)bytes * iters / (ms * 1e-3) / 1e9;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  (void)hipFree(a);
+  (void)hipFree(b);
+  return st;
+}
+
 const char* lb_describe(const lb_ctx* ctx) { return ctx ? ctx->desc.c_str() : ""; }
 
 const char* lb_last_error(const lb_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }

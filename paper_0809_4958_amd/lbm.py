@@ -60,7 +60,7 @@ class LbChain(ct.Structure):
 EXPORTS = ["lb_init", "lb_set_initial", "lb_set_boundary", "lb_couple_chain", "lb_step",
            "lb_read_fields", "lb_read_sites", "lb_write_state", "lb_sync", "lb_autotune",
            "lb_set_timing", "lb_get_timing", "lb_describe", "lb_last_error", "lb_free",
-           "lb_copy_probe"]
+           "lb_copy_probe", "lb_memcpy_probe"]
 
 _lib = None
 
@@ -94,6 +94,7 @@ def load(path: str = LIB):
     lib.lb_free.argtypes = [vp]
     lib.lb_free.restype = None
     lib.lb_copy_probe.argtypes = [ct.c_size_t, ct.c_int32, vp]
+    lib.lb_memcpy_probe.argtypes = [ct.c_size_t, ct.c_int32, vp]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ct.c_int
     _lib = lib
@@ -107,6 +108,16 @@ def copy_probe(nbytes=1 << 30, iters=20) -> float:
     st = lib.lb_copy_probe(int(nbytes), int(iters), ct.byref(out))
     if st != OK:
         raise LBError(st, "lb_copy_probe failed")
+    return out.value
+
+
+def memcpy_probe(nbytes=1 << 32, iters=10) -> float:
+    """The runtime's device-to-device copy (hipMemcpyAsync): (read + write) GB/s."""
+    lib = load()
+    out = ct.c_double()
+    st = lib.lb_memcpy_probe(int(nbytes), int(iters), ct.byref(out))
+    if st != OK:
+        raise LBError(st, "lb_memcpy_probe failed")
     return out.value
 
 
