@@ -189,6 +189,20 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
  * [n][3], out = host FP64 [n][19]. */
 lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out);
 
+/* Allocation-free variant of lb_read_sites, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation): the same result, with the site list and the
+ * output staged in a static device array of the library instead of buffers
+ * it allocates per call.  At most 32768 sites per call (LB_ERR_ARG beyond;
+ * the array takes about 5.1 MiB per GPU the library runs on, until the
+ * process ends).  Needs a context whose device tables exist (it has stepped,
+ * or been read by lb_read_sites or lb_read_fields, once; else LB_ERR_STATE)
+ * and its own device current (else LB_ERR_STATE).  Every context on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other host threads)
+ * race.  No hipMalloc, hipFree or other allocation. */
+lb_status lb_read_sites_noalloc(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz,
+                                double* out);
+
 /* Restores state for resume: LB_F_POP or LB_F_POP_DEV (FP64 [19][nz][ny][nx],
  * interior used; LB_F_POP_DEV round-trips bit for bit in every storage mode),
  * LB_F_BEAD_REL (FP64 [beads][3], exact),

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -135,6 +136,38 @@ int pick_row_words(int storage, int nx) {
   return fallback;
 }
 
+// Staging of the allocation-free site readout (lb_read_sites_noalloc): the
+// site list (int32 [n][3]) followed, at a 256-byte boundary, by the output
+// populations (FP64 [n][19]) of at most NOALLOC_SITES sites.  One copy per
+// GPU the library runs on, held until the process ends.  In host code its
+// name is not a device address: host code uses only the address that
+// hipGetSymbolAddress returned for the current device (scratch_ptr below).
+constexpr int NOALLOC_SITES = 32768;
+constexpr size_t NOALLOC_XYZ_BYTES = ((size_t)3 * NOALLOC_SITES * sizeof(int) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_XYZ_BYTES + (size_t)Q * NOALLOC_SITES * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// device address of `scratch` per device, looked up once per device by lb_init
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[MAX_DEVICES] = {};
+
+// Looks up (once per device, with that device current) the device address of
+// the staging array; nullptr if the lookup fails.
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    scratch_dev[dev] = p;
+  }
+  return scratch_dev[dev];
+}
+
 }  // namespace
 
 struct lb_ctx {
@@ -146,6 +179,8 @@ struct lb_ctx {
   int S = 0, coll = 0;
   bool per = false;
   int fp16_exp = 14;
+  int dev = 0;                    // device current at lb_init
+  void* noalloc = nullptr;        // that device's address of the static staging array
   void* arena[2] = {nullptr, nullptr};
   int64_t arena_elems = 0;
   // device tables
@@ -1016,6 +1051,17 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     for (int64_t k = 0; k < nodes; k += XF_ITEM)
       xf_items.push_back(make_int4((int)bi, (int)k, (int)std::min<int64_t>(XF_ITEM, nodes - k), 0));
   }
+  // the device this context lives on, and its copy of the static staging
+  // array of the allocation-free readout
+  if (hipGetDevice(&ctx->dev) != hipSuccess) {
+    lb_free(ctx);
+    return LB_ERR_HIP;
+  }
+  ctx->noalloc = scratch_ptr(ctx->dev);
+  if (!ctx->noalloc) {
+    lb_free(ctx);
+    return LB_ERR_HIP;
+  }
   // NULL is HIP's null stream (ordered with PyTorch's default stream)
   ctx->stream = (hipStream_t)cfg->stream;
   if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1411,11 +1457,14 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
   return ctx->latched;
 }
 
-lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out) {
+}  // extern "C"
+
+namespace {
+
+lb_status check_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, const double* out) {
   lb_status s = check_box(ctx, box);
   if (s) return s;
   if (n < 0 || (n > 0 && (!xyz || !out))) return fail(ctx, LB_ERR_ARG, "invalid site list");
-  if (n == 0) return LB_OK;
   const BoxHost& b = ctx->bx[box];
   for (int k = 0; k < n; k++) {
     const int x = xyz[3 * k], y = xyz[3 * k + 1], z = xyz[3 * k + 2];
@@ -1424,15 +1473,15 @@ lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz,
                     ((b.dim.periodic_mask & 4) ? (z >= 0 && z < b.dim.nz) : (z >= 1 && z <= b.dim.nz - 2));
     if (!in) return fail(ctx, LB_ERR_ARG, "site outside the interior");
   }
-  s = prepare(ctx);
-  if (s) return s;
-  DevState st;
-  s = sync_state(ctx, &st);
-  if (s) return s;
-  int* d_xyz = (int*)dalloc(ctx, (size_t)3 * n * sizeof(int));
-  double* d_out = (double*)dalloc(ctx, (size_t)Q * n * sizeof(double));
-  if (!d_xyz || !d_out) return fail(ctx, LB_ERR_OOM, "site readout allocation failed");
-  HIPCHK(h2d(ctx, d_xyz, xyz, (size_t)3 * n * sizeof(int)));
+  return LB_OK;
+}
+
+// Populations of n sites of a box at the current step: the site list is
+// already in d_xyz (device), the kernel writes d_out (device, [n][19]), which
+// is then copied to the host buffer out.
+lb_status sites_to_host(lb_ctx* ctx, int32_t box, int32_t n, const DevState& st, const int* d_xyz,
+                        double* d_out, double* out) {
+  const BoxHost& b = ctx->bx[box];
   const int par = (int)(st.step & 1);
   const size_t sb = store_bytes(ctx->S);
   const void* src = (char*)ctx->arena[par] + (size_t)b.off * sb;
@@ -1444,11 +1493,56 @@ lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz,
   else if (ctx->S == 1) launch_sites<1>(ctx->per, nblk, ctx->stream, d, src, d_xyz, n, d_out, pre, r0);
   else launch_sites<2>(ctx->per, nblk, ctx->stream, d, src, d_xyz, n, d_out, pre, r0);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(ctx->stream));
   HIPCHK(copy_sync(ctx, out, d_out, (size_t)Q * n * sizeof(double), hipMemcpyDeviceToHost));
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out) {
+  lb_status s = check_sites(ctx, box, n, xyz, out);
+  if (s || n == 0) return s;
+  s = prepare(ctx);
+  if (s) return s;
+  DevState st;
+  s = sync_state(ctx, &st);
+  if (s) return s;
+  int* d_xyz = (int*)dalloc(ctx, (size_t)3 * n * sizeof(int));
+  double* d_out = (double*)dalloc(ctx, (size_t)Q * n * sizeof(double));
+  if (!d_xyz || !d_out) {
+    dfree(ctx, d_xyz);
+    dfree(ctx, d_out);
+    return fail(ctx, LB_ERR_OOM, "site readout allocation failed");
+  }
+  s = h2d(ctx, d_xyz, xyz, (size_t)3 * n * sizeof(int)) == hipSuccess
+          ? sites_to_host(ctx, box, n, st, d_xyz, d_out, out)
+          : fail(ctx, LB_ERR_HIP, "site list upload failed");
   dfree(ctx, d_xyz);
   dfree(ctx, d_out);
-  return ctx->latched;
+  return s ? s : ctx->latched;
+}
+
+lb_status lb_read_sites_noalloc(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out) {
+  lb_status s = check_sites(ctx, box, n, xyz, out);
+  if (s || n == 0) return s;
+  if (n > NOALLOC_SITES)
+    return fail(ctx, LB_ERR_ARG, "lb_read_sites_noalloc reads at most 32768 sites per call");
+  if (!ctx->chains_ready || !ctx->tables_ready)
+    return fail(ctx, LB_ERR_STATE, "lb_read_sites_noalloc needs a context that has stepped or been "
+                                   "read once (its device tables are built then)");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != ctx->dev)
+    return fail(ctx, LB_ERR_STATE, "lb_read_sites_noalloc called with another device current");
+  DevState st;
+  s = sync_state(ctx, &st);
+  if (s) return s;
+  int* d_xyz = (int*)ctx->noalloc;
+  double* d_out = (double*)((char*)ctx->noalloc + NOALLOC_XYZ_BYTES);
+  HIPCHK(h2d(ctx, d_xyz, xyz, (size_t)3 * n * sizeof(int)));
+  s = sites_to_host(ctx, box, n, st, d_xyz, d_out, out);
+  return s ? s : ctx->latched;
 }
 
 lb_status lb_write_state(lb_ctx* ctx, int32_t box, lb_field field, const void* src, size_t bytes) {

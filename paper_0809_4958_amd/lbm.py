@@ -60,7 +60,7 @@ class LbChain(ct.Structure):
 EXPORTS = ["lb_init", "lb_set_initial", "lb_set_boundary", "lb_couple_chain", "lb_step",
            "lb_read_fields", "lb_read_sites", "lb_write_state", "lb_sync", "lb_autotune",
            "lb_set_timing", "lb_get_timing", "lb_describe", "lb_last_error", "lb_free",
-           "lb_copy_probe", "lb_memcpy_probe"]
+           "lb_copy_probe", "lb_memcpy_probe", "lb_read_sites_noalloc"]
 
 _lib = None
 
@@ -82,6 +82,7 @@ def load(path: str = LIB):
     lib.lb_step.argtypes = [vp, ct.c_int32]
     lib.lb_read_fields.argtypes = [vp, ct.c_int32, ct.c_int, vp, ct.c_size_t, ct.c_int32]
     lib.lb_read_sites.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
+    lib.lb_read_sites_noalloc.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
     lib.lb_write_state.argtypes = [vp, ct.c_int32, ct.c_int, vp, ct.c_size_t]
     lib.lb_sync.argtypes = [vp]
     lib.lb_autotune.argtypes = [vp, ct.c_int32]
@@ -310,6 +311,17 @@ class Context:
         out = np.zeros((xyz.shape[0], Q))
         self._check(self._lib.lb_read_sites(self._h, box, xyz.shape[0], _p(xyz), _p(out)))
         return out
+
+    def read_sites_noalloc(self, box, xyz, strict=True):
+        """lb_read_sites_noalloc: the same readout staged in the library's
+        static device array (no device allocation; at most 32768 sites)."""
+        xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+        out = np.zeros((xyz.shape[0], Q))
+        st = self._lib.lb_read_sites_noalloc(self._h, box, xyz.shape[0], _p(xyz), _p(out))
+        if strict:
+            self._check(st)
+            return out
+        return out, st
 
     def write_state(self, box, field, data):
         if field == F_STEP:
