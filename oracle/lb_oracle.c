@@ -700,3 +700,84 @@ void or_read_mass_mom(const or_box* b, double out[5]) { memcpy(out, b->mass_mom,
 void or_read_last_force(const or_box* b, double* g) {
   memcpy(g, b->g, sizeof(double) * (size_t)b->nn * 3);
 }
+
+/* ------------------------------------------------------------- vorticity */
+/* The paper validates the fine box against the DNS through the vorticity
+ * magnitude |omega| = |curl u|, averaged over a control volume around the
+ * tracer (Sec. 3, Figs. 1 and 2).  Here u = j/rho is the velocity of the
+ * pre-collision moments at t_n (the readout's u), and each derivative is the
+ * second-order central difference (d u_c/d x_a)(q) = (u_c(q + e_a) -
+ * u_c(q - e_a)) / 2.  It is defined at nodes whose six axis neighbours are
+ * interior (periodic axes wrap). */
+static void node_u(const or_box* b, long m, double u[3]) {
+  double r = 0.0, j[3] = {0, 0, 0};
+  for (int i = 0; i < OR_Q; i++) {
+    const double fi = b->f[i * b->nn + m];
+    r += fi;
+    for (int a = 0; a < 3; a++) j[a] += C[i][a] * fi;
+  }
+  for (int a = 0; a < 3; a++) u[a] = j[a] / r;
+}
+
+static int vort_defined(const or_box* b, const int q[3]) {
+  if (!in_interior(b, q)) return 0;
+  for (int a = 0; a < 3; a++)
+    for (int s = -1; s <= 1; s += 2) {
+      int n[3] = {q[0], q[1], q[2]};
+      n[a] = is_periodic(b, a) ? wrap(n[a] + s, axis_n(b, a)) : n[a] + s;
+      if (!in_interior(b, n)) return 0;
+    }
+  return 1;
+}
+
+/* |curl u| at a defined node q */
+static double node_vorticity(const or_box* b, const int q[3]) {
+  double du[3][3]; /* du[c][a] = d u_c / d x_a */
+  for (int a = 0; a < 3; a++) {
+    int qp[3] = {q[0], q[1], q[2]}, qm[3] = {q[0], q[1], q[2]};
+    qp[a] = wrap(q[a] + 1, axis_n(b, a));
+    qm[a] = wrap(q[a] - 1, axis_n(b, a));
+    double up[3], um[3];
+    node_u(b, nidx(b, qp[0], qp[1], qp[2]), up);
+    node_u(b, nidx(b, qm[0], qm[1], qm[2]), um);
+    for (int c = 0; c < 3; c++) du[c][a] = 0.5 * (up[c] - um[c]);
+  }
+  const double wx = du[2][1] - du[1][2];
+  const double wy = du[0][2] - du[2][0];
+  const double wz = du[1][0] - du[0][1];
+  return sqrt(wx * wx + wy * wy + wz * wz);
+}
+
+int or_vorticity(const or_box* b, double* out) {
+  int count = 0;
+  for (int z = 0; z < b->p.nz; z++)
+    for (int y = 0; y < b->p.ny; y++)
+      for (int x = 0; x < b->p.nx; x++) {
+        const int q[3] = {x, y, z};
+        const long m = nidx(b, x, y, z);
+        if (vort_defined(b, q)) {
+          out[m] = node_vorticity(b, q);
+          count++;
+        } else {
+          out[m] = 0.0;
+        }
+      }
+  return count;
+}
+
+int or_vorticity_mean(const or_box* b, const int lo[3], const int hi[3], double* mean) {
+  for (int a = 0; a < 3; a++)
+    if (lo[a] > hi[a] || lo[a] < 0 || hi[a] >= axis_n(b, a)) return OR_ERR_ARG;
+  double s = 0.0;
+  long n = 0;
+  for (int z = lo[2]; z <= hi[2]; z++)
+    for (int y = lo[1]; y <= hi[1]; y++)
+      for (int x = lo[0]; x <= hi[0]; x++) {
+        const int q[3] = {x, y, z};
+        if (!vort_defined(b, q)) return OR_ERR_ARG;
+        s += node_vorticity(b, q);
+        n++;
+      }
+  *mean = s / (double)n;
+  return OR_OK;
+}

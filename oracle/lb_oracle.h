@@ -88,6 +88,13 @@ void or_read_beads(const or_box* b, double* pos, double* vel);
 void or_read_mass_mom(const or_box* b, double out[5]);
 /* force density g[nz][ny][nx][3] spread onto the lattice in the last step */
 void or_read_last_force(const or_box* b, double* g);
+/* vorticity magnitude |curl u| of u = j/rho at t_n by central differences
+ * (Sec. 3, Figs. 1-2): out[nz][ny][nx], 0 where a node's six axis neighbours
+ * are not all interior; returns the number of nodes where it is defined */
+int or_vorticity(const or_box* b, double* out);
+/* its mean over the node range lo..hi (inclusive, x y z); OR_ERR_ARG if the
+ * range holds a node where it is not defined */
+int or_vorticity_mean(const or_box* b, const int lo[3], const int hi[3], double* mean);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,8 @@ def _load():
         lib.or_read_beads.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
         lib.or_read_mass_mom.argtypes = [ct.c_void_p, ct.c_void_p]
         lib.or_read_last_force.argtypes = [ct.c_void_p, ct.c_void_p]
+        lib.or_vorticity.argtypes = [ct.c_void_p, ct.c_void_p]
+        lib.or_vorticity_mean.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         lib.or_lattice.argtypes = [ct.c_void_p, ct.c_void_p]
         lib.or_threads.restype = ct.c_int
         lib.or_mrt_basis.argtypes = [ct.c_void_p, ct.c_void_p]
@@ -244,6 +246,23 @@ class OracleBox:
         out = np.zeros(self.shape + (3,))
         self._lib.or_read_last_force(self._h, _ptr(out))
         return out
+
+    def vorticity(self):
+        """(|curl u| [nz, ny, nx] by central differences, 0 where undefined;
+        number of nodes where it is defined)."""
+        out = np.zeros(self.shape)
+        n = self._lib.or_vorticity(self._h, _ptr(out))
+        return out, int(n)
+
+    def vorticity_mean(self, lo, hi) -> float:
+        """Mean |curl u| over the node range lo..hi (inclusive, x y z)."""
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        hi = np.ascontiguousarray(hi, dtype=np.int32)
+        out = ct.c_double()
+        st = self._lib.or_vorticity_mean(self._h, _ptr(lo), _ptr(hi), ct.byref(out))
+        if st != OK:
+            raise ValueError("vorticity is not defined on every node of the range")
+        return out.value
 
     def interior_mask(self) -> np.ndarray:
         """Boolean [nz, ny, nx] mask of evolved (interior) nodes."""
