@@ -175,8 +175,10 @@ typedef enum {
   LB_F_STEP = 6,      /* int64 [1]: current step (the context's, box ignored) */
   LB_F_POP_DEV = 7,   /* FP64 [19][nz][ny][nx] pre-collision deviations f_i - w_i rho0: the
                          exact image of the stored state (checkpoints); boundary nodes read 0 */
-  LB_F_BEAD_REL = 8   /* FP64 [beads][3] bead position minus its chain's anchor, as stored
+  LB_F_BEAD_REL = 8,  /* FP64 [beads][3] bead position minus its chain's anchor, as stored
                          (exact image; checkpoints) */
+  LB_F_VORT = 9       /* FP64 [nz][ny][nx] vorticity magnitude |curl u| (see lb_vorticity) at
+                         the nodes whose six axis neighbours are interior; 0 elsewhere */
 } lb_field;
 
 /* Copies a field of one box at the current step to dst (host memory, or
@@ -188,6 +190,18 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
 /* Pre-collision populations of selected interior nodes: xyz = host int32
  * [n][3], out = host FP64 [n][19]. */
 lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out);
+
+/* Vorticity of the fine box, the quantity the paper compares with the DNS
+ * (Sec. 3, Figs. 1-2: the vorticity magnitude averaged over control volumes
+ * around the tracer).  |omega| = |curl u| of u = j/rho at the current step
+ * (the pre-collision moments, as LB_F_U), each derivative the second-order
+ * central difference (u_c(q + e_a) - u_c(q - e_a)) / 2, summed in FP64.
+ * vol: host int32 [n_vol][6], each control volume's inclusive node range lo
+ * x, y, z then hi x, y, z; every node of it needs its six axis neighbours in
+ * the interior (on walled axes 2 <= lo <= hi <= n-3), else LB_ERR_ARG.
+ * mean: host FP64 [n_vol], the average of |omega| over each volume.
+ * Synchronises. */
+lb_status lb_vorticity(lb_ctx* ctx, int32_t box, int32_t n_vol, const int32_t* vol, double* mean);
 
 /* Allocation-free variant of lb_read_sites, for callers that cannot allocate
  * device memory (code under stream capture, tight serving loops, harnesses

@@ -25,6 +25,7 @@
 
 #include "lbm.h"
 #include "lb_io_kernels.hpp"
+#include "lb_vort_kernels.hpp"
 #include "lb_launch.hpp"
 
 using namespace lbdev;
@@ -944,6 +945,9 @@ lb_status sync_state(lb_ctx* ctx, DevState* out) {
   return LB_OK;
 }
 
+lb_status vorticity_run(lb_ctx* ctx, int32_t box, int32_t n_vol, const int32_t* vol,
+                        double* mean_host, double* field_dev);
+
 }  // namespace
 
 // =========================================================== C ABI
@@ -1422,6 +1426,30 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
     dfree(ctx, tmp);
     return ctx->latched;
   }
+  if (field == LB_F_VORT) {
+    const size_t need = (size_t)b.nn * sizeof(double);
+    if (dst_bytes != need) return fail(ctx, LB_ERR_BUFSIZE, "LB_F_VORT needs [nz][ny][nx] doubles");
+    int v6[6];
+    for (int a = 0; a < 3; a++) {
+      const int n = a == 0 ? b.dim.nx : (a == 1 ? b.dim.ny : b.dim.nz);
+      const bool p = (b.dim.periodic_mask >> a) & 1u;
+      v6[a] = p ? 0 : 2;
+      v6[3 + a] = p ? n - 1 : n - 3;
+      if (v6[a] > v6[3 + a]) {  // no node with interior neighbours: all zero
+        v6[0] = 1;
+        v6[3] = 0;
+      }
+    }
+    double* out = dst_on_device ? (double*)dst : (double*)dalloc(ctx, need);
+    if (!out) return fail(ctx, LB_ERR_OOM, "readout allocation failed");
+    lb_status r = dzero(ctx, out, need) == hipSuccess ? LB_OK : fail(ctx, LB_ERR_HIP, "zero fill failed");
+    if (!r && v6[0] <= v6[3]) r = vorticity_run(ctx, box, 1, v6, nullptr, out);
+    if (!r) r = hipStreamSynchronize(ctx->stream) == hipSuccess ? LB_OK : fail(ctx, LB_ERR_HIP, "sync failed");
+    if (!r && !dst_on_device && copy_sync(ctx, dst, out, need, hipMemcpyDeviceToHost) != hipSuccess)
+      r = fail(ctx, LB_ERR_HIP, "copy failed");
+    if (!dst_on_device) dfree(ctx, out);
+    return r ? r : ctx->latched;
+  }
   int what;
   size_t need;
   if (field == LB_F_POP || field == LB_F_POP_DEV) {
@@ -1460,6 +1488,100 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
 }  // extern "C"
 
 namespace {
+
+template <int S>
+void launch_vort(bool per, int grid, hipStream_t s, const VortArgs& a) {
+  if (per)
+    hipLaunchKernelGGL((k_vort<S, true>), dim3(grid), dim3(VT * VT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_vort<S, false>), dim3(grid), dim3(VT * VT), 0, s, a);
+}
+
+// Vorticity of n_vol control volumes of a box (vol: [n_vol][6] = lo x, y, z,
+// hi x, y, z inclusive): their means to mean_host (may be NULL) and, when
+// field_dev is given, |omega| per node into that device [nz][ny][nx] array.
+// Every node of a volume needs its six axis neighbours in the interior.
+lb_status vorticity_run(lb_ctx* ctx, int32_t box, int32_t n_vol, const int32_t* vol,
+                        double* mean_host, double* field_dev) {
+  const BoxHost& b = ctx->bx[box];
+  const int n3[3] = {b.dim.nx, b.dim.ny, b.dim.nz};
+  std::vector<int> off(1, 0);
+  std::vector<double> count;
+  std::vector<std::array<int, 4>> shape;  // tx, ty, zslab, grid per volume
+  for (int v = 0; v < n_vol; v++) {
+    const int* lo = vol + 6 * v;
+    const int* hi = lo + 3;
+    double cnt = 1.0;
+    for (int a = 0; a < 3; a++) {
+      const bool p = (b.dim.periodic_mask >> a) & 1u;
+      const int mn = p ? 0 : 2, mx = p ? n3[a] - 1 : n3[a] - 3;
+      if (lo[a] > hi[a] || lo[a] < mn || hi[a] > mx)
+        return fail(ctx, LB_ERR_ARG, "control volume outside the nodes whose neighbours are interior");
+      cnt *= (double)(hi[a] - lo[a] + 1);
+    }
+    const int tx = (hi[0] - lo[0] + VT) / VT, ty = (hi[1] - lo[1] + VT) / VT;
+    const int ez = hi[2] - lo[2] + 1;
+    const int zslab = std::max(4, std::min(32, (int)(((int64_t)ez * tx * ty + 2047) / 2048)));
+    const int64_t grid = (int64_t)tx * ty * ((ez + zslab - 1) / zslab);
+    if (grid + off.back() >= (1 << 30)) return fail(ctx, LB_ERR_ARG, "control volumes too large");
+    shape.push_back({tx, ty, zslab, (int)grid});
+    off.push_back(off.back() + (int)grid);
+    count.push_back(cnt);
+  }
+  if (n_vol == 0) return LB_OK;
+  lb_status s = prepare(ctx);
+  if (s) return s;
+  DevState st;
+  s = sync_state(ctx, &st);
+  if (s) return s;
+  double* d_part = (double*)dalloc(ctx, (size_t)off.back() * sizeof(double));
+  int* d_off = (int*)dalloc(ctx, off.size() * sizeof(int));
+  double* d_cnt = (double*)dalloc(ctx, count.size() * sizeof(double));
+  double* d_mean = (double*)dalloc(ctx, count.size() * sizeof(double));
+  auto release = [&]() {
+    dfree(ctx, d_part);
+    dfree(ctx, d_off);
+    dfree(ctx, d_cnt);
+    dfree(ctx, d_mean);
+  };
+  if (!d_part || !d_off || !d_cnt || !d_mean) {
+    release();
+    return fail(ctx, LB_ERR_OOM, "vorticity work buffers");
+  }
+  if (h2d(ctx, d_off, off.data(), off.size() * sizeof(int)) != hipSuccess ||
+      h2d(ctx, d_cnt, count.data(), count.size() * sizeof(double)) != hipSuccess) {
+    release();
+    return fail(ctx, LB_ERR_HIP, "vorticity tables upload failed");
+  }
+  const size_t sb = store_bytes(ctx->S);
+  VortArgs a{};
+  a.b = ctx->h_boxes[box];
+  a.src = (char*)ctx->arena[(int)(st.step & 1)] + (size_t)b.off * sb;
+  a.pre = ctx->state_pre ? 1 : 0;
+  a.rho0 = ctx->cfg.rho0;
+  a.field = field_dev;
+  for (int v = 0; v < n_vol; v++) {
+    for (int k = 0; k < 3; k++) {
+      a.lo[k] = vol[6 * v + k];
+      a.hi[k] = vol[6 * v + 3 + k];
+    }
+    a.tx = shape[v][0];
+    a.ty = shape[v][1];
+    a.zslab = shape[v][2];
+    a.partials = d_part + off[v];
+    if (ctx->S == 0) launch_vort<0>(ctx->per, shape[v][3], ctx->stream, a);
+    else if (ctx->S == 1) launch_vort<1>(ctx->per, shape[v][3], ctx->stream, a);
+    else launch_vort<2>(ctx->per, shape[v][3], ctx->stream, a);
+  }
+  hipLaunchKernelGGL(k_vort_sum, dim3(1), dim3(WG), 0, ctx->stream, d_part, d_off, d_cnt, n_vol, d_mean);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && mean_host)
+    e = copy_sync(ctx, mean_host, d_mean, (size_t)n_vol * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  release();
+  if (e != hipSuccess) return fail(ctx, LB_ERR_HIP, std::string("vorticity: ") + hipGetErrorString(e));
+  return ctx->latched;
+}
 
 lb_status check_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, const double* out) {
   lb_status s = check_box(ctx, box);
@@ -1522,6 +1644,13 @@ lb_status lb_read_sites(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz,
   dfree(ctx, d_xyz);
   dfree(ctx, d_out);
   return s ? s : ctx->latched;
+}
+
+lb_status lb_vorticity(lb_ctx* ctx, int32_t box, int32_t n_vol, const int32_t* vol, double* mean) {
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  if (n_vol < 0 || (n_vol > 0 && (!vol || !mean))) return fail(ctx, LB_ERR_ARG, "invalid control volumes");
+  return vorticity_run(ctx, box, n_vol, vol, mean, nullptr);
 }
 
 lb_status lb_read_sites_noalloc(lb_ctx* ctx, int32_t box, int32_t n, const int32_t* xyz, double* out) {

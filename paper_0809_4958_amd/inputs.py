@@ -149,7 +149,15 @@ class KSField:
         e^{ik_d r_d}, which is exact; only the evaluation order differs from
         ``velocity``.
         """
+        return self._grid_eval(self._coef(x0, t), axes)
+
+    def grid_vorticity(self, x0: np.ndarray, t: float, axes: list[np.ndarray]) -> np.ndarray:
+        """Analytic vorticity curl u on the same tensor grid, [nz][ny][nx][3]:
+        the curl of Re[c e^{ik.x}] is Re[(i k x c) e^{ik.x}] mode by mode."""
         c = self._coef(x0, t)
+        return self._grid_eval(1j * np.cross(self.k, c), axes)
+
+    def _grid_eval(self, c: np.ndarray, axes: list[np.ndarray]) -> np.ndarray:
         ex = np.exp(1j * np.outer(axes[0], self.k[:, 0]))  # [nx, n]
         ey = np.exp(1j * np.outer(axes[1], self.k[:, 1]))
         ez = np.exp(1j * np.outer(axes[2], self.k[:, 2]))
@@ -316,6 +324,16 @@ def anchors(n: int, box_n: int, gen: np.random.Generator) -> np.ndarray:
     return gen.uniform(box_n / 4.0, 3.0 * box_n / 4.0, size=(n, 3))
 
 
+def ks_tracer(config_idx: int, box_idx: int, n_modes: int = 200):
+    """The KS field of a box (modes from stream 0) and its tracer's start
+    (stream 1, uniform in [-50, 50]^3 Kolmogorov lengths), both spawned per box."""
+    base = np.random.SeedSequence(entropy=ENTROPY, spawn_key=(config_idx, 0, box_idx))
+    ks = KSField(np.random.Generator(np.random.PCG64(base)), n_modes=n_modes)
+    g1 = np.random.Generator(np.random.PCG64(
+        np.random.SeedSequence(entropy=ENTROPY, spawn_key=(config_idx, 1, box_idx))))
+    return ks, g1.uniform(-50.0, 50.0, size=3)
+
+
 def ks_box_inputs(config_idx: int, box_idx: int, n: int, tau: float, n_steps: int,
                   dt: int, res: int, width_eta: float = 2.0, n_modes: int = 200):
     """Everything one KS-driven box needs: (units, initial field, face samples).
@@ -324,11 +342,7 @@ def ks_box_inputs(config_idx: int, box_idx: int, n: int, tau: float, n_steps: in
     tracer start from stream 1.  Samples are taken at steps 0, dt, 2 dt, ...
     covering ``n_steps`` (the last sample lies at or beyond n_steps).
     """
-    base = np.random.SeedSequence(entropy=ENTROPY, spawn_key=(config_idx, 0, box_idx))
-    ks = KSField(np.random.Generator(np.random.PCG64(base)), n_modes=n_modes)
-    g1 = np.random.Generator(np.random.PCG64(
-        np.random.SeedSequence(entropy=ENTROPY, spawn_key=(config_idx, 1, box_idx))))
-    x0 = g1.uniform(-50.0, 50.0, size=3)
+    ks, x0 = ks_tracer(config_idx, box_idx, n_modes)
     units = UnitMap(n, tau, width_eta)
     n_samples = -(-n_steps // dt) + 1
     steps = np.arange(n_samples) * dt

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "LB_OK", -1: "LB_ERR_ARG", -2: "LB_ERR_OOM", -3: "LB_ERR_HIP"
 BGK, MRT = 0, 1
 STORE_F64, STORE_F32, STORE_F16DEV = 0, 1, 2
 BC_AFFINE, BC_SAMPLED, BC_LEARNED = 0, 1, 2
-F_RHO, F_U, F_POP, F_BEAD_POS, F_BEAD_VEL, F_MASS_MOM, F_STEP, F_POP_DEV, F_BEAD_REL = range(9)
+F_RHO, F_U, F_POP, F_BEAD_POS, F_BEAD_VEL, F_MASS_MOM, F_STEP, F_POP_DEV, F_BEAD_REL, F_VORT = \
+    range(10)
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
 FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
@@ -60,7 +61,7 @@ class LbChain(ct.Structure):
 EXPORTS = ["lb_init", "lb_set_initial", "lb_set_boundary", "lb_couple_chain", "lb_step",
            "lb_read_fields", "lb_read_sites", "lb_write_state", "lb_sync", "lb_autotune",
            "lb_set_timing", "lb_get_timing", "lb_describe", "lb_last_error", "lb_free",
-           "lb_copy_probe", "lb_memcpy_probe", "lb_read_sites_noalloc"]
+           "lb_copy_probe", "lb_memcpy_probe", "lb_read_sites_noalloc", "lb_vorticity"]
 
 _lib = None
 
@@ -83,6 +84,7 @@ def load(path: str = LIB):
     lib.lb_read_fields.argtypes = [vp, ct.c_int32, ct.c_int, vp, ct.c_size_t, ct.c_int32]
     lib.lb_read_sites.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
     lib.lb_read_sites_noalloc.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
+    lib.lb_vorticity.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
     lib.lb_write_state.argtypes = [vp, ct.c_int32, ct.c_int, vp, ct.c_size_t]
     lib.lb_sync.argtypes = [vp]
     lib.lb_autotune.argtypes = [vp, ct.c_int32]
@@ -290,7 +292,7 @@ class Context:
     def read(self, box, field, n_beads=0, strict=True):
         if field in (F_POP, F_POP_DEV):
             shp = (Q,) + self.shape(box)
-        elif field == F_RHO:
+        elif field in (F_RHO, F_VORT):
             shp = self.shape(box)
         elif field == F_U:
             shp = self.shape(box) + (3,)
@@ -310,6 +312,14 @@ class Context:
         xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
         out = np.zeros((xyz.shape[0], Q))
         self._check(self._lib.lb_read_sites(self._h, box, xyz.shape[0], _p(xyz), _p(out)))
+        return out
+
+    def vorticity(self, box, volumes):
+        """Mean |curl u| over control volumes [(lo_xyz, hi_xyz), ...] (inclusive)."""
+        vol = np.ascontiguousarray([list(lo) + list(hi) for lo, hi in volumes],
+                                   dtype=np.int32).reshape(-1, 6)
+        out = np.zeros(vol.shape[0])
+        self._check(self._lib.lb_vorticity(self._h, box, vol.shape[0], _p(vol), _p(out)))
         return out
 
     def read_sites_noalloc(self, box, xyz, strict=True):
