@@ -6,5 +6,5 @@ import this package.  It shares no code with the GPU library: its C source
 ctypes.
 """
 from .oracle import (OracleBox, build, threads, lattice, mrt_basis, equilibrium, collide,  # noqa: F401
-                     chain_md, BGK, MRT, BC_AFFINE, BC_SAMPLED, OK, ERR_ARG, ERR_FENE,
+                     chain_md, chain_md_noise, collide_noise, philox, unit_uniform, BGK, MRT, BC_AFFINE, BC_SAMPLED, OK, ERR_ARG, ERR_FENE,
                      ERR_BEAD_OUT, ERR_UNSTABLE, ERR_STATE)

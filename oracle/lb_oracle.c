@@ -173,11 +173,97 @@ void or_collide(const or_params* p, const double f[OR_Q], const double g[3], dou
   }
 }
 
+/* ------------------------------------------------ counter-based RNG */
+/* Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers:
+ * as easy as 1, 2, 3", SC 2011): ten rounds of two 32x32->64-bit products
+ * mixed into a 128-bit counter under a 64-bit key that is bumped by the Weyl
+ * constants between rounds. */
+void or_philox4x32(const unsigned ctr[4], const unsigned key[2], unsigned out[4]) {
+  unsigned c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  unsigned k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; r++) {
+    const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0;
+    const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c2;
+    const unsigned hi0 = (unsigned)(p0 >> 32), lo0 = (unsigned)p0;
+    const unsigned hi1 = (unsigned)(p1 >> 32), lo1 = (unsigned)p1;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* 32 random bits -> uniform on (-sqrt 3, sqrt 3): mean 0, variance 1 */
+double or_unit_uniform(unsigned u) {
+  return ((double)u - 2147483647.5) * (1.7320508075688772 / 2147483648.0);
+}
+
+/* Fluctuating MRT (Duenweg, Schiller and Ladd; the LB review the paper cites
+ * for its coupling): the same relaxation as or_collide, plus on every
+ * non-conserved mode k >= 4 the noise sqrt(mu rho b_k (1 - gamma_k^2)) r_k,
+ * mu = 3 kT (k_B T in lattice units over c_s^2), rho the node's density and
+ * r_k of zero mean and unit variance.  It keeps the mode fluctuations at
+ * their equilibrium variance mu rho b_k. */
+void or_collide_noise(const or_params* p, const double f[OR_Q], const double g[3], double mu,
+                      const double r[OR_Q], double out[OR_Q]) {
+  init_tables();
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < OR_Q; i++) {
+    rho += f[i];
+    for (int a = 0; a < 3; a++) j[a] += C[i][a] * f[i];
+  }
+  double u[3];
+  for (int a = 0; a < 3; a++) u[a] = (j[a] + 0.5 * g[a]) / rho;
+  double feq[OR_Q], F[OR_Q];
+  or_equilibrium(rho, u, feq);
+  forcing_pops(u, g, F);
+  double gam[OR_Q];
+  for (int k = 0; k < OR_Q; k++) {
+    if (k < 4) gam[k] = 1.0;
+    else if (k == 4) gam[k] = 1.0 - 1.0 / p->tau_bulk;
+    else if (k < 10) gam[k] = 1.0 - 1.0 / p->tau;
+    else gam[k] = 1.0 - p->ghost_rate;
+  }
+  double ms[OR_Q];
+  for (int k = 0; k < OR_Q; k++) {
+    double m = 0.0, meq = 0.0, mf = 0.0;
+    for (int i = 0; i < OR_Q; i++) {
+      m += E[k][i] * f[i];
+      meq += E[k][i] * feq[i];
+      mf += E[k][i] * F[i];
+    }
+    ms[k] = meq + gam[k] * (m - meq) + 0.5 * (1.0 + gam[k]) * mf;
+    if (k >= 4) ms[k] += sqrt(mu * rho * B[k] * (1.0 - gam[k] * gam[k])) * r[k];
+  }
+  for (int i = 0; i < OR_Q; i++) {
+    double s = 0.0;
+    for (int k = 0; k < OR_Q; k++) s += E[k][i] * ms[k] / B[k];
+    out[i] = W[i] * s;
+  }
+}
+
 int or_chain_md(int nb, int substeps, int fix_com, double zeta, double mass, double fene_k,
                 double fene_r0, const double anchor[3], double* pos, double* vel,
                 const double* ubead, double* dp) {
+  return or_chain_md_noise(nb, substeps, fix_com, zeta, mass, fene_k, fene_r0, anchor, pos, vel,
+                           ubead, 0.0, NULL, dp);
+}
+
+int or_chain_md_noise(int nb, int substeps, int fix_com, double zeta, double mass, double fene_k,
+                      double fene_r0, const double anchor[3], double* pos, double* vel,
+                      const double* ubead, double kT, const double* rnd, double* dp) {
   const double h = 1.0 / substeps;
   const double decay = exp(-zeta * h / mass);
+  /* Langevin noise of the exact friction update: the velocity of a bead
+   * relaxing toward u + F/zeta over a substep takes the Ornstein-Uhlenbeck
+   * increment of standard deviation sqrt(kT/m (1 - e^{-2 zeta h/m})) */
+  const double kick = kT > 0.0 ? sqrt(kT / mass * (1.0 - exp(-2.0 * zeta * h / mass))) : 0.0;
   const double r02 = fene_r0 * fene_r0;
   double* F = (double*)calloc((size_t)nb * 3, sizeof(double));
   if (!F) return OR_ERR_OOM;
@@ -206,7 +292,8 @@ int or_chain_md(int nb, int substeps, int fix_com, double zeta, double mass, dou
         const double u = ubead[3 * j + a];
         const double fz = F[3 * j + a] / zeta;
         const double v0 = vel[3 * j + a];
-        const double v1 = u + fz + (v0 - u - fz) * decay;
+        double v1 = u + fz + (v0 - u - fz) * decay;
+        if (kick > 0.0) v1 += kick * rnd[((size_t)s * nb + j) * 3 + a];
         dp[3 * j + a] += mass * (v1 - v0) - F[3 * j + a] * h;
         vel[3 * j + a] = v1;
         pos[3 * j + a] += h * v1;
@@ -255,6 +342,14 @@ struct or_box {
   int n_chains;
   chain_t* chains;
   double mass_mom[5];
+  /* accelerated-frame body force: tracer acceleration samples [ns][3] */
+  int has_body, body_dt, body_ns;
+  long body_t0;
+  double* body;
+  /* thermal fluctuations: kT, Philox key, the box's index in the counter */
+  double kT;
+  unsigned key[2];
+  unsigned box_index;
 };
 
 static long nidx(const or_box* b, int x, int y, int z) {
@@ -307,6 +402,7 @@ void or_destroy(or_box* b) {
   free(b->fn);
   free(b->g);
   free(b->bc);
+  free(b->body);
   for (int c = 0; c < b->n_chains; c++) {
     free(b->chains[c].pos);
     free(b->chains[c].vel);
@@ -380,6 +476,60 @@ int or_add_chain(or_box* b, int nb, int substeps, int fix_com, double zeta, doub
   if (vel) memcpy(c->vel, vel, sizeof(double) * 3 * nb);
   b->n_chains++;
   return OR_OK;
+}
+
+int or_set_body_force(or_box* b, long t0, int dt, int n_samples, const double* accel) {
+  if (n_samples == 0 || !accel) {
+    free(b->body);
+    b->body = NULL;
+    b->has_body = 0;
+    return OR_OK;
+  }
+  if (dt < 1 || n_samples < 1) return OR_ERR_ARG;
+  double* a = (double*)malloc(sizeof(double) * 3 * (size_t)n_samples);
+  if (!a) return OR_ERR_OOM;
+  memcpy(a, accel, sizeof(double) * 3 * (size_t)n_samples);
+  free(b->body);
+  b->body = a;
+  b->has_body = 1;
+  b->body_t0 = t0;
+  b->body_dt = dt;
+  b->body_ns = n_samples;
+  return OR_OK;
+}
+
+int or_set_thermal(or_box* b, double kT, unsigned long long seed, unsigned box_index) {
+  if (!(kT >= 0.0)) return OR_ERR_ARG;
+  if (kT > 0.0 && b->p.collision != OR_MRT) return OR_ERR_ARG;
+  b->kT = kT;
+  b->key[0] = (unsigned)(seed & 0xffffffffu);
+  b->key[1] = (unsigned)(seed >> 32);
+  b->box_index = box_index;
+  return OR_OK;
+}
+
+/* tracer acceleration at step n, linear in time between samples */
+static int body_accel(const or_box* b, long n, double a[3]) {
+  const long rel = n - b->body_t0;
+  if (rel < 0) return OR_ERR_ARG;
+  const long k = rel / b->body_dt;
+  const long rem = rel - k * b->body_dt;
+  if (k >= b->body_ns || (rem > 0 && k + 1 >= b->body_ns)) return OR_ERR_ARG;
+  const double th = (double)rem / (double)b->body_dt;
+  for (int c = 0; c < 3; c++)
+    a[c] = rem > 0 ? (1.0 - th) * b->body[3 * k + c] + th * b->body[3 * (k + 1) + c] : b->body[3 * k + c];
+  return OR_OK;
+}
+
+/* the 16 unit-variance numbers of node m at step n: four Philox draws with
+ * counter (node, box, step, draw) */
+static void node_noise(const or_box* b, long m, long n, double r[16]) {
+  for (unsigned d = 0; d < 4; d++) {
+    const unsigned ctr[4] = {(unsigned)m, b->box_index, (unsigned)n, d};
+    unsigned o[4];
+    or_philox4x32(ctr, b->key, o);
+    for (int q = 0; q < 4; q++) r[4 * d + q] = or_unit_uniform(o[q]);
+  }
 }
 
 /* First face, in the order -x, +x, -y, +y, -z, +z, that contains node q; -1 if none. */
@@ -492,6 +642,8 @@ int or_step(or_box* b, int nsteps) {
       int need2;
       if (time_slot(b, n, &k, &th, &need2)) return OR_ERR_ARG;
     }
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (b->has_body && body_accel(b, n, acc)) return OR_ERR_ARG;
 
     /* 1-4: chain against the pre-collision moments at t_n; force density g */
     memset(b->g, 0, sizeof(double) * (size_t)nn * 3);
@@ -499,7 +651,8 @@ int or_step(or_box* b, int nsteps) {
     chain_t* nxt = NULL;
     if (b->n_chains) {
       nxt = (chain_t*)calloc((size_t)b->n_chains, sizeof(chain_t));
-      for (int c = 0; c < b->n_chains && !err; c++) {
+      unsigned bead0 = 0; /* index of the chain's first bead among the box's beads */
+      for (int c = 0; c < b->n_chains && !err; bead0 += (unsigned)b->chains[c].nb, c++) {
         const chain_t* ch = &b->chains[c];
         nxt[c] = *ch;
         nxt[c].pos = (double*)malloc(sizeof(double) * 3 * ch->nb);
@@ -524,9 +677,23 @@ int or_step(or_box* b, int nsteps) {
             for (int a = 0; a < 3; a++) ub[3 * j + a] += wts[8 * j + cc] * jj[a] / rho;
           }
         }
+        /* bead noise: one Philox draw per bead and substep, counter
+         * (bead index in the box, box, step, 16 + substep), three numbers used */
+        double* rnd = NULL;
+        if (!err && b->kT > 0.0) {
+          rnd = (double*)malloc(sizeof(double) * 3 * (size_t)ch->nb * ch->substeps);
+          for (int s2 = 0; s2 < ch->substeps; s2++)
+            for (int j = 0; j < ch->nb; j++) {
+              const unsigned ctr[4] = {bead0 + (unsigned)j, b->box_index, (unsigned)n, 16u + (unsigned)s2};
+              unsigned o[4];
+              or_philox4x32(ctr, b->key, o);
+              for (int a = 0; a < 3; a++) rnd[((size_t)s2 * ch->nb + j) * 3 + a] = or_unit_uniform(o[a]);
+            }
+        }
         if (!err)
-          err = or_chain_md(ch->nb, ch->substeps, ch->fix_com, ch->zeta, ch->mass, ch->fene_k,
-                            ch->fene_r0, ch->anchor, nxt[c].pos, nxt[c].vel, ub, dp);
+          err = or_chain_md_noise(ch->nb, ch->substeps, ch->fix_com, ch->zeta, ch->mass, ch->fene_k,
+                                  ch->fene_r0, ch->anchor, nxt[c].pos, nxt[c].vel, ub, b->kT, rnd, dp);
+        free(rnd);
         if (!err)
           for (int j = 0; j < ch->nb; j++)
             for (int cc = 0; cc < 8; cc++)
@@ -561,8 +728,22 @@ int or_step(or_box* b, int nsteps) {
           const int q[3] = {x, y, z};
           double fin[OR_Q], fout[OR_Q];
           if (in_interior(b, q)) {
-            for (int i = 0; i < OR_Q; i++) fin[i] = b->f[i * nn + m];
-            or_collide(&b->p, fin, &b->g[3 * m], fout);
+            double rho = 0.0;
+            for (int i = 0; i < OR_Q; i++) {
+              fin[i] = b->f[i * nn + m];
+              rho += fin[i];
+            }
+            /* accelerated frame: force density -rho dv/dt on top of the chains' */
+            double gt[3];
+            for (int a = 0; a < 3; a++) gt[a] = b->g[3 * m + a] - rho * acc[a];
+            if (b->kT > 0.0) {
+              double r16[16], r[OR_Q] = {0};
+              node_noise(b, m, n, r16);
+              for (int k = 4; k < OR_Q; k++) r[k] = r16[k - 4];
+              or_collide_noise(&b->p, fin, gt, 3.0 * b->kT, r, fout);
+            } else {
+              or_collide(&b->p, fin, gt, fout);
+            }
           } else {
             double ubv[3];
             int st = or_boundary_velocity(b, x, y, z, n, ubv);

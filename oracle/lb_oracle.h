@@ -62,6 +62,19 @@ int or_chain_md(int nb, int substeps, int fix_com, double zeta, double mass, dou
                 double fene_r0, const double anchor[3], double* pos, double* vel,
                 const double* ubead, double* dp);
 
+/* or_chain_md with Langevin noise at temperature kT: rnd[substeps][nb][3]
+ * unit-variance numbers (NULL when kT = 0) */
+int or_chain_md_noise(int nb, int substeps, int fix_com, double zeta, double mass, double fene_k,
+                      double fene_r0, const double anchor[3], double* pos, double* vel,
+                      const double* ubead, double kT, const double* rnd, double* dp);
+/* fluctuating MRT collision: mu = 3 kT, r[k] (k >= 4) unit-variance numbers */
+void or_collide_noise(const or_params* p, const double f[OR_Q], const double g[3], double mu,
+                      const double r[OR_Q], double out[OR_Q]);
+/* Philox4x32-10 counter-based generator, and its map of 32 bits to a uniform
+ * number of mean 0 and variance 1 */
+void or_philox4x32(const unsigned ctr[4], const unsigned key[2], unsigned out[4]);
+double or_unit_uniform(unsigned u);
+
 or_box* or_create(const or_params* p);
 void or_destroy(or_box* b);
 /* f(x,0) = f_eq(rho0, u(x)) on interior nodes; u = [nz][ny][nx][3] or NULL (rest) */
@@ -75,6 +88,14 @@ int or_set_boundary(or_box* b, int mode, long t0, int dt, int n_samples, int res
 int or_add_chain(or_box* b, int nb, int substeps, int fix_com, double zeta, double mass,
                  double fene_k, double fene_r0, const double anchor[3], const double* pos,
                  const double* vel);
+/* accelerated-frame body force (Sec. 2): the tracer acceleration a = dv/dt,
+ * accel[n_samples][3] (lattice units) at steps t0 + k dt, linear in time
+ * between samples; every interior node receives -rho a.  n_samples = 0 clears */
+int or_set_body_force(or_box* b, long t0, int dt, int n_samples, const double* accel);
+/* thermal fluctuations at kT (MRT only): fluctuating collision and bead
+ * Langevin noise from Philox4x32-10 with key = seed and counters (node, box,
+ * step, draw 0..3) for the fluid and (bead, box, step, 16 + substep) for beads */
+int or_set_thermal(or_box* b, double kT, unsigned long long seed, unsigned box_index);
 /* advance n steps; stops at and latches the first error */
 int or_step(or_box* b, int n);
 long or_get_step(const or_box* b);

@@ -70,6 +70,17 @@ def _load():
         lib.or_read_beads.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
         lib.or_read_mass_mom.argtypes = [ct.c_void_p, ct.c_void_p]
         lib.or_read_last_force.argtypes = [ct.c_void_p, ct.c_void_p]
+        lib.or_set_body_force.argtypes = [ct.c_void_p, ct.c_long, ct.c_int, ct.c_int, ct.c_void_p]
+        lib.or_set_thermal.argtypes = [ct.c_void_p, ct.c_double, ct.c_ulonglong, ct.c_uint]
+        lib.or_philox4x32.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        lib.or_unit_uniform.argtypes = [ct.c_uint]
+        lib.or_unit_uniform.restype = ct.c_double
+        lib.or_collide_noise.argtypes = [ct.POINTER(_Params), ct.c_void_p, ct.c_void_p, ct.c_double,
+                                         ct.c_void_p, ct.c_void_p]
+        lib.or_chain_md_noise.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_double, ct.c_double,
+                                          ct.c_double, ct.c_double, ct.c_void_p, ct.c_void_p,
+                                          ct.c_void_p, ct.c_void_p, ct.c_double, ct.c_void_p,
+                                          ct.c_void_p]
         lib.or_vorticity.argtypes = [ct.c_void_p, ct.c_void_p]
         lib.or_vorticity_mean.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         lib.or_lattice.argtypes = [ct.c_void_p, ct.c_void_p]
@@ -154,6 +165,45 @@ def chain_md(pos, vel, ubead, substeps=10, fix_com=False, zeta=5.0, mass=1.0, fe
     return st, pos, vel, dp
 
 
+def philox(ctr, key):
+    """Philox4x32-10 of a 128-bit counter under a 64-bit key: four uint32."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.or_philox4x32(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def unit_uniform(u) -> float:
+    """32 random bits -> uniform on (-sqrt 3, sqrt 3) (mean 0, variance 1)."""
+    return float(_load().or_unit_uniform(int(u)))
+
+
+def collide_noise(f, g, mu, r, **kw) -> np.ndarray:
+    """Fluctuating MRT collision of one node: mu = 3 kT, r[19] (modes k >= 4 used)."""
+    lib = _load()
+    p = _params(**kw)
+    out = np.zeros(Q)
+    lib.or_collide_noise(ct.byref(p), _ptr(_f64(f)), _ptr(_f64(g)), float(mu), _ptr(_f64(r)),
+                         _ptr(out))
+    return out
+
+
+def chain_md_noise(pos, vel, ubead, kT, rnd, substeps=10, fix_com=False, zeta=5.0, mass=1.0,
+                   fene_k=1.0, fene_r0=2.0, anchor=(0.0, 0.0, 0.0)):
+    """chain_md with Langevin noise: rnd[substeps][nb][3] unit-variance numbers."""
+    lib = _load()
+    pos = _f64(pos).copy()
+    vel = _f64(vel).copy()
+    nb = pos.shape[0]
+    dp = np.zeros((nb, 3))
+    st = lib.or_chain_md_noise(nb, substeps, int(fix_com), zeta, mass, fene_k, fene_r0,
+                               _ptr(_f64(anchor)), _ptr(pos), _ptr(vel), _ptr(_f64(ubead)),
+                               float(kT), _ptr(_f64(rnd)), _ptr(dp))
+    return st, pos, vel, dp
+
+
 class OracleBox:
     """One lattice box: ``dims`` = (nx, ny, nz) nodes including the boundary layer."""
 
@@ -200,6 +250,16 @@ class OracleBox:
         v = None if vel is None else _ptr(_f64(vel))
         return self._lib.or_add_chain(self._h, pos.shape[0], substeps, int(fix_com), zeta, mass,
                                       fene_k, fene_r0, _ptr(_f64(anchor)), _ptr(pos), v)
+
+    def set_body_force(self, accel, t0=0, dt=1):
+        """Tracer acceleration samples [n][3] (lattice units); None clears."""
+        if accel is None:
+            return self._lib.or_set_body_force(self._h, 0, 1, 0, None)
+        a = _f64(accel).reshape(-1, 3)
+        return self._lib.or_set_body_force(self._h, t0, dt, a.shape[0], _ptr(a))
+
+    def set_thermal(self, kT, seed=0, box_index=0):
+        return self._lib.or_set_thermal(self._h, float(kT), int(seed), int(box_index))
 
     def step(self, n=1) -> int:
         return self._lib.or_step(self._h, int(n))
