@@ -63,7 +63,9 @@ def test_momentum_balance_uses_the_local_density_and_time_interpolation():
     # instead of the local density would be off by (M - N) |a| 4 = 5.6e-5
     assert np.abs(P1 - P0 - want).max() < 1e-13 * M
     assert abs(ob.pop().sum() - M) < 1e-12 * M
-    # step 4 would need the sample after a1: refused, never extrapolated
+    # step 4 sits on the last sample; step 5 would need the one after it:
+    # refused, never extrapolated
+    assert ob.step(1) == 0
     assert ob.step(1) == oracle.ERR_ARG
 
 
