@@ -162,6 +162,62 @@ typedef struct {
 lb_status lb_couple_chain(lb_ctx* ctx, int32_t box, const lb_chain* chain, const double* pos,
                           const double* vel);
 
+/* Accelerated-frame body force of one box (Sec. 2: in the frame of the
+ * tracer, which moves with velocity v(t), the transformed field w = u - v
+ * obeys the Navier-Stokes equation with the extra force density rho times
+ * -dv/dt).  accel: host FP64 [n_samples][3], the tracer acceleration dv/dt in
+ * lattice units (velocity per step) at steps t0 + k dt, linear in time
+ * between samples; stepping outside [t0, t0 + (n_samples-1) dt] fails with
+ * LB_ERR_ARG (no extrapolation).  Every interior node then receives the force
+ * density -rho(x, t_n) a(t_n), rho its pre-collision density, through the
+ * collision's forcing, on top of the chains' spread force.  n_samples = 0
+ * (accel may be NULL) removes it.  Copied; may be replaced between lb_step
+ * calls.  While any box has one, the steps run the extended collision. */
+lb_status lb_set_body_force(lb_ctx* ctx, int32_t box, int64_t t0, int32_t dt, int32_t n_samples,
+                            const double* accel);
+
+/* Sub-volume history files.  The paper couples its two scales through data
+ * on disk (Sec. 1): the velocity of the sub-volume around the tracer, stored
+ * during the coarse run, Galilei transformed into the tracer frame and
+ * linearly interpolated onto the fine lattice (Sec. 2).  Format (little
+ * endian), version 1:
+ *   char    magic[8]   "LBSUBVOL"
+ *   int32   version    1
+ *   int32   R          sample-grid points per edge (2..1024)
+ *   int32   n_samples
+ *   int32   dt         LB steps between samples
+ *   int64   t0         LB step of the first sample
+ *   int32   flags      bit 0: tracer accelerations follow the velocities
+ *   int32   reserved   0
+ *   float32 w[n_samples][R][R][R][3]   tracer-frame velocity in lattice
+ *                                      units, index [z][y][x][component]
+ *   float64 accel[n_samples][3]        (flags bit 0) tracer acceleration
+ *                                      dv/dt in lattice units per step
+ * Grid point p of an axis lies at node coordinate p (n - 1)/(R - 1) of the box
+ * (corner aligned).  lb_load_subvolume reads a file for one box and applies
+ * what `what` asks for: LB_SUBVOL_BOUNDARY -- the six faces of the grid as a
+ * SAMPLED boundary history (lb_set_boundary); LB_SUBVOL_INITIAL -- sample 0
+ * interpolated trilinearly (FP64) onto every node as the initial field
+ * (lb_set_initial; only before the first lb_step); LB_SUBVOL_BODY -- the
+ * accelerations as the box's body force (lb_set_body_force).  A malformed or
+ * truncated file gives LB_ERR_ARG and changes nothing. */
+enum { LB_SUBVOL_INITIAL = 1, LB_SUBVOL_BOUNDARY = 2, LB_SUBVOL_BODY = 4 };
+lb_status lb_load_subvolume(lb_ctx* ctx, int32_t box, const char* path, int32_t what);
+
+/* Thermal fluctuations at temperature kT (k_B T in lattice units), for the
+ * Stokes-friction coupling of beads and fluid the paper builds on (Sec. 1)
+ * in its fluctuating form: every relaxed MRT mode k >= 4 gains the noise
+ * sqrt(mu rho b_k (1 - gamma_k^2)) r_k, mu = 3 kT, gamma_k its relaxation
+ * factor and b_k its norm, and every bead's exact friction update over a
+ * substep h gains the Ornstein-Uhlenbeck kick sqrt(kT/m (1 - e^{-2 zeta h/m}))
+ * r.  The r are uniform numbers of mean 0 and variance 1 from the
+ * counter-based generator Philox4x32-10 under the 64-bit key `seed`, counter
+ * (node index (z ny + y) nx + x, box, step, draw 0..3) for the fluid and
+ * (bead index among the box's beads, box, step, 16 + substep) for the beads,
+ * so a run is reproducible bit for bit.  MRT contexts only (LB_ERR_ARG
+ * otherwise); kT = 0 switches it off.  Only before the first lb_step. */
+lb_status lb_set_thermal(lb_ctx* ctx, double kT, uint64_t seed);
+
 /* Advances every box by n_steps (asynchronous on the context stream). */
 lb_status lb_step(lb_ctx* ctx, int32_t n_steps);
 

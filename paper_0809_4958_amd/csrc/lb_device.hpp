@@ -105,6 +105,10 @@ struct BoxDesc {
   int ylog;             // log2 of the rows interleaved per population row (see aidx)
   int vw;               // row boxes: 32-bit words per lane vector (2 or 3)
   int xf_off;           // row boxes: first float of the box's x-face velocities, else -1
+  int index;            // the box's index (random-number counters)
+  int body_dt, body_ns; // accelerated-frame body force: samples every body_dt steps
+  int64_t body_t0;      // step of the first sample
+  const double* body;   // tracer acceleration [body_ns][3] (lattice units), NULL = none
 };
 
 struct Item {
@@ -114,9 +118,11 @@ struct Item {
 };
 
 struct ChainDesc {
-  int box, first, nb, substeps, fix_com, pad;
+  int box, first, nb, substeps, fix_com;
+  int bead0;            // index of the chain's first bead among its box's beads
   double zeta, mass, fene_k, fene_r0;
   double decay;         // exp(-zeta h / mass), h = 1/substeps
+  double kick;          // Langevin velocity kick sqrt(kT/m (1 - exp(-2 zeta h/m))), 0 at kT = 0
   int ai[3];            // integer part of the anchor
   double af[3];         // fractional part of the anchor
 };
@@ -276,6 +282,54 @@ __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omeg
 }
 
 // ---------------------------------------------------------------------------
+// Thermal fluctuations.  Counter-based random numbers: Philox4x32-10 (Salmon,
+// Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC
+// 2011) -- ten rounds of two 32 x 32 -> 64-bit products mixed into the 128-bit
+// counter under a 64-bit key bumped by the Weyl constants -- and the map of
+// 32 random bits to a uniform number on (-sqrt 3, sqrt 3), mean 0, variance 1.
+__device__ __forceinline__ void philox4x32(unsigned (&c)[4], unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    const unsigned lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const unsigned lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ double unit_uniform(unsigned u) {
+  return ((double)u - 2147483647.5) * (1.7320508075688772 / 2147483648.0);
+}
+
+// What a node's collision adds to the plain step: the accelerated-frame force
+// density -rho a (Sec. 2) and, when mu = 3 kT > 0, the fluctuating collision;
+// its random numbers come from the Philox counter (node, box, step, draw 0..3).
+template <typename R>
+struct Ext {
+  R ax, ay, az;
+  R mu;
+  unsigned k0, k1;
+  unsigned node, box, step;
+};
+
+// the 16 unit-variance numbers of a node (modes 4..18 use the first 15)
+template <typename R>
+__device__ __forceinline__ void mode_noise(const Ext<R>& e, R (&r)[16]) {
+#pragma unroll
+  for (unsigned dd = 0; dd < 4; dd++) {
+    unsigned c[4] = {e.node, e.box, e.step, dd};
+    philox4x32(c, e.k0, e.k1);
+#pragma unroll
+    for (int q = 0; q < 4; q++) r[4 * dd + q] = (R)unit_uniform(c[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // MRT in pair form.  Directions come in opposite pairs (2p-1, 2p), p = 1..9,
 // with representative velocities (1,0,0) (0,1,0) (0,0,1) (1,1,0) (1,-1,0)
 // (1,0,1) (1,0,-1) (0,1,1) (0,1,-1).  Even basis polynomials see the pair sum
@@ -396,9 +450,14 @@ static_assert(pair_backward_matches_basis(), "pair-form back transform != basis"
 
 // MRT collision in pair form on deviations (moments of d equal those of f for
 // k >= 1; m_0 is the density deviation).  GZ: ghost relaxation rate 1.
-template <typename R, bool GZ>
+// NOISE: the fluctuating collision (Duenweg, Schiller and Ladd): every relaxed
+// mode k >= 4 gains sqrt(mu rho b_k (1 - gamma_k^2)) r_k, which keeps its
+// fluctuations at the equilibrium variance mu rho b_k (mu = 3 kT); the ghosts
+// are then formed whatever GZ says.
+template <typename R, bool GZ, bool NOISE = false>
 __device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rho0, R omega,
-                                                  R om_bulk, R om_ghost) {
+                                                  R om_bulk, R om_ghost,
+                                                  const Ext<R>* ext = nullptr) {
   R m[Q];
   mrt_forward<R>(d, m);
   const R drho = m[0];
@@ -440,12 +499,30 @@ __device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rh
     const R eq = rho * ux * uz;
     M[9] = (eq + gs * (m[9] - eq) + hs * (ux * gz + uz * gx)) * (R)9;
   }
-  if (!GZ) {
+  if constexpr (NOISE) {
     const R gg = (R)1 - om_ghost;
 #pragma unroll
-    for (int k = 10; k < Q; k++) M[k] = gg * m[k] * (R)INVB[k];
+    for (int k = 10; k < Q; k++) M[k] = GZ ? (R)0 : gg * m[k] * (R)INVB[k];
+    R r[16];
+    mode_noise<R>(*ext, r);
+    const R mr = ext->mu * rho;
+    const R ab = sqrt(mr * ((R)1 - gb * gb)), as = sqrt(mr * ((R)1 - gs * gs)),
+            ag = sqrt(mr * ((R)1 - gg * gg));
+    // noise of mode k, divided by b_k like the relaxed moments: a r_k / sqrt(b_k)
+    M[4] += ab * r[0] * (R)sqrt(INVB[4]);
+#pragma unroll
+    for (int k = 5; k < 10; k++) M[k] += as * r[k - 4] * (R)sqrt(INVB[k]);
+#pragma unroll
+    for (int k = 10; k < Q; k++) M[k] += ag * r[k - 4] * (R)sqrt(INVB[k]);
+    mrt_backward<R, false>(M, d);
+  } else {
+    if (!GZ) {
+      const R gg = (R)1 - om_ghost;
+#pragma unroll
+      for (int k = 10; k < Q; k++) M[k] = gg * m[k] * (R)INVB[k];
+    }
+    mrt_backward<R, GZ>(M, d);
   }
-  mrt_backward<R, GZ>(M, d);
 }
 
 // Arena layout: pop[z][y / Y][i][y % Y][x] (x fastest), Y = 2^ylog.  The

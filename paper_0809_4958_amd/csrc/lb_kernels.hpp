@@ -114,7 +114,7 @@ __device__ __forceinline__ void xface_wave(const BoxDesc* __restrict__ boxes,
 // Workgroups n_chains and up compute the x-face boundary velocities of the
 // step instead (CB / 64 work items each), so the two independent pieces of
 // work before the fused step share one launch and run side by side.
-template <int S, bool PER, int CB>
+template <int S, bool PER, int CB, bool TH = false>
 __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
                                               const ChainDesc* __restrict__ chains,
                                               const typename Store<S>::T* __restrict__ a0,
@@ -127,7 +127,8 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
                                               int* __restrict__ bbox, DevState* __restrict__ st,
                                               double rho0_d, int pre, long long* stamp,
                                               int n_chains, const int4* __restrict__ xf_items,
-                                              int n_xf_items, float* __restrict__ xface) {
+                                              int n_xf_items, float* __restrict__ xface,
+                                              unsigned key0, unsigned key1) {
   using R = typename Store<S>::R;
   const int ci = blockIdx.x;
   if (ci >= n_chains) {
@@ -317,8 +318,18 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
         Fz -= gz;
       }
       const R tx = ux + Fx / zeta, ty = uy + Fy / zeta, tz = uz + Fz / zeta;
-      const R nvx = tx + (vx - tx) * decay, nvy = ty + (vy - ty) * decay,
-              nvz = tz + (vz - tz) * decay;
+      R nvx = tx + (vx - tx) * decay, nvy = ty + (vy - ty) * decay, nvz = tz + (vz - tz) * decay;
+      if constexpr (TH) {
+        // Langevin noise of the exact friction update: the Ornstein-Uhlenbeck
+        // kick of the substep, from the Philox counter (bead index in the box,
+        // box, step, 16 + substep)
+        unsigned cc[4] = {(unsigned)(c.bead0 + j), (unsigned)b.index, (unsigned)step, 16u + (unsigned)s};
+        philox4x32(cc, key0, key1);
+        const double kick = c.kick;
+        nvx += (R)(kick * unit_uniform(cc[0]));
+        nvy += (R)(kick * unit_uniform(cc[1]));
+        nvz += (R)(kick * unit_uniform(cc[2]));
+      }
       dpx += mass * (nvx - vx) - Fx * h;
       dpy += mass * (nvy - vy) - Fy * h;
       dpz += mass * (nvz - vz) - Fz * h;
@@ -554,6 +565,8 @@ struct LbArgs {
   double rho0, omega, om_bulk, om_ghost;
   int pre;
   int advance;
+  double kT;               // thermal fluctuations (fluctuating MRT) when > 0
+  unsigned key0, key1;     // Philox key of the context's random numbers
 };
 
 // Collision dispatcher: 0 BGK, 1 MRT, 2 MRT with ghost rate 1.
@@ -563,6 +576,65 @@ __device__ __forceinline__ void collide_any(R d[Q], R gx, R gy, R gz, R rho0, R 
   if (COLL == 0) collide<R, 0>(d, gx, gy, gz, rho0, omega, omb, omg);
   else if (COLL == 1) collide_mrt_pairs<R, false>(d, gx, gy, gz, rho0, omega, omb, omg);
   else collide_mrt_pairs<R, true>(d, gx, gy, gz, rho0, omega, omb, omg);
+}
+
+// Tracer acceleration of a box at step n (accelerated-frame body force,
+// Sec. 2): linear in time between samples, in FP64 like the samples.
+template <typename R>
+__device__ __forceinline__ void body_accel(const BoxDesc& b, long long n, R& ax, R& ay, R& az) {
+  ax = ay = az = (R)0;
+  if (!b.body) return;
+  long long rel = n - b.body_t0;
+  if (rel < 0) rel = 0;
+  long long k = rel / b.body_dt, rem = rel - k * b.body_dt;
+  if (k >= b.body_ns) {
+    k = b.body_ns - 1;
+    rem = 0;
+  }
+  const double* a0 = b.body + 3 * k;
+  if (rem > 0 && k + 1 < b.body_ns) {
+    const double th = (double)rem / (double)b.body_dt;
+    ax = (R)((1.0 - th) * a0[0] + th * a0[3]);
+    ay = (R)((1.0 - th) * a0[1] + th * a0[4]);
+    az = (R)((1.0 - th) * a0[2] + th * a0[5]);
+  } else {
+    ax = (R)a0[0];
+    ay = (R)a0[1];
+    az = (R)a0[2];
+  }
+}
+
+// The per-step part of a box's collision extensions (node counter set per node).
+template <typename R>
+__device__ __forceinline__ Ext<R> make_ext(const LbArgs& A, const BoxDesc& b, long long step) {
+  Ext<R> e;
+  body_accel<R>(b, step, e.ax, e.ay, e.az);
+  e.mu = (R)(3.0 * A.kT);
+  e.k0 = A.key0;
+  e.k1 = A.key1;
+  e.node = 0u;
+  e.box = (unsigned)b.index;
+  e.step = (unsigned)step;
+  return e;
+}
+
+// Collision with the extensions: the force density of the chains g plus the
+// body force -rho a (rho the node's pre-collision density), and the
+// fluctuating collision when mu > 0 (MRT only).
+template <typename R, int COLL>
+__device__ __forceinline__ void collide_ext(R d[Q], R gx, R gy, R gz, R rho0, R omega, R omb,
+                                            R omg, const Ext<R>& e) {
+  R drho = 0;
+#pragma unroll
+  for (int i = 0; i < Q; i++) drho += d[i];
+  const R rho = rho0 + drho;
+  gx -= rho * e.ax;
+  gy -= rho * e.ay;
+  gz -= rho * e.az;
+  if (COLL != 0 && e.mu > (R)0)
+    collide_mrt_pairs<R, COLL == 2, true>(d, gx, gy, gz, rho0, omega, omb, omg, &e);
+  else
+    collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
 }
 
 // Spread force g(x) = - sum_j w_jx dP_j at node (x, y, z): chains whose stencil
@@ -608,10 +680,10 @@ __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
 // Interior tile of a non-periodic box whose population groups (0..9 and
 // 10..18) each span less than 4 GiB: every load is one 32-bit offset add on
 // a per-thread node offset plus a scalar (uniform) group base.
-template <int S, int COLL, int BS>
+template <int S, int COLL, int BS, bool EXT>
 __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, const Item& it,
                                           const typename Store<S>::T* src,
-                                          typename Store<S>::T* dst, bool pre,
+                                          typename Store<S>::T* dst, bool pre, long long step,
                                           typename Store<S>::R rho0,
                                           typename Store<S>::R omega, typename Store<S>::R omb,
                                           typename Store<S>::R omg) {
@@ -634,6 +706,8 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
   const float dc0 = b.dec[0], dc1 = b.dec[1], dc2 = b.dec[2];
   const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
   const int plane = it.ex * it.ey;
+  Ext<R> ext{};
+  if constexpr (EXT) ext = make_ext<R>(A, b, step);
 #pragma unroll 1
   for (int p = threadIdx.x; p < plane; p += BS) {
     const int x = it.x0 + p % it.ex;
@@ -648,7 +722,12 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
         const float k = WCLS[i] == 0 ? dc0 : (WCLS[i] == 1 ? dc1 : dc2);
         d[i] = St::dec(v, k);
       }
-      collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+      if constexpr (EXT) {
+        ext.node = ((unsigned)z * ny + (unsigned)y) * nx + (unsigned)x;
+        collide_ext<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
+      } else {
+        collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+      }
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float k = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
@@ -767,7 +846,7 @@ __device__ __forceinline__ void vput(unsigned (&w)[W], int e, typename Store<S>:
   }
 }
 
-template <int S, int W, int COLL, bool PRE, int BS>
+template <int S, int W, int COLL, bool PRE, int BS, bool EXT>
 __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, const Item& it,
                                           const typename Store<S>::T* src,
                                           typename Store<S>::T* dst, long long step,
@@ -798,6 +877,8 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
   // lane's line offsets for y - c_y, c_y = 1, 0, -1
   const int ps = (int)psb;
   auto ybytes = [&](int yy) { return (yy >> yl) * bkb + (yy & ym) * nxb; };
+  Ext<R> ext{};
+  if constexpr (EXT) ext = make_ext<R>(A, b, step);
 #pragma unroll 1
   for (int qb = it.x0; qb < q_end; qb += BS) {
     const int zf = 1 + (qb / L) / nyi;             // first plane of this iteration
@@ -885,7 +966,12 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
         d[i] = St::dec(velem<S, W>(raw[i], left[i], right[i], e), kd);
       }
       const int x = x0 + k;
-      collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+      if constexpr (EXT) {
+        ext.node = ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
+        collide_ext<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
+      } else {
+        collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+      }
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
@@ -991,16 +1077,18 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
 }
 
 // Interior tile, general addressing (periodic axes wrap, any box size).
-template <int S, int COLL, bool PER, int BS>
+template <int S, int COLL, bool PER, int BS, bool EXT>
 __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, const Item& it,
                                              const typename Store<S>::T* src,
-                                             typename Store<S>::T* dst, bool pre,
+                                             typename Store<S>::T* dst, bool pre, long long step,
                                              unsigned long long cmask, typename Store<S>::R rho0,
                                              typename Store<S>::R omega, typename Store<S>::R omb,
                                              typename Store<S>::R omg) {
   using St = Store<S>;
   using R = typename St::R;
   const int plane = it.ex * it.ey;
+  Ext<R> ext{};
+  if constexpr (EXT) ext = make_ext<R>(A, b, step);
 #pragma unroll 1
   for (int p = threadIdx.x; p < plane; p += BS) {
     const int x = it.x0 + p % it.ex;
@@ -1011,7 +1099,12 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
       load_pre<S, PER>(src, b, x, y, z, pre, d);
       R gx = 0, gy = 0, gz = 0;
       if (cmask) gather_force<R, PER, 1>(A, b, cmask, x, y, z, gx, gy, gz);
-      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+      if constexpr (EXT) {
+        ext.node = (unsigned)(((int64_t)z * b.ny + y) * b.nx + x);
+        collide_ext<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
+      } else {
+        collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+      }
 #pragma unroll
       for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
     }
@@ -1034,8 +1127,12 @@ constexpr int lb_min_waves(int S, int COLL) {
 #endif
 }
 
-template <int S, int COLL, bool PER, int BS = WG>
-__global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
+// The extended collision (body force, thermal noise) holds more registers:
+// its instantiations ask for two resident waves per SIMD.
+constexpr int lb_min_waves_ext(int S, int COLL, bool EXT) { return EXT ? 2 : lb_min_waves(S, COLL); }
+
+template <int S, int COLL, bool PER, int BS = WG, bool EXT = false>
+__global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArgs A) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -1067,9 +1164,9 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
 #define LB_ROWS(PR)                                                                    \
   do {                                                                                 \
     if (b.vw == 3)                                                                     \
-      tile_rows<S, 3, COLL, PR, BS>(A, b, it, src, dst, step, rho0, omega, omb, omg);  \
+      tile_rows<S, 3, COLL, PR, BS, EXT>(A, b, it, src, dst, step, rho0, omega, omb, omg); \
     else                                                                               \
-      tile_rows<S, 2, COLL, PR, BS>(A, b, it, src, dst, step, rho0, omega, omb, omg);  \
+      tile_rows<S, 2, COLL, PR, BS, EXT>(A, b, it, src, dst, step, rho0, omega, omb, omg); \
   } while (0)
         if (pre) LB_ROWS(true);
         else LB_ROWS(false);
@@ -1091,9 +1188,10 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
         if (ov) cmask |= 1ull << c;
       }
       if (!PER && b.fast) {
-        tile_fast<S, COLL, BS>(A, b, it, src, dst, pre, rho0, omega, omb, omg);
+        tile_fast<S, COLL, BS, EXT>(A, b, it, src, dst, pre, step, rho0, omega, omb, omg);
       } else {
-        tile_generic<S, COLL, PER, BS>(A, b, it, src, dst, pre, cmask, rho0, omega, omb, omg);
+        tile_generic<S, COLL, PER, BS, EXT>(A, b, it, src, dst, pre, step, cmask, rho0, omega, omb,
+                                            omg);
       }
     } else {
       // boundary chunk: equilibrium at rho0 and u_b(t_n) for the populations
@@ -1149,7 +1247,7 @@ __global__ __launch_bounds__(BS, lb_min_waves(S, COLL)) void k_lb(LbArgs A) {
 // node and store the same values.  One workgroup per chain.  On steps that
 // have no check pass it also ends the step (step index advance), which then
 // needs no launch of its own.
-template <int S, int COLL, bool PER>
+template <int S, int COLL, bool PER, bool EXT = false>
 __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
   using St = Store<S>;
   using T = typename St::T;
@@ -1183,7 +1281,14 @@ __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
       load_pre<S, PER>(src, b, x, y, z, A.pre != 0, d);
       R gx = 0, gy = 0, gz = 0;
       gather_force<R, PER, 4>(A, b, all, x, y, z, gx, gy, gz);
-      collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+      if constexpr (EXT) {
+        // the same body force and noise k_lb gave the node (same counter)
+        Ext<R> ext = make_ext<R>(A, b, step);
+        ext.node = (unsigned)(((int64_t)z * b.ny + y) * b.nx + x);
+        collide_ext<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
+      } else {
+        collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+      }
 #pragma unroll
       for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
     }

@@ -57,6 +57,10 @@ struct BoxHost {
   int ylog = 0;      // log2 of the y lines interleaved per population row
   int xf_off = -1;   // row boxes: first float of the x-face velocities
   int vw = 0;        // row boxes: 32-bit words per lane vector
+  // accelerated-frame body force: tracer acceleration samples on the device
+  double* d_body = nullptr;
+  int body_dt = 1, body_ns = 0;
+  int64_t body_t0 = 0;
 };
 
 struct ChainHost {
@@ -103,17 +107,17 @@ CheckLaunch pick_check(bool per) {
 
 // coll: 0 BGK, 1 MRT, 2 MRT with ghost relaxation rate 1 (ghost moments not formed)
 template <int S>
-LbLaunch pick_lb(int coll, bool per) {
-  if (coll == 0) return lbhost::pick_lb<S, 0>(per);
-  if (coll == 1) return lbhost::pick_lb<S, 1>(per);
-  return lbhost::pick_lb<S, 2>(per);
+LbLaunch pick_lb(int coll, bool per, bool ext) {
+  if (coll == 0) return lbhost::pick_lb<S, 0>(per, ext);
+  if (coll == 1) return lbhost::pick_lb<S, 1>(per, ext);
+  return lbhost::pick_lb<S, 2>(per, ext);
 }
 
 template <int S>
-LbLaunch pick_force(int coll, bool per) {
-  if (coll == 0) return lbhost::pick_force<S, 0>(per);
-  if (coll == 1) return lbhost::pick_force<S, 1>(per);
-  return lbhost::pick_force<S, 2>(per);
+LbLaunch pick_force(int coll, bool per, bool ext) {
+  if (coll == 0) return lbhost::pick_force<S, 0>(per, ext);
+  if (coll == 1) return lbhost::pick_force<S, 1>(per, ext);
+  return lbhost::pick_force<S, 2>(per, ext);
 }
 
 size_t store_bytes(int s) { return s == LB_STORE_F64 ? 8 : (s == LB_STORE_F32 ? 4 : 2); }
@@ -182,6 +186,8 @@ struct lb_ctx {
   int fp16_exp = 14;
   int dev = 0;                    // device current at lb_init
   void* noalloc = nullptr;        // that device's address of the static staging array
+  double kT = 0.0;                // thermal fluctuations (lb_set_thermal)
+  uint64_t seed = 0;              // their Philox key
   void* arena[2] = {nullptr, nullptr};
   int64_t arena_elems = 0;
   // device tables
@@ -597,6 +603,11 @@ lb_status upload_boxes(lb_ctx* ctx) {
     d.ylog = b.ylog;
     d.vw = b.vw;
     d.xf_off = b.xf_off;
+    d.index = (int)i;
+    d.body = b.body_ns > 0 ? b.d_body : nullptr;
+    d.body_dt = b.body_dt;
+    d.body_ns = b.body_ns;
+    d.body_t0 = b.body_t0;
     for (int c = 0; c < 3; c++) {
       d.enc[c] = (float)(s2 / WD[c]);
       d.dec[c] = (float)(WD[c] / s2);
@@ -637,11 +648,19 @@ lb_status upload_chains(lb_ctx* ctx) {
   std::vector<ChainDesc> cd;
   std::vector<double> rel, vel;
   int first = 0;
+  std::vector<int> box_beads(ctx->bx.size(), 0);
   for (int k : corder) {
     const ChainHost& c = ctx->ch[k];
     ChainDesc d{};
     d.box = c.box;
     d.first = first;
+    d.bead0 = box_beads[c.box];
+    box_beads[c.box] += c.p.n_beads;
+    {
+      const double h = 1.0 / c.p.md_substeps;
+      d.kick = ctx->kT > 0.0 ? std::sqrt(ctx->kT / c.p.mass * (1.0 - std::exp(-2.0 * c.p.zeta * h / c.p.mass)))
+                             : 0.0;
+    }
     d.nb = c.p.n_beads;
     d.substeps = c.p.md_substeps;
     d.fix_com = c.p.fix_com;
@@ -706,14 +725,28 @@ lb_status upload_chains(lb_ctx* ctx) {
   // chain kernel: one wavefront per chain when every chain fits in one
   int max_nb = 0;
   for (auto& c : ctx->ch) max_nb = std::max(max_nb, c.p.n_beads);
+  const bool th = ctx->kT > 0.0;
   if (ctx->S == 0)
-    ctx->chain_fn = lbhost::pick_chain<0>(ctx->per, max_nb);
+    ctx->chain_fn = lbhost::pick_chain<0>(ctx->per, max_nb, th);
   else if (ctx->S == 1)
-    ctx->chain_fn = lbhost::pick_chain<1>(ctx->per, max_nb);
+    ctx->chain_fn = lbhost::pick_chain<1>(ctx->per, max_nb, th);
   else
-    ctx->chain_fn = lbhost::pick_chain<2>(ctx->per, max_nb);
+    ctx->chain_fn = lbhost::pick_chain<2>(ctx->per, max_nb, th);
   ctx->chains_ready = true;
   return upload_boxes(ctx);
+}
+
+// Step and force-pass kernels: the extended collision when a box has a body
+// force or the context is thermal, the plain one otherwise.
+void select_launchers(lb_ctx* ctx) {
+  bool ext = ctx->kT > 0.0;
+  for (auto& b : ctx->bx) ext = ext || b.body_ns > 0;
+  const int kc = ctx->coll == LB_BGK ? 0 : (ctx->cfg.ghost_rate == 1.0 ? 2 : 1);
+  switch (ctx->S) {
+    case 0: ctx->lb_fn = pick_lb<0>(kc, ctx->per, ext); ctx->force_fn = pick_force<0>(kc, ctx->per, ext); break;
+    case 1: ctx->lb_fn = pick_lb<1>(kc, ctx->per, ext); ctx->force_fn = pick_force<1>(kc, ctx->per, ext); break;
+    default: ctx->lb_fn = pick_lb<2>(kc, ctx->per, ext); ctx->force_fn = pick_force<2>(kc, ctx->per, ext); break;
+  }
 }
 
 lb_status prepare(lb_ctx* ctx) {
@@ -757,6 +790,9 @@ LbArgs make_args(lb_ctx* ctx, int pre, int advance, int reduce_every) {
   a.om_ghost = ctx->cfg.ghost_rate;
   a.pre = pre;
   a.advance = advance;
+  a.kT = ctx->kT;
+  a.key0 = (unsigned)(ctx->seed & 0xffffffffu);
+  a.key1 = (unsigned)(ctx->seed >> 32);
   return a;
 }
 
@@ -794,7 +830,8 @@ void enqueue_step(lb_ctx* ctx, hipStream_t s, int pre, const hipEvent_t* ev3,
     ctx->chain_fn((int)ctx->ch.size(), s, ctx->d_boxes, ctx->d_chains, ctx->arena[0], ctx->arena[1],
                   ctx->d_pos, ctx->d_vel, ctx->total_beads, ctx->d_rec_base, ctx->d_rec_d,
                   ctx->d_rec_dp, ctx->d_bbox, ctx->d_st, ctx->cfg.rho0, pre, st3,
-                  ctx->d_xf_items, ctx->n_xf_items, ctx->d_xface);
+                  ctx->d_xf_items, ctx->n_xf_items, ctx->d_xface,
+                  (unsigned)(ctx->seed & 0xffffffffu), (unsigned)(ctx->seed >> 32));
   } else if (xf) {
     LbArgs xa = make_args(ctx, pre, 0, 0);
     if (st3) xa.stamp_first = st3;
@@ -1108,14 +1145,7 @@ lb_status lb_init(const lb_config* cfg, lb_ctx** out) {
     lb_free(ctx);
     return LB_ERR_HIP;
   }
-  {
-    const int kc = ctx->coll == LB_BGK ? 0 : (ctx->cfg.ghost_rate == 1.0 ? 2 : 1);
-    switch (ctx->S) {
-      case 0: ctx->lb_fn = pick_lb<0>(kc, ctx->per); ctx->force_fn = pick_force<0>(kc, ctx->per); break;
-      case 1: ctx->lb_fn = pick_lb<1>(kc, ctx->per); ctx->force_fn = pick_force<1>(kc, ctx->per); break;
-      default: ctx->lb_fn = pick_lb<2>(kc, ctx->per); ctx->force_fn = pick_force<2>(kc, ctx->per); break;
-    }
-  }
+  select_launchers(ctx);
   ctx->check_fn = ctx->S == 0 ? pick_check<0>(ctx->per)
                               : (ctx->S == 1 ? pick_check<1>(ctx->per) : pick_check<2>(ctx->per));
   load_tune_cache(ctx);
@@ -1251,6 +1281,181 @@ lb_status lb_couple_chain(lb_ctx* ctx, int32_t box, const lb_chain* chain, const
   return LB_OK;
 }
 
+lb_status lb_set_body_force(lb_ctx* ctx, int32_t box, int64_t t0, int32_t dt, int32_t n_samples,
+                            const double* accel) {
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  BoxHost& b = ctx->bx[box];
+  if (n_samples < 0 || (n_samples > 0 && (!accel || dt < 1)))
+    return fail(ctx, LB_ERR_ARG, "invalid body-force samples");
+  for (int64_t k = 0; k < 3 * (int64_t)n_samples; k++)
+    if (!std::isfinite(accel[k])) return fail(ctx, LB_ERR_ARG, "non-finite body-force sample");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double* d = nullptr;
+  if (n_samples > 0) {
+    d = (double*)dalloc(ctx, (size_t)3 * n_samples * sizeof(double));
+    if (!d) return fail(ctx, LB_ERR_OOM, "body-force allocation failed");
+    if (h2d(ctx, d, accel, (size_t)3 * n_samples * sizeof(double)) != hipSuccess) {
+      dfree(ctx, d);
+      return fail(ctx, LB_ERR_HIP, "body-force upload failed");
+    }
+  }
+  dfree(ctx, b.d_body);
+  b.d_body = d;
+  b.body_ns = n_samples;
+  b.body_dt = n_samples > 0 ? dt : 1;
+  b.body_t0 = t0;
+  select_launchers(ctx);
+  drop_graph(ctx);
+  return upload_boxes(ctx);
+}
+
+lb_status lb_set_thermal(lb_ctx* ctx, double kT, uint64_t seed) {
+  if (!ctx) return LB_ERR_ARG;
+  if (!(kT >= 0.0) || !std::isfinite(kT)) return fail(ctx, LB_ERR_ARG, "kT must be finite and >= 0");
+  if (kT > 0.0 && ctx->coll != LB_MRT)
+    return fail(ctx, LB_ERR_ARG, "thermal fluctuations need the MRT collision");
+  if (!ctx->state_pre) return fail(ctx, LB_ERR_STATE, "lb_set_thermal after the first lb_step");
+  ctx->kT = kT;
+  ctx->seed = seed;
+  select_launchers(ctx);
+  drop_graph(ctx);
+  if (ctx->chains_ready && !ctx->ch.empty()) {
+    // chains already on the device: refresh their Langevin kicks and the
+    // chain kernel variant in place (their state may have been restored)
+    std::vector<ChainDesc> cd(ctx->ch.size());
+    HIPCHK(copy_sync(ctx, cd.data(), ctx->d_chains, cd.size() * sizeof(ChainDesc),
+                     hipMemcpyDeviceToHost));
+    int max_nb = 0;
+    for (auto& d : cd) {
+      const double h = 1.0 / d.substeps;
+      d.kick = kT > 0.0 ? std::sqrt(kT / d.mass * (1.0 - std::exp(-2.0 * d.zeta * h / d.mass))) : 0.0;
+      max_nb = std::max(max_nb, d.nb);
+    }
+    HIPCHK(h2d(ctx, ctx->d_chains, cd.data(), cd.size() * sizeof(ChainDesc)));
+    const bool th = kT > 0.0;
+    if (ctx->S == 0) ctx->chain_fn = lbhost::pick_chain<0>(ctx->per, max_nb, th);
+    else if (ctx->S == 1) ctx->chain_fn = lbhost::pick_chain<1>(ctx->per, max_nb, th);
+    else ctx->chain_fn = lbhost::pick_chain<2>(ctx->per, max_nb, th);
+  }
+  return LB_OK;
+}
+
+lb_status lb_load_subvolume(lb_ctx* ctx, int32_t box, const char* path, int32_t what) {
+  lb_status s = check_box(ctx, box);
+  if (s) return s;
+  if (!path || (what & ~(LB_SUBVOL_INITIAL | LB_SUBVOL_BOUNDARY | LB_SUBVOL_BODY)))
+    return fail(ctx, LB_ERR_ARG, "invalid sub-volume load request");
+  std::ifstream in(path, std::ios::binary);
+  if (!in) return fail(ctx, LB_ERR_ARG, std::string("cannot open sub-volume file ") + path);
+  char magic[8];
+  int32_t version = 0, R = 0, ns = 0, dt = 0, flags = 0, reserved = 0;
+  int64_t t0 = 0;
+  in.read(magic, 8);
+  in.read((char*)&version, 4);
+  in.read((char*)&R, 4);
+  in.read((char*)&ns, 4);
+  in.read((char*)&dt, 4);
+  in.read((char*)&t0, 8);
+  in.read((char*)&flags, 4);
+  in.read((char*)&reserved, 4);
+  if (!in || std::memcmp(magic, "LBSUBVOL", 8) != 0 || version != 1)
+    return fail(ctx, LB_ERR_ARG, "not a version-1 sub-volume file");
+  if (R < 2 || R > 1024 || ns < 1 || dt < 1 || (flags & ~1))
+    return fail(ctx, LB_ERR_ARG, "invalid sub-volume header");
+  const size_t per = (size_t)R * R * R * 3;
+  std::vector<float> w(per * ns);
+  in.read((char*)w.data(), (std::streamsize)(w.size() * sizeof(float)));
+  std::vector<double> acc;
+  if (flags & 1) {
+    acc.resize((size_t)3 * ns);
+    in.read((char*)acc.data(), (std::streamsize)(acc.size() * sizeof(double)));
+  }
+  if (!in) return fail(ctx, LB_ERR_ARG, "sub-volume file shorter than its header says");
+  in.peek();
+  if (!in.eof()) return fail(ctx, LB_ERR_ARG, "sub-volume file longer than its header says");
+  if ((what & LB_SUBVOL_BODY) && !(flags & 1))
+    return fail(ctx, LB_ERR_ARG, "sub-volume file holds no tracer accelerations");
+  const BoxHost& b = ctx->bx[box];
+  const int n3[3] = {b.dim.nx, b.dim.ny, b.dim.nz};
+  // grid value of sample k at grid point (i, j, l) along x, y, z, component c
+  auto W = [&](int k, int i, int j, int l, int c) -> float {
+    return w[(((size_t)k * R + l) * R + j) * R * 3 + (size_t)i * 3 + c];
+  };
+  if (what & LB_SUBVOL_BOUNDARY) {
+    // the six faces of the grid, corner-aligned with the box's faces: face f
+    // lies on axis f/2 at grid index 0 or R-1, entry [v][u] with u the
+    // lower-index tangential axis (the SAMPLED layout)
+    std::vector<float> faces((size_t)ns * 6 * R * R * 3);
+    for (int k = 0; k < ns; k++)
+      for (int f = 0; f < 6; f++) {
+        const int a = f / 2, au = a == 0 ? 1 : 0, av = a == 2 ? 1 : 2;
+        for (int iv = 0; iv < R; iv++)
+          for (int iu = 0; iu < R; iu++) {
+            int g[3];
+            g[a] = (f % 2) ? R - 1 : 0;
+            g[au] = iu;
+            g[av] = iv;
+            for (int c = 0; c < 3; c++)
+              faces[((((size_t)k * 6 + f) * R + iv) * R + iu) * 3 + c] = W(k, g[0], g[1], g[2], c);
+          }
+      }
+    lb_boundary bc{};
+    bc.mode = LB_BC_SAMPLED;
+    bc.t0 = t0;
+    bc.dt = dt;
+    bc.n_samples = ns;
+    bc.res = R;
+    bc.data = faces.data();
+    bc.data_is_f64 = 0;
+    s = lb_set_boundary(ctx, box, &bc);
+    if (s) return s;
+  }
+  if (what & LB_SUBVOL_INITIAL) {
+    // Sec. 2: the sub-volume field linearly interpolated onto every site at
+    // t = 0: grid point p of an axis sits at node coordinate p (n - 1)/(R - 1)
+    if (n3[0] < 2 || n3[1] < 2 || n3[2] < 2)
+      return fail(ctx, LB_ERR_ARG, "a sub-volume initial field needs two nodes per axis");
+    std::vector<double> u((size_t)3 * b.nn);
+    std::vector<int> cell[3];
+    std::vector<double> frac[3];
+    for (int a = 0; a < 3; a++) {
+      cell[a].resize(n3[a]);
+      frac[a].resize(n3[a]);
+    }
+    for (int a = 0; a < 3; a++)
+      for (int q = 0; q < n3[a]; q++) {
+        const int64_t sq = (int64_t)q * (R - 1);
+        int p = (int)(sq / (n3[a] - 1));
+        if (p > R - 2) p = R - 2;
+        cell[a][q] = p;
+        frac[a][q] = (double)(sq - (int64_t)p * (n3[a] - 1)) / (double)(n3[a] - 1);
+      }
+    for (int z = 0; z < n3[2]; z++)
+      for (int y = 0; y < n3[1]; y++)
+        for (int x = 0; x < n3[0]; x++) {
+          const int ci = cell[0][x], cj = cell[1][y], cl = cell[2][z];
+          const double fx = frac[0][x], fy = frac[1][y], fz = frac[2][z];
+          for (int c = 0; c < 3; c++) {
+            double v = 0.0;
+            for (int o = 0; o < 8; o++) {
+              const int ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+              const double wgt = (ox ? fx : 1.0 - fx) * (oy ? fy : 1.0 - fy) * (oz ? fz : 1.0 - fz);
+              v += wgt * (double)W(0, ci + ox, cj + oy, cl + oz, c);
+            }
+            u[(((size_t)z * n3[1] + y) * n3[0] + x) * 3 + c] = v;
+          }
+        }
+    s = lb_set_initial(ctx, box, u.data());
+    if (s) return s;
+  }
+  if (what & LB_SUBVOL_BODY) {
+    s = lb_set_body_force(ctx, box, t0, dt, ns, acc.data());
+    if (s) return s;
+  }
+  return LB_OK;
+}
+
 lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
   if (!ctx || n_steps < 0) return LB_ERR_ARG;
   if (ctx->latched) return ctx->latched;
@@ -1262,6 +1467,13 @@ lb_status lb_step(lb_ctx* ctx, int32_t n_steps) {
     const int64_t end = b.bc_t0 + (int64_t)(b.bc_ns - 1) * b.bc_dt;
     if (first < b.bc_t0 || (b.bc_mode != LB_BC_LEARNED && last > end))
       return fail(ctx, LB_ERR_ARG, "steps beyond the boundary samples (no extrapolation)");
+  }
+  for (auto& b : ctx->bx) {
+    if (b.body_ns <= 0) continue;
+    const int64_t first = ctx->host_step, last = ctx->host_step + n_steps - 1;
+    const int64_t end = b.body_t0 + (int64_t)(b.body_ns - 1) * b.body_dt;
+    if (first < b.body_t0 || last > end)
+      return fail(ctx, LB_ERR_ARG, "steps beyond the body-force samples (no extrapolation)");
   }
   lb_status s = prepare(ctx);
   if (s) return s;
@@ -1945,7 +2157,10 @@ void lb_free(lb_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   drop_graph(ctx);
   free_tables(ctx);
-  for (auto& b : ctx->bx) dfree(ctx, b.d_bc);
+  for (auto& b : ctx->bx) {
+    dfree(ctx, b.d_bc);
+    dfree(ctx, b.d_body);
+  }
   dfree(ctx, ctx->arena[0]);
   dfree(ctx, ctx->arena[1]);
   dfree(ctx, ctx->d_boxes);

@@ -128,6 +128,11 @@ class KSField:
         ph = x @ self.k.T + self.omega * t
         return np.cos(ph) @ self.A + np.sin(ph) @ self.B
 
+    def time_derivative(self, x: np.ndarray, t: float) -> np.ndarray:
+        """du/dt at fixed points x[..., 3]."""
+        ph = x @ self.k.T + self.omega * t
+        return (-np.sin(ph) * self.omega) @ self.A + (np.cos(ph) * self.omega) @ self.B
+
     def gradient(self, x: np.ndarray, t: float) -> np.ndarray:
         """du_i/dx_j at points x[..., 3]: shape [..., 3 (i), 3 (j)]."""
         ph = x @ self.k.T + self.omega * t
@@ -404,3 +409,59 @@ def upsampler_samples(config_idx: int, traj_ids, n: int = 64, tau: float = 0.6, 
     return (np.asarray(co_list, dtype=np.float32), np.asarray(th_list, dtype=np.float32),
             np.asarray(tr_list, dtype=np.float32))
 
+
+
+# --------------------------------------------------------------------------
+# Sub-volume history files (the data-on-disk coupling of the two scales)
+# --------------------------------------------------------------------------
+def tracer_acceleration(ks: KSField, tracer: Tracer) -> np.ndarray:
+    """dv/dt of the tracer, the Lagrangian acceleration du/dt + (u . grad) u of
+    the field at its position: [T, 3] in Kolmogorov units."""
+    out = np.empty((len(tracer.times), 3))
+    for i, (p, t) in enumerate(zip(tracer.pos, tracer.times)):
+        g = ks.gradient(p, float(t))
+        out[i] = ks.time_derivative(p, float(t)) + g @ ks.velocity(p, float(t))
+    return out
+
+
+def ks_subvolume_history(config_idx: int, box_idx: int, n: int, tau: float, n_steps: int,
+                         dt: int, grid: int, width_eta: float = 2.0, n_modes: int = 200):
+    """A sub-volume history of a KS tracer box: the tracer-frame velocity on a
+    corner-aligned grid of ``grid`` points per edge at steps 0, dt, ... covering
+    n_steps, [S][grid][grid][grid][3] as [z][y][x][c] in lattice units, and the
+    tracer accelerations [S][3] in lattice units per step."""
+    ks, x0 = ks_tracer(config_idx, box_idx, n_modes)
+    units = UnitMap(n, tau, width_eta)
+    n_samples = -(-n_steps // dt) + 1
+    steps = np.arange(n_samples) * dt
+    tr = tracer_path(ks, x0, steps / units.tau_eta)
+    offs = _sample_offsets(n, grid, (n - 1) / 2.0) / units.eta
+    w = np.empty((n_samples, grid, grid, grid, 3))
+    for k in range(n_samples):
+        g = ks.grid_velocity(tr.pos[k], float(tr.times[k]), [offs, offs, offs])
+        w[k] = (g - tr.vel[k]) * units.u_scale
+    acc = tracer_acceleration(ks, tr) * units.u_scale / units.tau_eta
+    return w, acc
+
+
+def write_subvolume(path: str, w: np.ndarray, dt: int, t0: int = 0, accel=None) -> None:
+    """Writes a sub-volume history file (format version 1, little endian):
+    magic "LBSUBVOL", int32 version, grid R, n_samples, dt, int64 t0, int32
+    flags (bit 0: accelerations follow), int32 0, float32 w[S][R][R][R][3],
+    then float64 accel[S][3] if given."""
+    w = np.ascontiguousarray(w, dtype="<f4")
+    S, R = w.shape[0], w.shape[1]
+    if w.shape != (S, R, R, R, 3):
+        raise ValueError("w must be [samples][R][R][R][3]")
+    flags = 1 if accel is not None else 0
+    with open(path, "wb") as fh:
+        fh.write(b"LBSUBVOL")
+        fh.write(np.array([1, R, S, dt], dtype="<i4").tobytes())
+        fh.write(np.array([t0], dtype="<i8").tobytes())
+        fh.write(np.array([flags, 0], dtype="<i4").tobytes())
+        fh.write(w.tobytes())
+        if accel is not None:
+            a = np.ascontiguousarray(accel, dtype="<f8")
+            if a.shape != (S, 3):
+                raise ValueError("accel must be [samples][3]")
+            fh.write(a.tobytes())

@@ -61,7 +61,9 @@ class LbChain(ct.Structure):
 EXPORTS = ["lb_init", "lb_set_initial", "lb_set_boundary", "lb_couple_chain", "lb_step",
            "lb_read_fields", "lb_read_sites", "lb_write_state", "lb_sync", "lb_autotune",
            "lb_set_timing", "lb_get_timing", "lb_describe", "lb_last_error", "lb_free",
-           "lb_copy_probe", "lb_memcpy_probe", "lb_read_sites_noalloc", "lb_vorticity"]
+           "lb_copy_probe", "lb_memcpy_probe", "lb_read_sites_noalloc", "lb_vorticity",
+           "lb_set_body_force", "lb_set_thermal", "lb_load_subvolume"]
+SUBVOL_INITIAL, SUBVOL_BOUNDARY, SUBVOL_BODY = 1, 2, 4
 
 _lib = None
 
@@ -85,6 +87,9 @@ def load(path: str = LIB):
     lib.lb_read_sites.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
     lib.lb_read_sites_noalloc.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
     lib.lb_vorticity.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp]
+    lib.lb_set_body_force.argtypes = [vp, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32, vp]
+    lib.lb_set_thermal.argtypes = [vp, ct.c_double, ct.c_uint64]
+    lib.lb_load_subvolume.argtypes = [vp, ct.c_int32, ct.c_char_p, ct.c_int32]
     lib.lb_write_state.argtypes = [vp, ct.c_int32, ct.c_int, vp, ct.c_size_t]
     lib.lb_sync.argtypes = [vp]
     lib.lb_autotune.argtypes = [vp, ct.c_int32]
@@ -247,6 +252,21 @@ class Context:
             vel = np.ascontiguousarray(vel, dtype=np.float64)
             v = _p(vel)
         return self._check(self._lib.lb_couple_chain(self._h, box, ct.byref(ch), _p(pos), v))
+
+    def set_body_force(self, box, accel, t0=0, dt=1):
+        """Tracer acceleration samples [n][3] (lattice units); None removes it."""
+        if accel is None:
+            return self._check(self._lib.lb_set_body_force(self._h, box, 0, 1, 0, None))
+        a = np.ascontiguousarray(accel, dtype=np.float64).reshape(-1, 3)
+        return self._check(self._lib.lb_set_body_force(self._h, box, int(t0), int(dt), a.shape[0],
+                                                       _p(a)))
+
+    def load_subvolume(self, box, path, what=SUBVOL_INITIAL | SUBVOL_BOUNDARY):
+        """Apply a sub-volume history file (format in include/lbm.h) to a box."""
+        return self._check(self._lib.lb_load_subvolume(self._h, box, str(path).encode(), int(what)))
+
+    def set_thermal(self, kT, seed=0):
+        return self._check(self._lib.lb_set_thermal(self._h, float(kT), int(seed)))
 
     # -- stepping -----------------------------------------------------------
     def step(self, n=1):

@@ -82,7 +82,8 @@ class Case:
     """Inputs of one box: dims, collision, boundary, chains, initial field."""
 
     def __init__(self, dims, collision=oracle.BGK, tau=0.8, tau_bulk=None, ghost_rate=1.0,
-                 periodic_mask=0, bc=None, u0=None, chains=(), reduce_every=0):
+                 periodic_mask=0, bc=None, u0=None, chains=(), reduce_every=0, body=None,
+                 kT=0.0, seed=0, box_index=0):
         self.dims = tuple(dims)
         self.collision = collision
         self.tau = tau
@@ -93,6 +94,9 @@ class Case:
         self.u0 = u0
         self.chains = list(chains)  # dicts: pos, vel, substeps, fix_com, zeta, fene_k, fene_r0, anchor
         self.reduce_every = reduce_every
+        self.body = body            # (accel [n][3], t0, dt) or None
+        self.kT, self.seed = kT, seed
+        self.box_index = box_index  # the box's index in the GPU context (random counters)
 
     def oracle_box(self):
         ob = oracle.OracleBox(self.dims, collision=self.collision, tau=self.tau,
@@ -108,6 +112,11 @@ class Case:
                          mass=c.get("mass", bead_mass(len(c["pos"]))),
                          fene_k=c.get("fene_k", 1.0), fene_r0=c.get("fene_r0", 2.0),
                          anchor=c.get("anchor"))
+        if self.body is not None:
+            accel, t0, dt = self.body
+            ob.set_body_force(accel, t0=t0, dt=dt)
+        if self.kT:
+            assert ob.set_thermal(self.kT, self.seed, self.box_index) == 0
         return ob
 
     def add_to(self, ctx, box=0):
@@ -121,6 +130,9 @@ class Case:
                              mass=c.get("mass", bead_mass(len(c["pos"]))),
                              fene_k=c.get("fene_k", 1.0), fene_r0=c.get("fene_r0", 2.0),
                              anchor=c.get("anchor"))
+        if self.body is not None:
+            accel, t0, dt = self.body
+            ctx.set_body_force(box, accel, t0=t0, dt=dt)
 
     @property
     def n_beads(self):
