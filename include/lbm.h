@@ -73,6 +73,18 @@ typedef enum { LB_BGK = 0, LB_MRT = 1 } lb_collision;
  * nearest even), s = lb_config.fp16_exp. */
 typedef enum { LB_STORE_F64 = 0, LB_STORE_F32 = 1, LB_STORE_F16DEV = 2 } lb_storage;
 
+/* Streaming.  LB_STREAM_AB: two population buffers, each step pulls from one
+ * and writes the other.  LB_STREAM_AA: one buffer updated in place (half the
+ * memory): an even step reads every node's populations in place and writes
+ * its post-collision f*_i into the node's own slot of the opposite direction;
+ * an odd step reads those from the neighbours and writes f*_i into slot i of
+ * node x + c_i, where the next even step finds the next pre-collision state
+ * in place.  Every slot is read and written by one node only, so no step needs
+ * a second buffer.  The same arithmetic as LB_STREAM_AB, bit for bit on tile
+ * boxes; in-place contexts run every box as tile items (no row items), gather
+ * the chains' spread force inside the fused step, and have no autotuner. */
+typedef enum { LB_STREAM_AB = 0, LB_STREAM_AA = 1 } lb_streaming;
+
 typedef struct {
   int32_t nx, ny, nz;      /* nodes per axis, boundary layer included (>= 3 on non-periodic axes) */
   uint32_t periodic_mask;  /* bit a set: axis a (x=0, y=1, z=2) is periodic and has no boundary layer */
@@ -99,6 +111,7 @@ typedef struct {
   int32_t graph_steps;     /* > 0: lb_step replays a HIP graph of this many steps; 0 = eager launches.
                               A multiple of reduce_every lets the graphs leave the check pass out of
                               the steps that are not check steps (captured once per check phase). */
+  int32_t streaming;       /* lb_streaming: LB_STREAM_AB (0) or LB_STREAM_AA (1) */
 } lb_config;
 
 /* Creates a context: validates the configuration, allocates two population

@@ -15,6 +15,8 @@ constexpr int Q = 19;
 constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+// opposite direction: c_OPP[i] = -c_i
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 // weight class: 0 rest (1/3), 1 axis (1/18), 2 diagonal (1/36)
 constexpr int WCLS[Q] = {0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
 constexpr double WD[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
@@ -169,6 +171,25 @@ template <> struct Store<2> {
 template <typename R>
 __device__ __forceinline__ R wgt(int i) { return (R)WD[WCLS[i]]; }
 
+// w_c x without the bias of a rounded weight.  In FP32 the weights 1/3, 1/18
+// and 1/36 round up by 3.0e-8, 7.5e-9 and 7.5e-9 of themselves: multiplied
+// into every post-collision population, that same-signed factor would scale
+// the conserved mass and momentum on every step and build up over the flow's
+// relaxation time (1e-5 of the velocity over 10^4 steps of a 128^3 box).  The
+// residual w_c - (float)w_c, added by a fused multiply-add, cancels it; in
+// FP64 the weights' rounding (1e-17) is left alone.
+constexpr float WF[3] = {(float)WD[0], (float)WD[1], (float)WD[2]};
+constexpr float WLO[3] = {(float)(WD[0] - (double)WF[0]), (float)(WD[1] - (double)WF[1]),
+                          (float)(WD[2] - (double)WF[2])};
+template <typename R>
+__host__ __device__ __forceinline__ constexpr R wmul(int c, R x) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_fmaf(x, WF[c], x * WLO[c]);
+  } else {
+    return (R)WD[c] * x;
+  }
+}
+
 // 1/rho: exact division in FP64, the hardware reciprocal (1 ulp) in FP32
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -181,7 +202,7 @@ __device__ __forceinline__ void eq_dev(R drho, R rho, R ux, R uy, R uz, R out[Q]
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const R cu = (R)CX[i] * ux + (R)CY[i] * uy + (R)CZ[i] * uz;
-    out[i] = wgt<R>(i) * (base + rho * cu * ((R)3.0 + (R)4.5 * cu));
+    out[i] = wmul<R>(WCLS[i], base + rho * cu * ((R)3.0 + (R)4.5 * cu));
   }
 }
 
@@ -213,7 +234,7 @@ __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omeg
     for (int i = 0; i < Q; i++) {
       const R cu = (R)CX[i] * ux + (R)CY[i] * uy + (R)CZ[i] * uz;
       const R cg = (R)CX[i] * gx + (R)CY[i] * gy + (R)CZ[i] * gz;
-      const R F = wgt<R>(i) * ((R)3 * (cg - ug) + (R)9 * cu * cg);
+      const R F = wmul<R>(WCLS[i], (R)3 * (cg - ug) + (R)9 * cu * cg);
       d[i] = d[i] - omega * (d[i] - eq[i]) + fpre * F;
     }
   } else {
@@ -276,7 +297,7 @@ __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omeg
         else if (e == -1) s -= ms[k];
         else if (e != 0) s += (R)e * ms[k];
       }
-      d[i] = wgt<R>(i) * s;
+      d[i] = wmul<R>(WCLS[i], s);
     }
   }
 }
@@ -380,8 +401,7 @@ __host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q]) {
   const R g10 = GZ ? R(0) : M[10], g11 = GZ ? R(0) : M[11], g12 = GZ ? R(0) : M[12];
   const R g13 = GZ ? R(0) : M[13], g14 = GZ ? R(0) : M[14], g15 = GZ ? R(0) : M[15];
   const R g16 = GZ ? R(0) : M[16], g17 = GZ ? R(0) : M[17], g18 = GZ ? R(0) : M[18];
-  const R w0 = R(WD[0]), w1 = R(WD[1]), w2 = R(WD[2]);
-  d[0] = w0 * (M[0] - M[4] + g16);
+  d[0] = wmul<R>(0, M[0] - M[4] + g16);
   const R E1 = M[0] + (M[5] + M[5]) - (g16 + g16) - (g17 + g17);
   const R O1 = M[1] - (g10 + g10);
   const R E2 = M[0] - M[5] + M[6] - (g16 + g16) + g17 - g18;
@@ -402,24 +422,24 @@ __host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q]) {
   const R O7 = x10 - z12 - g13 - g15;
   const R O8 = y11 + z12 + g14 - g15;
   const R O9 = y11 - z12 + g14 + g15;
-  d[1] = w1 * (E1 + O1);
-  d[2] = w1 * (E1 - O1);
-  d[3] = w1 * (E2 + O2);
-  d[4] = w1 * (E2 - O2);
-  d[5] = w1 * (E3 + O3);
-  d[6] = w1 * (E3 - O3);
-  d[7] = w2 * (E4 + O4);
-  d[8] = w2 * (E4 - O4);
-  d[9] = w2 * (E5 + O5);
-  d[10] = w2 * (E5 - O5);
-  d[11] = w2 * (E6 + O6);
-  d[12] = w2 * (E6 - O6);
-  d[13] = w2 * (E7 + O7);
-  d[14] = w2 * (E7 - O7);
-  d[15] = w2 * (E8 + O8);
-  d[16] = w2 * (E8 - O8);
-  d[17] = w2 * (E9 + O9);
-  d[18] = w2 * (E9 - O9);
+  d[1] = wmul<R>(1, E1 + O1);
+  d[2] = wmul<R>(1, E1 - O1);
+  d[3] = wmul<R>(1, E2 + O2);
+  d[4] = wmul<R>(1, E2 - O2);
+  d[5] = wmul<R>(1, E3 + O3);
+  d[6] = wmul<R>(1, E3 - O3);
+  d[7] = wmul<R>(2, E4 + O4);
+  d[8] = wmul<R>(2, E4 - O4);
+  d[9] = wmul<R>(2, E5 + O5);
+  d[10] = wmul<R>(2, E5 - O5);
+  d[11] = wmul<R>(2, E6 + O6);
+  d[12] = wmul<R>(2, E6 - O6);
+  d[13] = wmul<R>(2, E7 + O7);
+  d[14] = wmul<R>(2, E7 - O7);
+  d[15] = wmul<R>(2, E8 + O8);
+  d[16] = wmul<R>(2, E8 - O8);
+  d[17] = wmul<R>(2, E9 + O9);
+  d[18] = wmul<R>(2, E9 - O9);
 }
 
 __host__ __device__ constexpr bool pair_forward_matches_basis() {
@@ -540,19 +560,37 @@ __host__ __device__ __forceinline__ int64_t aidx(const BoxDesc& b, int i, int x,
 // Neighbour coordinate with wrap on periodic axes.
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Pre-collision deviations of node (x, y, z) at t_n: pulled from the
-// post-collision buffer of t_{n-1} (boundary slots hold the boundary
-// equilibrium), or read in place when the buffer holds a pre-collision state.
+// How a buffer holds the pre-collision state of t_n:
+//   LAYOUT_PULL   post-collision populations of t_{n-1} at their source node:
+//                 f_i(x) = A[x - c_i][i] (two buffers; boundary slots hold the
+//                 boundary equilibrium)
+//   LAYOUT_PLACE  in place: f_i(x) = A[x][i] (a state just uploaded, or the
+//                 single buffer of in-place streaming after an odd step)
+//   LAYOUT_SWAP   post-collision populations of t_{n-1} in the opposite slot
+//                 of their source node: f_i(x) = A[x - c_i][OPP[i]] (in-place
+//                 streaming after an even step)
+enum : int { LAYOUT_PULL = 0, LAYOUT_PLACE = 1, LAYOUT_SWAP = 2 };
+
+// Layout of the single buffer of in-place streaming at time index n: even
+// steps read in place and write each node's results into its opposite slots,
+// odd steps read those and write the next in-place state.
+__host__ __device__ __forceinline__ int aa_layout(long long n) {
+  return (n & 1) ? LAYOUT_SWAP : LAYOUT_PLACE;
+}
+
+// Pre-collision deviations of node (x, y, z) at t_n from a buffer of the given
+// layout (PER: periodic axes wrap).
 template <int S, bool PER>
 __device__ __forceinline__ void load_pre(const typename Store<S>::T* __restrict__ src,
-                                         const BoxDesc& b, int x, int y, int z, bool pre,
+                                         const BoxDesc& b, int x, int y, int z, int layout,
                                          typename Store<S>::R d[Q]) {
   using St = Store<S>;
-  if (pre) {
+  if (layout == LAYOUT_PLACE) {
 #pragma unroll
     for (int i = 0; i < Q; i++) d[i] = St::dec(src[aidx(b, i, x, y, z)], b.dec[WCLS[i]]);
     return;
   }
+  const bool swap = layout == LAYOUT_SWAP;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     int sx = x - CX[i], sy = y - CY[i], sz = z - CZ[i];
@@ -561,7 +599,7 @@ __device__ __forceinline__ void load_pre(const typename Store<S>::T* __restrict_
       if (b.pmask & 2) sy = wrapc(sy, b.ny);
       if (b.pmask & 4) sz = wrapc(sz, b.nz);
     }
-    d[i] = St::dec(src[aidx(b, i, sx, sy, sz)], b.dec[WCLS[i]]);
+    d[i] = St::dec(src[aidx(b, swap ? OPP[i] : i, sx, sy, sz)], b.dec[WCLS[i]]);
   }
 }
 

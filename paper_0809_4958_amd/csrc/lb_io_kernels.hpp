@@ -55,9 +55,13 @@ __global__ __launch_bounds__(WG) void k_finalize(LbArgs A) {
 // pre-collision state of one box from FP64 populations [19][nn] (mode 0), from
 // the equilibrium of a velocity field u[nn][3] (mode 1), rest (mode 2), or FP64
 // deviations f_i - w_i rho0 [19][nn] (mode 3)
+// swap: write the LAYOUT_SWAP image of that state (in-place streaming at an
+// odd time index): f_i(x) of every interior node x into slot OPP[i] of node
+// x - c_i (each slot has one writer); other slots are left as they are.
 template <int S>
 __global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T* __restrict__ dst,
-                                                const double* __restrict__ in, int mode, double rho0) {
+                                                const double* __restrict__ in, int mode, double rho0,
+                                                int swap) {
   using St = Store<S>;
   using R = typename St::R;
   const int64_t nn = b.nn;
@@ -84,13 +88,26 @@ __global__ __launch_bounds__(WG) void k_set_pre(BoxDesc b, typename Store<S>::T*
 #pragma unroll
       for (int i = 0; i < Q; i++) d[i] = (R)eq[i];
     }
+    if (swap) {
+      if (!is_interior(b, x, y, z)) continue;
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        int sx = x - CX[i], sy = y - CY[i], sz = z - CZ[i];
+        if (b.pmask & 1) sx = wrapc(sx, b.nx);
+        if (b.pmask & 2) sy = wrapc(sy, b.ny);
+        if (b.pmask & 4) sz = wrapc(sz, b.nz);
+        dst[aidx(b, OPP[i], sx, sy, sz)] = St::enc(d[i], b.enc[WCLS[i]]);
+      }
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
   }
 }
 
 // ------------------------------------------------------------ readout
-// what: 0 populations [19][nn], 1 rho [nn], 2 u [nn][3], 3 deviations [19][nn]
+// what: 0 populations [19][nn], 1 rho [nn], 2 u [nn][3], 3 deviations [19][nn];
+// pre: the layout of the buffer (LAYOUT_PULL, LAYOUT_PLACE or LAYOUT_SWAP)
 template <int S, bool PER>
 __global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>::T* __restrict__ src,
                                              double* __restrict__ out, int what, int pre, double rho0) {
@@ -104,7 +121,7 @@ __global__ __launch_bounds__(WG) void k_read(BoxDesc b, const typename Store<S>:
     double f[Q];
     if (is_interior(b, x, y, z)) {
       R d[Q];
-      load_pre<S, PER>(src, b, x, y, z, pre != 0, d);
+      load_pre<S, PER>(src, b, x, y, z, pre, d);
 #pragma unroll
       for (int i = 0; i < Q; i++) f[i] = WD[WCLS[i]] * rho0 + (double)d[i];
       if (what == 0) {
@@ -155,7 +172,7 @@ __global__ __launch_bounds__(WG) void k_read_sites(BoxDesc b, const typename Sto
   const int k = blockIdx.x * WG + threadIdx.x;
   if (k >= n) return;
   R d[Q];
-  load_pre<S, PER>(src, b, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2], pre != 0, d);
+  load_pre<S, PER>(src, b, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2], pre, d);
 #pragma unroll
   for (int i = 0; i < Q; i++) out[Q * k + i] = WD[WCLS[i]] * rho0 + (double)d[i];
 }

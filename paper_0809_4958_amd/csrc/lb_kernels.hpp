@@ -222,7 +222,7 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
       const R w = (o0 ? dl[0] : (R)1 - dl[0]) * (o1 ? dl[1] : (R)1 - dl[1]) *
                   (o2 ? dl[2] : (R)1 - dl[2]);
       R d[Q];
-      load_pre<S, PER>(src, b, qx, qy, qz, pre != 0, d);
+      load_pre<S, PER>(src, b, qx, qy, qz, pre == 2 ? aa_layout(step) : pre, d);
       R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
       for (int i = 0; i < Q; i++) {
@@ -567,6 +567,7 @@ struct LbArgs {
   int advance;
   double kT;               // thermal fluctuations (fluctuating MRT) when > 0
   unsigned key0, key1;     // Philox key of the context's random numbers
+  int aa;                  // in-place streaming on one buffer (a0 == a1): tile items only
 };
 
 // Collision dispatcher: 0 BGK, 1 MRT, 2 MRT with ghost rate 1.
@@ -1077,10 +1078,14 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
 }
 
 // Interior tile, general addressing (periodic axes wrap, any box size).
+// In-place streaming (A.aa): an even step reads each node in place and
+// writes f*_i into its own slot OPP[i]; an odd step reads those (LAYOUT_SWAP)
+// and writes f*_i into slot i of node x + c_i, where the next even step reads
+// it in place.  Each slot is read and written by one node only.
 template <int S, int COLL, bool PER, int BS, bool EXT>
 __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, const Item& it,
                                              const typename Store<S>::T* src,
-                                             typename Store<S>::T* dst, bool pre, long long step,
+                                             typename Store<S>::T* dst, int layout, long long step,
                                              unsigned long long cmask, typename Store<S>::R rho0,
                                              typename Store<S>::R omega, typename Store<S>::R omb,
                                              typename Store<S>::R omg) {
@@ -1096,7 +1101,7 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
 #pragma unroll 1
     for (int z = it.z0; z < it.z0 + it.ez; z++) {
       R d[Q];
-      load_pre<S, PER>(src, b, x, y, z, pre, d);
+      load_pre<S, PER>(src, b, x, y, z, layout, d);
       R gx = 0, gy = 0, gz = 0;
       if (cmask) gather_force<R, PER, 1>(A, b, cmask, x, y, z, gx, gy, gz);
       if constexpr (EXT) {
@@ -1105,8 +1110,24 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
       } else {
         collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
       }
+      if (A.aa && !(step & 1)) {
 #pragma unroll
-      for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+        for (int i = 0; i < Q; i++) dst[aidx(b, OPP[i], x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+      } else if (A.aa) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+          if (PER) {
+            if (b.pmask & 1) tx = wrapc(tx, b.nx);
+            if (b.pmask & 2) ty = wrapc(ty, b.ny);
+            if (b.pmask & 4) tz = wrapc(tz, b.nz);
+          }
+          dst[aidx(b, i, tx, ty, tz)] = St::enc(d[i], b.enc[WCLS[i]]);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+      }
     }
   }
 }
@@ -1181,7 +1202,8 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
       // chains whose stencil box overlaps this tile, periodic boxes only (the
       // chains of the other boxes couple in k_force)
       unsigned long long cmask = 0;
-      for (int c = 0; PER && b.pmask && c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
+      const bool gather = (PER && b.pmask) || A.aa;
+      for (int c = 0; gather && c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
         const int* bb = A.bbox + 6 * (b.chain_first + c);
         const bool ov = bb[0] <= it.x0 + it.ex - 1 && bb[3] >= it.x0 && bb[1] <= it.y0 + it.ey - 1 &&
                         bb[4] >= it.y0 && bb[2] <= it.z0 + it.ez - 1 && bb[5] >= it.z0;
@@ -1190,8 +1212,9 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
       if (!PER && b.fast) {
         tile_fast<S, COLL, BS, EXT>(A, b, it, src, dst, pre, step, rho0, omega, omb, omg);
       } else {
-        tile_generic<S, COLL, PER, BS, EXT>(A, b, it, src, dst, pre, step, cmask, rho0, omega, omb,
-                                            omg);
+        const int layout = A.aa ? aa_layout(step) : (pre ? LAYOUT_PLACE : LAYOUT_PULL);
+        tile_generic<S, COLL, PER, BS, EXT>(A, b, it, src, dst, layout, step, cmask, rho0, omega,
+                                            omb, omg);
       }
     } else {
       // boundary chunk: equilibrium at rho0 and u_b(t_n) for the populations
@@ -1222,7 +1245,14 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
             if (b.pmask & 4) tz = wrapc(tz, b.nz);
           }
           if (!is_interior(b, tx, ty, tz)) continue;
-          dst[aidx(b, i, q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
+          // in-place streaming: an even step leaves the population in the
+          // node's opposite slot, an odd step in slot i of the target node
+          if (A.aa && !(step & 1))
+            dst[aidx(b, OPP[i], q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
+          else if (A.aa)
+            dst[aidx(b, i, tx, ty, tz)] = St::enc(eq[i], b.enc[WCLS[i]]);
+          else
+            dst[aidx(b, i, q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
         }
       }
     }
@@ -1382,7 +1412,7 @@ __global__ __launch_bounds__(WG) void k_check(LbArgs A) {
   const int par = (int)(step & 1);
   const T* __restrict__ arena = (const T*)(par ? A.a0 : A.a1) + b.off;  // written by this step
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (!PER && b.nx % 8 == 0) {
+  if (!A.aa && !PER && b.nx % 8 == 0) {
     // chunks of 8 consecutive nodes of a row, every population read as
     // 16-byte vectors (rows start 16-byte aligned: box offsets are multiples
     // of 128 elements and 8 nodes span 16 bytes or a multiple of it).  The
@@ -1433,9 +1463,14 @@ __global__ __launch_bounds__(WG) void k_check(LbArgs A) {
       T raw[Q];
 #pragma unroll
       for (int i = 0; i < Q; i++) raw[i] = arena[aidx(b, i, x, y, z)];
+      // where slot i of this node streams to, and along which direction:
+      // two buffers and an in-place even step (slot OPP[i] holds f*_OPP[i],
+      // moving along -c_i) move it on, an in-place odd step left it in place
+      const int mv = A.aa ? ((step & 1) ? 0 : -1) : 1;
+      const int dir = A.aa && !(step & 1) ? -1 : 1;
 #pragma unroll
       for (int i = 0; i < Q; i++) {
-        int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
+        int tx = x + mv * CX[i], ty = y + mv * CY[i], tz = z + mv * CZ[i];
         if (PER) {
           if (b.pmask & 1) tx = wrapc(tx, b.nx);
           if (b.pmask & 2) ty = wrapc(ty, b.ny);
@@ -1444,9 +1479,9 @@ __global__ __launch_bounds__(WG) void k_check(LbArgs A) {
         const double d = (double)St::dec(raw[i], b.dec[WCLS[i]]);
         const double v = is_interior(b, tx, ty, tz) ? d : 0.0;
         acc[0] += v;
-        if (CX[i]) acc[1] += CX[i] * v;
-        if (CY[i]) acc[2] += CY[i] * v;
-        if (CZ[i]) acc[3] += CZ[i] * v;
+        if (CX[i]) acc[1] += dir * CX[i] * v;
+        if (CY[i]) acc[2] += dir * CY[i] * v;
+        if (CZ[i]) acc[3] += dir * CZ[i] * v;
       }
     }
   }

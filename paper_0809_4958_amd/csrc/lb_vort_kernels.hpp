@@ -24,7 +24,7 @@ constexpr int VH = VT + 2;
 struct VortArgs {
   BoxDesc b;
   const void* src;      // the box's populations in the current arena
-  int pre;              // the arena holds a pre-collision state (read in place)
+  int pre;              // layout of the arena (LAYOUT_PULL, LAYOUT_PLACE or LAYOUT_SWAP)
   double rho0;
   int lo[3], hi[3];     // control volume, inclusive node ranges
   int tx, ty, zslab;    // tiles along x and y, planes per workgroup
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(VT * VT) void k_vort(VortArgs A) {
         if (b.pmask & 4) zz = wrapc(zz, b.nz);
       }
       R d[Q];
-      load_pre<S, PER>(src, b, x, y, zz, A.pre != 0, d);
+      load_pre<S, PER>(src, b, x, y, zz, A.pre, d);
       double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
       for (int i = 0; i < Q; i++) {

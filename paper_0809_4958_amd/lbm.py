@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "LB_OK", -1: "LB_ERR_ARG", -2: "LB_ERR_OOM", -3: "LB_ERR_HIP"
 BGK, MRT = 0, 1
 STORE_F64, STORE_F32, STORE_F16DEV = 0, 1, 2
 BC_AFFINE, BC_SAMPLED, BC_LEARNED = 0, 1, 2
+STREAM_AB, STREAM_AA = 0, 1
 F_RHO, F_U, F_POP, F_BEAD_POS, F_BEAD_VEL, F_MASS_MOM, F_STEP, F_POP_DEV, F_BEAD_REL, F_VORT = \
     range(10)
 
@@ -43,7 +44,7 @@ class LbConfig(ct.Structure):
                 ("storage", ct.c_int), ("rho0", ct.c_double), ("reduce_every", ct.c_int32),
                 ("fp16_exp", ct.c_int32), ("stream", ct.c_void_p), ("dev_alloc", ALLOC_FN),
                 ("dev_free", FREE_FN), ("alloc_user", ct.c_void_p), ("tune_cache", ct.c_char_p),
-                ("graph_steps", ct.c_int32)]
+                ("graph_steps", ct.c_int32), ("streaming", ct.c_int32)]
 
 
 class LbBoundary(ct.Structure):
@@ -144,7 +145,7 @@ class Context:
 
     def __init__(self, boxes, collision=BGK, tau=0.8, tau_bulk=None, ghost_rate=1.0,
                  storage=STORE_F64, rho0=1.0, reduce_every=0, fp16_exp=0, stream=None,
-                 torch_alloc=False, tune_cache=None, graph_steps=0):
+                 torch_alloc=False, tune_cache=None, graph_steps=0, streaming=STREAM_AB):
         self._lib = load()
         self.boxes = [tuple(int(v) for v in b) + ((0,) if len(b) == 3 else ()) for b in boxes]
         arr = (LbBox * len(self.boxes))(*[LbBox(*b) for b in self.boxes])
@@ -162,6 +163,7 @@ class Context:
         cfg.fp16_exp = fp16_exp
         cfg.stream = stream
         cfg.graph_steps = graph_steps
+        cfg.streaming = streaming
         if tune_cache:
             self._tc = tune_cache.encode()
             cfg.tune_cache = self._tc
