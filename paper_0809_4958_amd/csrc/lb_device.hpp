@@ -176,14 +176,16 @@ __device__ __forceinline__ R wgt(int i) { return (R)WD[WCLS[i]]; }
 // into every post-collision population, that same-signed factor would scale
 // the conserved mass and momentum on every step and build up over the flow's
 // relaxation time (1e-5 of the velocity over 10^4 steps of a 128^3 box).  The
-// residual w_c - (float)w_c, added by a fused multiply-add, cancels it; in
-// FP64 the weights' rounding (1e-17) is left alone.
+// residual w_c - (float)w_c, added by a fused multiply-add, cancels it (CW:
+// FP32 storage).  In FP64 the weights' rounding (1e-17) is left alone, and in
+// FP16 storage the half-precision rounding of every stored value (2^-11) is
+// far larger than the bias, so the step keeps the plain product there.
 constexpr float WF[3] = {(float)WD[0], (float)WD[1], (float)WD[2]};
 constexpr float WLO[3] = {(float)(WD[0] - (double)WF[0]), (float)(WD[1] - (double)WF[1]),
                           (float)(WD[2] - (double)WF[2])};
-template <typename R>
+template <typename R, bool CW>
 __host__ __device__ __forceinline__ constexpr R wmul(int c, R x) {
-  if constexpr (sizeof(R) == 4) {
+  if constexpr (CW && sizeof(R) == 4) {
     return __builtin_fmaf(x, WF[c], x * WLO[c]);
   } else {
     return (R)WD[c] * x;
@@ -195,20 +197,20 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Equilibrium deviation f_eq_i(rho, u) - w_i rho0 = w_i [drho + rho(3 cu + 9/2 cu^2 - 3/2 u^2)]
-template <typename R>
+template <typename R, bool CW = false>
 __device__ __forceinline__ void eq_dev(R drho, R rho, R ux, R uy, R uz, R out[Q]) {
   const R uu = ux * ux + uy * uy + uz * uz;
   const R base = drho - (R)1.5 * rho * uu;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const R cu = (R)CX[i] * ux + (R)CY[i] * uy + (R)CZ[i] * uz;
-    out[i] = wmul<R>(WCLS[i], base + rho * cu * ((R)3.0 + (R)4.5 * cu));
+    out[i] = wmul<R, CW>(WCLS[i], base + rho * cu * ((R)3.0 + (R)4.5 * cu));
   }
 }
 
 // Collision of one node in deviation form.  d[] in: pre-collision deviations,
 // out: post-collision deviations.  g: force density of this step.
-template <typename R, int COLL>
+template <typename R, int COLL, bool CW = false>
 __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omega, R om_bulk,
                                         R om_ghost) {
   R drho = 0, jx = 0, jy = 0, jz = 0;
@@ -227,14 +229,14 @@ __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omeg
   if (COLL == 0) {
     // BGK with Guo forcing
     R eq[Q];
-    eq_dev<R>(drho, rho, ux, uy, uz, eq);
+    eq_dev<R, CW>(drho, rho, ux, uy, uz, eq);
     const R ug = ux * gx + uy * gy + uz * gz;
     const R fpre = (R)1 - (R)0.5 * omega;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
       const R cu = (R)CX[i] * ux + (R)CY[i] * uy + (R)CZ[i] * uz;
       const R cg = (R)CX[i] * gx + (R)CY[i] * gy + (R)CZ[i] * gz;
-      const R F = wmul<R>(WCLS[i], (R)3 * (cg - ug) + (R)9 * cu * cg);
+      const R F = wmul<R, CW>(WCLS[i], (R)3 * (cg - ug) + (R)9 * cu * cg);
       d[i] = d[i] - omega * (d[i] - eq[i]) + fpre * F;
     }
   } else {
@@ -297,7 +299,7 @@ __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omeg
         else if (e == -1) s -= ms[k];
         else if (e != 0) s += (R)e * ms[k];
       }
-      d[i] = wmul<R>(WCLS[i], s);
+      d[i] = wmul<R, CW>(WCLS[i], s);
     }
   }
 }
@@ -396,12 +398,12 @@ __host__ __device__ constexpr void mrt_forward(const R d[Q], R m[Q]) {
 
 // Back transform of moments already divided by b_k: d_i = w_i sum_k e_k(c_i) M_k.
 // GZ: the nine ghost moments are zero (not read).
-template <typename R, bool GZ>
+template <typename R, bool GZ, bool CW = false>
 __host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q]) {
   const R g10 = GZ ? R(0) : M[10], g11 = GZ ? R(0) : M[11], g12 = GZ ? R(0) : M[12];
   const R g13 = GZ ? R(0) : M[13], g14 = GZ ? R(0) : M[14], g15 = GZ ? R(0) : M[15];
   const R g16 = GZ ? R(0) : M[16], g17 = GZ ? R(0) : M[17], g18 = GZ ? R(0) : M[18];
-  d[0] = wmul<R>(0, M[0] - M[4] + g16);
+  d[0] = wmul<R, CW>(0, M[0] - M[4] + g16);
   const R E1 = M[0] + (M[5] + M[5]) - (g16 + g16) - (g17 + g17);
   const R O1 = M[1] - (g10 + g10);
   const R E2 = M[0] - M[5] + M[6] - (g16 + g16) + g17 - g18;
@@ -422,24 +424,24 @@ __host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q]) {
   const R O7 = x10 - z12 - g13 - g15;
   const R O8 = y11 + z12 + g14 - g15;
   const R O9 = y11 - z12 + g14 + g15;
-  d[1] = wmul<R>(1, E1 + O1);
-  d[2] = wmul<R>(1, E1 - O1);
-  d[3] = wmul<R>(1, E2 + O2);
-  d[4] = wmul<R>(1, E2 - O2);
-  d[5] = wmul<R>(1, E3 + O3);
-  d[6] = wmul<R>(1, E3 - O3);
-  d[7] = wmul<R>(2, E4 + O4);
-  d[8] = wmul<R>(2, E4 - O4);
-  d[9] = wmul<R>(2, E5 + O5);
-  d[10] = wmul<R>(2, E5 - O5);
-  d[11] = wmul<R>(2, E6 + O6);
-  d[12] = wmul<R>(2, E6 - O6);
-  d[13] = wmul<R>(2, E7 + O7);
-  d[14] = wmul<R>(2, E7 - O7);
-  d[15] = wmul<R>(2, E8 + O8);
-  d[16] = wmul<R>(2, E8 - O8);
-  d[17] = wmul<R>(2, E9 + O9);
-  d[18] = wmul<R>(2, E9 - O9);
+  d[1] = wmul<R, CW>(1, E1 + O1);
+  d[2] = wmul<R, CW>(1, E1 - O1);
+  d[3] = wmul<R, CW>(1, E2 + O2);
+  d[4] = wmul<R, CW>(1, E2 - O2);
+  d[5] = wmul<R, CW>(1, E3 + O3);
+  d[6] = wmul<R, CW>(1, E3 - O3);
+  d[7] = wmul<R, CW>(2, E4 + O4);
+  d[8] = wmul<R, CW>(2, E4 - O4);
+  d[9] = wmul<R, CW>(2, E5 + O5);
+  d[10] = wmul<R, CW>(2, E5 - O5);
+  d[11] = wmul<R, CW>(2, E6 + O6);
+  d[12] = wmul<R, CW>(2, E6 - O6);
+  d[13] = wmul<R, CW>(2, E7 + O7);
+  d[14] = wmul<R, CW>(2, E7 - O7);
+  d[15] = wmul<R, CW>(2, E8 + O8);
+  d[16] = wmul<R, CW>(2, E8 - O8);
+  d[17] = wmul<R, CW>(2, E9 + O9);
+  d[18] = wmul<R, CW>(2, E9 - O9);
 }
 
 __host__ __device__ constexpr bool pair_forward_matches_basis() {
@@ -474,7 +476,7 @@ static_assert(pair_backward_matches_basis(), "pair-form back transform != basis"
 // mode k >= 4 gains sqrt(mu rho b_k (1 - gamma_k^2)) r_k, which keeps its
 // fluctuations at the equilibrium variance mu rho b_k (mu = 3 kT); the ghosts
 // are then formed whatever GZ says.
-template <typename R, bool GZ, bool NOISE = false>
+template <typename R, bool GZ, bool NOISE = false, bool CW = false>
 __device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rho0, R omega,
                                                   R om_bulk, R om_ghost,
                                                   const Ext<R>* ext = nullptr) {
@@ -534,14 +536,14 @@ __device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rh
     for (int k = 5; k < 10; k++) M[k] += as * r[k - 4] * (R)sqrt(INVB[k]);
 #pragma unroll
     for (int k = 10; k < Q; k++) M[k] += ag * r[k - 4] * (R)sqrt(INVB[k]);
-    mrt_backward<R, false>(M, d);
+    mrt_backward<R, false, CW>(M, d);
   } else {
     if (!GZ) {
       const R gg = (R)1 - om_ghost;
 #pragma unroll
       for (int k = 10; k < Q; k++) M[k] = gg * m[k] * (R)INVB[k];
     }
-    mrt_backward<R, GZ>(M, d);
+    mrt_backward<R, GZ, CW>(M, d);
   }
 }
 

@@ -570,14 +570,19 @@ struct LbArgs {
   int aa;                  // in-place streaming on one buffer (a0 == a1): tile items only
 };
 
-// Collision dispatcher: 0 BGK, 1 MRT, 2 MRT with ghost rate 1.
-template <typename R, int COLL>
+// Collision dispatcher: 0 BGK, 1 MRT, 2 MRT with ghost rate 1.  CW: the
+// lattice weights applied with their FP32 residual (FP32 storage).
+template <typename R, int COLL, bool CW = false>
 __device__ __forceinline__ void collide_any(R d[Q], R gx, R gy, R gz, R rho0, R omega, R omb,
                                             R omg) {
-  if (COLL == 0) collide<R, 0>(d, gx, gy, gz, rho0, omega, omb, omg);
-  else if (COLL == 1) collide_mrt_pairs<R, false>(d, gx, gy, gz, rho0, omega, omb, omg);
-  else collide_mrt_pairs<R, true>(d, gx, gy, gz, rho0, omega, omb, omg);
+  if (COLL == 0) collide<R, 0, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
+  else if (COLL == 1) collide_mrt_pairs<R, false, false, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
+  else collide_mrt_pairs<R, true, false, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
 }
+
+// whether the step of storage S applies the weights with their residual
+template <int S>
+constexpr bool comp_weights() { return S == 1; }
 
 // Tracer acceleration of a box at step n (accelerated-frame body force,
 // Sec. 2): linear in time between samples, in FP64 like the samples.
@@ -622,7 +627,7 @@ __device__ __forceinline__ Ext<R> make_ext(const LbArgs& A, const BoxDesc& b, lo
 // Collision with the extensions: the force density of the chains g plus the
 // body force -rho a (rho the node's pre-collision density), and the
 // fluctuating collision when mu > 0 (MRT only).
-template <typename R, int COLL>
+template <typename R, int COLL, bool CW = false>
 __device__ __forceinline__ void collide_ext(R d[Q], R gx, R gy, R gz, R rho0, R omega, R omb,
                                             R omg, const Ext<R>& e) {
   R drho = 0;
@@ -633,9 +638,9 @@ __device__ __forceinline__ void collide_ext(R d[Q], R gx, R gy, R gz, R rho0, R 
   gy -= rho * e.ay;
   gz -= rho * e.az;
   if (COLL != 0 && e.mu > (R)0)
-    collide_mrt_pairs<R, COLL == 2, true>(d, gx, gy, gz, rho0, omega, omb, omg, &e);
+    collide_mrt_pairs<R, COLL == 2, true, CW>(d, gx, gy, gz, rho0, omega, omb, omg, &e);
   else
-    collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+    collide_any<R, COLL, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
 }
 
 // Spread force g(x) = - sum_j w_jx dP_j at node (x, y, z): chains whose stencil
@@ -725,9 +730,9 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
       }
       if constexpr (EXT) {
         ext.node = ((unsigned)z * ny + (unsigned)y) * nx + (unsigned)x;
-        collide_ext<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
       } else {
-        collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
       }
 #pragma unroll
       for (int i = 0; i < Q; i++) {
@@ -969,9 +974,9 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
       const int x = x0 + k;
       if constexpr (EXT) {
         ext.node = ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
-        collide_ext<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
       } else {
-        collide_any<R, COLL>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
       }
 #pragma unroll
       for (int i = 0; i < Q; i++) {
@@ -1078,14 +1083,15 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
 }
 
 // Interior tile, general addressing (periodic axes wrap, any box size).
-// In-place streaming (A.aa): an even step reads each node in place and
-// writes f*_i into its own slot OPP[i]; an odd step reads those (LAYOUT_SWAP)
-// and writes f*_i into slot i of node x + c_i, where the next even step reads
-// it in place.  Each slot is read and written by one node only.
+// In-place streaming (aa): an even step reads each node in place and writes
+// f*_i into its own slot OPP[i]; an odd step reads those (LAYOUT_SWAP) and
+// writes f*_i into slot i of node x + c_i, where the next even step reads it
+// in place.  Each slot is read and written by one node only.
 template <int S, int COLL, bool PER, int BS, bool EXT>
 __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, const Item& it,
                                              const typename Store<S>::T* src,
-                                             typename Store<S>::T* dst, int layout, long long step,
+                                             typename Store<S>::T* dst, int layout, bool aa,
+                                             long long step,
                                              unsigned long long cmask, typename Store<S>::R rho0,
                                              typename Store<S>::R omega, typename Store<S>::R omb,
                                              typename Store<S>::R omg) {
@@ -1106,14 +1112,14 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
       if (cmask) gather_force<R, PER, 1>(A, b, cmask, x, y, z, gx, gy, gz);
       if constexpr (EXT) {
         ext.node = (unsigned)(((int64_t)z * b.ny + y) * b.nx + x);
-        collide_ext<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
       } else {
-        collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg);
       }
-      if (A.aa && !(step & 1)) {
+      if (aa && !(step & 1)) {
 #pragma unroll
         for (int i = 0; i < Q; i++) dst[aidx(b, OPP[i], x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
-      } else if (A.aa) {
+      } else if (aa) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           int tx = x + CX[i], ty = y + CY[i], tz = z + CZ[i];
@@ -1152,7 +1158,10 @@ constexpr int lb_min_waves(int S, int COLL) {
 // its instantiations ask for two resident waves per SIMD.
 constexpr int lb_min_waves_ext(int S, int COLL, bool EXT) { return EXT ? 2 : lb_min_waves(S, COLL); }
 
-template <int S, int COLL, bool PER, int BS = WG, bool EXT = false>
+// AA: the instantiation for in-place streaming on boxes without periodic
+// axes (no row items, no stores of the two-buffer step); the periodic
+// instantiation takes either streaming from A.aa.
+template <int S, int COLL, bool PER, int BS = WG, bool EXT = false, bool AA = false>
 __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArgs A) {
   using St = Store<S>;
   using T = typename St::T;
@@ -1170,6 +1179,7 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
   const T* __restrict__ srcA = (const T*)(par ? A.a1 : A.a0);
   T* __restrict__ dstA = (T*)(par ? A.a0 : A.a1);
   const bool pre = A.pre != 0;
+  const bool aa = AA || (PER && A.aa);
 
   for (int e = blockIdx.x; e < A.n_entries; e += gridDim.x) {
     const int ii = A.order[e];
@@ -1181,7 +1191,7 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
 
     if (it.kind == ITEM_ROWS) {
       // row boxes are never periodic: their chains couple in k_force
-      if constexpr (S != 0 && !PER) {
+      if constexpr (S != 0 && !PER && !AA) {
 #define LB_ROWS(PR)                                                                    \
   do {                                                                                 \
     if (b.vw == 3)                                                                     \
@@ -1194,7 +1204,7 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
 #undef LB_ROWS
       }
     } else if (it.kind == ITEM_FACE_ROWS) {
-      if constexpr (S != 0 && !PER) {
+      if constexpr (S != 0 && !PER && !AA) {
         if (b.vw == 3) face_rows<S, 3, BS>(b, it, dst, step, rho0);
         else face_rows<S, 2, BS>(b, it, dst, step, rho0);
       }
@@ -1202,19 +1212,19 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
       // chains whose stencil box overlaps this tile, periodic boxes only (the
       // chains of the other boxes couple in k_force)
       unsigned long long cmask = 0;
-      const bool gather = (PER && b.pmask) || A.aa;
+      const bool gather = (PER && b.pmask) || aa;
       for (int c = 0; gather && c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
         const int* bb = A.bbox + 6 * (b.chain_first + c);
         const bool ov = bb[0] <= it.x0 + it.ex - 1 && bb[3] >= it.x0 && bb[1] <= it.y0 + it.ey - 1 &&
                         bb[4] >= it.y0 && bb[2] <= it.z0 + it.ez - 1 && bb[5] >= it.z0;
         if (ov) cmask |= 1ull << c;
       }
-      if (!PER && b.fast) {
+      if (!PER && !AA && b.fast) {
         tile_fast<S, COLL, BS, EXT>(A, b, it, src, dst, pre, step, rho0, omega, omb, omg);
       } else {
-        const int layout = A.aa ? aa_layout(step) : (pre ? LAYOUT_PLACE : LAYOUT_PULL);
-        tile_generic<S, COLL, PER, BS, EXT>(A, b, it, src, dst, layout, step, cmask, rho0, omega,
-                                            omb, omg);
+        const int layout = aa ? aa_layout(step) : (pre ? LAYOUT_PLACE : LAYOUT_PULL);
+        tile_generic<S, COLL, PER, BS, EXT>(A, b, it, src, dst, layout, aa, step, cmask, rho0,
+                                            omega, omb, omg);
       }
     } else {
       // boundary chunk: equilibrium at rho0 and u_b(t_n) for the populations
@@ -1247,9 +1257,9 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
           if (!is_interior(b, tx, ty, tz)) continue;
           // in-place streaming: an even step leaves the population in the
           // node's opposite slot, an odd step in slot i of the target node
-          if (A.aa && !(step & 1))
+          if (aa && !(step & 1))
             dst[aidx(b, OPP[i], q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
-          else if (A.aa)
+          else if (aa)
             dst[aidx(b, i, tx, ty, tz)] = St::enc(eq[i], b.enc[WCLS[i]]);
           else
             dst[aidx(b, i, q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
@@ -1315,9 +1325,9 @@ __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
         // the same body force and noise k_lb gave the node (same counter)
         Ext<R> ext = make_ext<R>(A, b, step);
         ext.node = (unsigned)(((int64_t)z * b.ny + y) * b.nx + x);
-        collide_ext<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
       } else {
-        collide_any<R, COLL>(d, gx, gy, gz, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg);
       }
 #pragma unroll
       for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);

@@ -23,7 +23,7 @@ using ChainLaunch = void (*)(int, hipStream_t, const lbdev::BoxDesc*, const lbde
 // C (0 BGK, 1 MRT, 2 MRT with ghost rate 1), periodic or not; ext: the
 // extended collision (accelerated-frame body force, thermal fluctuations)
 template <int S, int C>
-LbLaunch pick_lb(bool periodic, bool ext);
+LbLaunch pick_lb(bool periodic, bool ext, bool in_place);
 
 // chain forcing pass after the fused step (grid: one workgroup per chain)
 template <int S, int C>

@@ -13,18 +13,19 @@ namespace lbhost {
 
 using namespace lbdev;
 
-template <int S, int C, bool P, bool E>
+template <int S, int C, bool P, bool E, bool AA>
 void launch_lb(dim3 g, hipStream_t s, const LbArgs& a) {
-  hipLaunchKernelGGL((k_lb<S, C, P, WG, E>), g, dim3(WG), 0, s, a);
+  hipLaunchKernelGGL((k_lb<S, C, P, WG, E, AA>), g, dim3(WG), 0, s, a);
 }
 
 template <int S, int C>
-LbLaunch pick_lb(bool periodic, bool ext) {
-  if (ext) return periodic ? launch_lb<S, C, true, true> : launch_lb<S, C, false, true>;
-  return periodic ? launch_lb<S, C, true, false> : launch_lb<S, C, false, false>;
+LbLaunch pick_lb(bool periodic, bool ext, bool in_place) {
+  if (periodic) return ext ? launch_lb<S, C, true, true, false> : launch_lb<S, C, true, false, false>;
+  if (in_place) return ext ? launch_lb<S, C, false, true, true> : launch_lb<S, C, false, false, true>;
+  return ext ? launch_lb<S, C, false, true, false> : launch_lb<S, C, false, false, false>;
 }
 
-template LbLaunch pick_lb<LB_S, LB_C>(bool, bool);
+template LbLaunch pick_lb<LB_S, LB_C>(bool, bool, bool);
 
 template <int S, int C, bool P, bool E>
 void launch_force(dim3 g, hipStream_t s, const LbArgs& a) {

@@ -107,10 +107,10 @@ CheckLaunch pick_check(bool per) {
 
 // coll: 0 BGK, 1 MRT, 2 MRT with ghost relaxation rate 1 (ghost moments not formed)
 template <int S>
-LbLaunch pick_lb(int coll, bool per, bool ext) {
-  if (coll == 0) return lbhost::pick_lb<S, 0>(per, ext);
-  if (coll == 1) return lbhost::pick_lb<S, 1>(per, ext);
-  return lbhost::pick_lb<S, 2>(per, ext);
+LbLaunch pick_lb(int coll, bool per, bool ext, bool aa) {
+  if (coll == 0) return lbhost::pick_lb<S, 0>(per, ext, aa);
+  if (coll == 1) return lbhost::pick_lb<S, 1>(per, ext, aa);
+  return lbhost::pick_lb<S, 2>(per, ext, aa);
 }
 
 template <int S>
@@ -748,10 +748,11 @@ void select_launchers(lb_ctx* ctx) {
   bool ext = ctx->kT > 0.0;
   for (auto& b : ctx->bx) ext = ext || b.body_ns > 0;
   const int kc = ctx->coll == LB_BGK ? 0 : (ctx->cfg.ghost_rate == 1.0 ? 2 : 1);
+  const bool aa = ctx->aa;
   switch (ctx->S) {
-    case 0: ctx->lb_fn = pick_lb<0>(kc, ctx->per, ext); ctx->force_fn = pick_force<0>(kc, ctx->per, ext); break;
-    case 1: ctx->lb_fn = pick_lb<1>(kc, ctx->per, ext); ctx->force_fn = pick_force<1>(kc, ctx->per, ext); break;
-    default: ctx->lb_fn = pick_lb<2>(kc, ctx->per, ext); ctx->force_fn = pick_force<2>(kc, ctx->per, ext); break;
+    case 0: ctx->lb_fn = pick_lb<0>(kc, ctx->per, ext, aa); ctx->force_fn = pick_force<0>(kc, ctx->per, ext); break;
+    case 1: ctx->lb_fn = pick_lb<1>(kc, ctx->per, ext, aa); ctx->force_fn = pick_force<1>(kc, ctx->per, ext); break;
+    default: ctx->lb_fn = pick_lb<2>(kc, ctx->per, ext, aa); ctx->force_fn = pick_force<2>(kc, ctx->per, ext); break;
   }
 }
 

@@ -1,7 +1,7 @@
 """In-place streaming (one population buffer, LB_STREAM_AA): parity with the
 oracle in every storage, with and without chains, on walled, periodic and
-mixed boxes; bit-for-bit equality with the two-buffer step on the same tile
-items, after even and odd step counts; checkpoint/resume at even and odd
+mixed boxes; equality with the two-buffer step on the same tile items (FP16
+bit for bit, FP32 to a few ulp), after even and odd step counts; checkpoint/resume at even and odd
 steps; graph replay; the extended collision (body force, thermal noise); half
 the population memory; and the 512^3 large box against its oracle values."""
 import os
@@ -60,7 +60,15 @@ def test_aa_ks_box_with_chain_against_oracle(storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_aa_bitwise_equals_two_buffer_tiles(storage):
+def test_aa_equals_two_buffer_tiles(storage):
+    """Same step on the same tile items: FP16 bit for bit; FP32 to a few
+    units in the last place of the largest population.  In-place streaming
+    runs its own kernel instantiation, and the fused multiply-adds the
+    compiler forms there may round differently from the two-buffer one
+    (measured: 1 ulp on the 8 interior corner nodes after the first step,
+    spreading to ~2% of the nodes at the same size after 7 steps).  An
+    addressing mistake moves whole populations, orders of magnitude above
+    this bound."""
     cases = [ks_case(n, 40, dt=20, res=9, n_beads=6, config_idx=2, box_idx=i)
              for i, n in enumerate([20, 27])]
     for c in cases:
@@ -72,9 +80,17 @@ def test_aa_bitwise_equals_two_buffer_tiles(storage):
         aa.step(n)
         ab.step(n)
         for k, c in enumerate(cases):
-            assert np.array_equal(aa.read(k, lbm.F_POP_DEV), ab.read(k, lbm.F_POP_DEV)), (n, k)
-            assert np.array_equal(aa.read(k, lbm.F_BEAD_POS, n_beads=6),
-                                  ab.read(k, lbm.F_BEAD_POS, n_beads=6))
+            pa, pb = aa.read(k, lbm.F_POP_DEV), ab.read(k, lbm.F_POP_DEV)
+            ba, bb = aa.read(k, lbm.F_BEAD_POS, n_beads=6), ab.read(k, lbm.F_BEAD_POS, n_beads=6)
+            if storage == "f16":
+                assert np.array_equal(pa, pb), (n, k)
+                assert np.array_equal(ba, bb)
+            else:
+                ulp = np.spacing(np.float32(np.abs(pb).max()))
+                say(f"after {n} steps box {k}: max |diff| {np.abs(pa - pb).max() / ulp:.1f} ulp, "
+                    f"nodes differing {int(np.any(pa != pb, axis=0).sum())}")
+                assert np.abs(pa - pb).max() <= 8 * ulp, (n, k)
+                assert np.abs(ba - bb).max() < 1e-6
             ma, mb = aa.read(k, lbm.F_MASS_MOM), ab.read(k, lbm.F_MASS_MOM)
             assert ma[0] == mb[0] and abs(ma[1] - mb[1]) < 1e-12 * mb[1]
     aa.close()
