@@ -119,17 +119,24 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
                                               const ChainDesc* __restrict__ chains,
                                               const typename Store<S>::T* __restrict__ a0,
                                               const typename Store<S>::T* __restrict__ a1,
-                                              typename Store<S>::R* __restrict__ pos,
-                                              typename Store<S>::R* __restrict__ vel,
+                                              double* __restrict__ pos,
+                                              double* __restrict__ vel,
                                               int total_beads, int4* __restrict__ rec_base,
-                                              typename Store<S>::R* __restrict__ rec_d,
-                                              typename Store<S>::R* __restrict__ rec_dp,
+                                              double* __restrict__ rec_d,
+                                              double* __restrict__ rec_dp,
                                               int* __restrict__ bbox, DevState* __restrict__ st,
                                               double rho0_d, int pre, long long* stamp,
                                               int n_chains, const int4* __restrict__ xf_items,
                                               int n_xf_items, float* __restrict__ xface,
                                               unsigned key0, unsigned key1) {
-  using R = typename Store<S>::R;
+  // Chain arithmetic in FP64 for every storage.  The friction impulses of a
+  // chain's beads are dominated by their bond forces, which cancel between
+  // neighbouring beads on the nodes the spreading shares: the node force is
+  // a small difference of large terms, and FP32 impulses and stencil weights
+  // cost 1e-4 of the fluid velocity near 32 collapsed 256-bead chains over
+  // 2,000 steps (FP32 storage, against 5e-8 without chains).
+  using R = double;
+  using RP = typename Store<S>::R;
   const int ci = blockIdx.x;
   if (ci >= n_chains) {
     const int item = (ci - n_chains) * (CB / 64) +
@@ -221,7 +228,7 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
       }
       const R w = (o0 ? dl[0] : (R)1 - dl[0]) * (o1 ? dl[1] : (R)1 - dl[1]) *
                   (o2 ? dl[2] : (R)1 - dl[2]);
-      R d[Q];
+      RP d[Q];
       load_pre<S, PER>(src, b, qx, qy, qz, pre == 2 ? aa_layout(step) : pre, d);
       R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -253,18 +260,7 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
   auto fene = [&](R ex, R ey, R ez, R& fx, R& fy, R& fz) -> bool {
     const R r2 = ex * ex + ey * ey + ez * ez;
     if (r2 >= r02) return false;
-    R fac;
-    if (S != 0 && r2 > (R)0.8 * r02) {
-      // near full extension: evaluate the FENE factor in FP64, and decide
-      // the range there too (within a few float ulps of R0 the FP32 test can
-      // pass while the FP64 separation has already reached R0)
-      const double r2d = (double)ex * ex + (double)ey * ey + (double)ez * ez;
-      const double r02d = c.fene_r0 * c.fene_r0;
-      if (r2d >= r02d) return false;
-      fac = (R)(c.fene_k / (1.0 - r2d / r02d));
-    } else {
-      fac = fk / ((R)1 - r2 / r02);
-    }
+    const R fac = fk / ((R)1 - r2 / r02);
     fx = fac * ex;
     fy = fac * ey;
     fz = fac * ez;
@@ -651,8 +647,11 @@ template <typename R, bool PER, int UNROLL>
 __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
                                              unsigned long long cmask, int x, int y, int z, R& gx,
                                              R& gy, R& gz) {
-  const R* rd = (const R*)A.rec_d;
-  const R* rp = (const R*)A.rec_dp;
+  // records and sums in FP64 (the bead impulses cancel on shared nodes),
+  // rounded to the collision's precision once
+  const double* rd = (const double*)A.rec_d;
+  const double* rp = (const double*)A.rec_dp;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
   for (int c = 0; c < b.chain_count && c < MAX_BOX_CHAINS; c++) {
     if (!((cmask >> c) & 1ull)) continue;
     const int gc = b.chain_first + c;
@@ -672,15 +671,18 @@ __device__ __forceinline__ void gather_force(const LbArgs& A, const BoxDesc& b,
         if ((b.pmask & 4) && oz < 0) oz += b.nz;
       }
       const bool hit = (unsigned)ox <= 1u && (unsigned)oy <= 1u && (unsigned)oz <= 1u;
-      const R w = (ox ? rd[3 * jb] : (R)1 - rd[3 * jb]) *
-                  (oy ? rd[3 * jb + 1] : (R)1 - rd[3 * jb + 1]) *
-                  (oz ? rd[3 * jb + 2] : (R)1 - rd[3 * jb + 2]);
-      const R px = rp[3 * jb], py = rp[3 * jb + 1], pz = rp[3 * jb + 2];
-      gx -= hit ? w * px : (R)0;
-      gy -= hit ? w * py : (R)0;
-      gz -= hit ? w * pz : (R)0;
+      const double w = (ox ? rd[3 * jb] : 1.0 - rd[3 * jb]) *
+                       (oy ? rd[3 * jb + 1] : 1.0 - rd[3 * jb + 1]) *
+                       (oz ? rd[3 * jb + 2] : 1.0 - rd[3 * jb + 2]);
+      const double px = rp[3 * jb], py = rp[3 * jb + 1], pz = rp[3 * jb + 2];
+      sx -= hit ? w * px : 0.0;
+      sy -= hit ? w * py : 0.0;
+      sz -= hit ? w * pz : 0.0;
     }
   }
+  gx += (R)sx;
+  gy += (R)sy;
+  gz += (R)sz;
 }
 
 // Interior tile of a non-periodic box whose population groups (0..9 and
@@ -734,10 +736,11 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
       } else {
         collide_any<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
       }
+      const unsigned hn = dither_node(((unsigned)z * ny + (unsigned)y) * nx + (unsigned)x, (unsigned)step);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float k = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-        *(T*)(d0 + (voff + doff[i])) = St::enc(d[i], k);
+        *(T*)(d0 + (voff + doff[i])) = St::enc(d[i], k, dither_pop(hn, i));
       }
     }
   }
@@ -978,28 +981,33 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
       } else {
         collide_any<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
       }
+      const unsigned hn =
+          dither_node(((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x, (unsigned)step);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-        vput<S, W>(out[i], k, St::enc(d[i], ke));
+        vput<S, W>(out[i], k, St::enc(d[i], ke, dither_pop(hn, i)));
       }
     }
     // x-face nodes of this row: boundary equilibrium at t_n (faces -x, +x)
     if (xface) {
       R eq[Q];
       eq_dev<R>((R)0, rho0, xu[0], xu[1], xu[2], eq);
+      const unsigned xn = xside == 0 ? 0u : (unsigned)(nx - 1);
+      const unsigned hx =
+          dither_node(((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + xn, (unsigned)step);
       // element indices stay compile-time constants (registers, not scratch)
       if (xside == 0) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-          vput<S, W>(out[i], 0, St::enc(eq[i], ke));
+          vput<S, W>(out[i], 0, St::enc(eq[i], ke, dither_pop(hx, i)));
         }
       } else {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-          vput<S, W>(out[i], V - 1, St::enc(eq[i], ke));
+          vput<S, W>(out[i], V - 1, St::enc(eq[i], ke, dither_pop(hx, i)));
         }
       }
     }
@@ -1060,10 +1068,12 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
       boundary_velocity<R>(b, f, qn, tm, u);
       R eq[Q];
       eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
+      const unsigned hn =
+          dither_node(((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x, (unsigned)step);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-        vput<S, W>(out[i], k, St::enc(eq[i], ke));
+        vput<S, W>(out[i], k, St::enc(eq[i], ke, dither_pop(hn, i)));
       }
     }
     char* row = (char*)dst + (long long)z * psb + (long long)(y >> yl) * bkb + (long long)(y & ym) * nxb +
@@ -1116,9 +1126,11 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
       } else {
         collide_any<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg);
       }
+      const unsigned hn = dither_node((unsigned)(((int64_t)z * b.ny + y) * b.nx + x), (unsigned)step);
       if (aa && !(step & 1)) {
 #pragma unroll
-        for (int i = 0; i < Q; i++) dst[aidx(b, OPP[i], x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+        for (int i = 0; i < Q; i++)
+          dst[aidx(b, OPP[i], x, y, z)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
       } else if (aa) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
@@ -1128,11 +1140,12 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
             if (b.pmask & 2) ty = wrapc(ty, b.ny);
             if (b.pmask & 4) tz = wrapc(tz, b.nz);
           }
-          dst[aidx(b, i, tx, ty, tz)] = St::enc(d[i], b.enc[WCLS[i]]);
+          dst[aidx(b, i, tx, ty, tz)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+        for (int i = 0; i < Q; i++)
+          dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
       }
     }
   }
@@ -1246,6 +1259,8 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
         boundary_velocity<R>(b, f, q, tm, u);
         R eq[Q];
         eq_dev<R>((R)0, rho0, u[0], u[1], u[2], eq);
+        const unsigned hn =
+            dither_node((unsigned)(((int64_t)q[2] * b.ny + q[1]) * b.nx + q[0]), (unsigned)step);
 #pragma unroll
         for (int i = 1; i < Q; i++) {
           int tx = q[0] + CX[i], ty = q[1] + CY[i], tz = q[2] + CZ[i];
@@ -1257,12 +1272,13 @@ __global__ __launch_bounds__(BS, lb_min_waves_ext(S, COLL, EXT)) void k_lb(LbArg
           if (!is_interior(b, tx, ty, tz)) continue;
           // in-place streaming: an even step leaves the population in the
           // node's opposite slot, an odd step in slot i of the target node
+          const T v = St::enc(eq[i], b.enc[WCLS[i]], dither_pop(hn, i));
           if (aa && !(step & 1))
-            dst[aidx(b, OPP[i], q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
+            dst[aidx(b, OPP[i], q[0], q[1], q[2])] = v;
           else if (aa)
-            dst[aidx(b, i, tx, ty, tz)] = St::enc(eq[i], b.enc[WCLS[i]]);
+            dst[aidx(b, i, tx, ty, tz)] = v;
           else
-            dst[aidx(b, i, q[0], q[1], q[2])] = St::enc(eq[i], b.enc[WCLS[i]]);
+            dst[aidx(b, i, q[0], q[1], q[2])] = v;
         }
       }
     }
@@ -1329,8 +1345,10 @@ __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
       } else {
         collide_any<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg);
       }
+      const unsigned hn = dither_node((unsigned)(((int64_t)z * b.ny + y) * b.nx + x), (unsigned)step);
 #pragma unroll
-      for (int i = 0; i < Q; i++) dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]]);
+      for (int i = 0; i < Q; i++)
+        dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
     }
   }
   // On steps without a check pass (advance set) the last workgroup to take a

@@ -48,12 +48,11 @@ void launch_chain(int nch, hipStream_t s, const BoxDesc* boxes, const ChainDesc*
                   long long* stamp, const int4* xf_items, int n_xf, float* xface, unsigned key0,
                   unsigned key1) {
   using T = typename Store<S>::T;
-  using R = typename Store<S>::R;
   // one workgroup per chain, then CB / 64 x-face work items per workgroup
   const int nxb = (n_xf + CB / 64 - 1) / (CB / 64);
   hipLaunchKernelGGL((k_chain<S, P, CB, TH>), dim3(nch + nxb), dim3(CB), 0, s, boxes, chains,
-                     (const T*)a0, (const T*)a1, (R*)pos, (R*)vel, total, rb, (R*)rd, (R*)rp, bbox,
-                     st, rho0, pre, stamp, nch, xf_items, n_xf, xface, key0, key1);
+                     (const T*)a0, (const T*)a1, (double*)pos, (double*)vel, total, rb, (double*)rd,
+                     (double*)rp, bbox, st, rho0, pre, stamp, nch, xf_items, n_xf, xface, key0, key1);
 }
 
 template <int S, bool TH>

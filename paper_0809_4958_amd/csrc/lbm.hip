@@ -121,7 +121,6 @@ LbLaunch pick_force(int coll, bool per, bool ext) {
 }
 
 size_t store_bytes(int s) { return s == LB_STORE_F64 ? 8 : (s == LB_STORE_F32 ? 4 : 2); }
-size_t real_bytes(int s) { return s == LB_STORE_F64 ? 8 : 4; }
 // nodes per lane of the row items with w 32-bit words per lane
 int row_nodes(int s, int w) { return w * 4 / (int)store_bytes(s); }
 
@@ -626,12 +625,6 @@ lb_status upload_boxes(lb_ctx* ctx) {
   return LB_OK;
 }
 
-template <typename R>
-void to_real(const std::vector<double>& in, std::vector<R>& out) {
-  out.resize(in.size());
-  for (size_t i = 0; i < in.size(); i++) out[i] = (R)in[i];
-}
-
 // chain tables, bead state (into the parity buffer of the current step),
 // spreading records
 lb_status upload_chains(lb_ctx* ctx) {
@@ -690,7 +683,7 @@ lb_status upload_chains(lb_ctx* ctx) {
   }
   ctx->total_beads = first;
   bool ok = true;
-  const size_t rb = real_bytes(ctx->S);
+  const size_t rb = sizeof(double);  // bead state and records: FP64 for every storage
   const size_t nbd = std::max(1, first);
   ctx->d_chains = dalloc_t<ChainDesc>(ctx, std::max<size_t>(1, cd.size()), &ok);
   ctx->d_pos = dalloc(ctx, 2 * 3 * nbd * rb);
@@ -707,16 +700,8 @@ lb_status upload_chains(lb_ctx* ctx) {
   char* pbase = (char*)ctx->d_pos + (size_t)par * 3 * nbd * rb;
   char* vbase = (char*)ctx->d_vel + (size_t)par * 3 * nbd * rb;
   if (first) {
-    if (ctx->S == LB_STORE_F64) {
-      HIPCHK(h2d(ctx, pbase, rel.data(), rel.size() * 8));
-      HIPCHK(h2d(ctx, vbase, vel.data(), vel.size() * 8));
-    } else {
-      std::vector<float> r, v;
-      to_real(rel, r);
-      to_real(vel, v);
-      HIPCHK(h2d(ctx, pbase, r.data(), r.size() * 4));
-      HIPCHK(h2d(ctx, vbase, v.data(), v.size() * 4));
-    }
+    HIPCHK(h2d(ctx, pbase, rel.data(), rel.size() * sizeof(double)));
+    HIPCHK(h2d(ctx, vbase, vel.data(), vel.size() * sizeof(double)));
   }
   // empty bounding boxes until the first chain step
   std::vector<int> bb(6 * std::max<size_t>(1, cd.size()));
@@ -1652,17 +1637,11 @@ lb_status lb_read_fields(lb_ctx* ctx, int32_t box, lb_field field, void* dst, si
     if (nb == 0) return ctx->latched;
     double* tmp = (double*)dalloc(ctx, (size_t)nb * 3 * sizeof(double));
     if (!tmp) return fail(ctx, LB_ERR_OOM, "readout allocation failed");
-    const size_t rb = real_bytes(ctx->S);
     const size_t nbd = std::max(1, ctx->total_beads);
     const bool is_pos = field != LB_F_BEAD_VEL;
-    const void* src = (char*)(is_pos ? ctx->d_pos : ctx->d_vel) + (size_t)par * 3 * nbd * rb;
-    if (ctx->S == 0)
-      hipLaunchKernelGGL(k_read_beads<double>, dim3(1), dim3(WG), 0, ctx->stream, ctx->d_chains, c0, c1,
-                         (const double*)src, tmp, field == LB_F_BEAD_POS ? 1 : 0);
-    else
-      hipLaunchKernelGGL(k_read_beads<float>, dim3(1), dim3(WG), 0, ctx->stream, ctx->d_chains, c0, c1,
-                         (const float*)src, tmp, field == LB_F_BEAD_POS ? 1 : 0);
-    (void)is_pos;
+    const void* src = (char*)(is_pos ? ctx->d_pos : ctx->d_vel) + (size_t)par * 3 * nbd * sizeof(double);
+    hipLaunchKernelGGL(k_read_beads<double>, dim3(1), dim3(WG), 0, ctx->stream, ctx->d_chains, c0, c1,
+                       (const double*)src, tmp, field == LB_F_BEAD_POS ? 1 : 0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(copy_sync(ctx, dst, tmp, (size_t)nb * 3 * sizeof(double), kind));

@@ -92,7 +92,8 @@ def test_aa_equals_two_buffer_tiles(storage):
                 assert np.abs(pa - pb).max() <= 8 * ulp, (n, k)
                 assert np.abs(ba - bb).max() < 1e-6
             ma, mb = aa.read(k, lbm.F_MASS_MOM), ab.read(k, lbm.F_MASS_MOM)
-            assert ma[0] == mb[0] and abs(ma[1] - mb[1]) < 1e-12 * mb[1]
+            # FP32: ulp differences of the populations reach the FP64 mass sum
+            assert ma[0] == mb[0] and abs(ma[1] - mb[1]) < (1e-12 if storage == "f16" else 1e-9) * mb[1]
     aa.close()
     ab.close()
 

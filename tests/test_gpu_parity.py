@@ -461,10 +461,11 @@ def zigzag_chain(n_beads, bond, centre, angle=0.5):
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_fene_near_full_extension(storage):
     """A chain pre-stretched to r^2/R0^2 = 0.856 (bonds 1.85, R0 = 2) in a
-    walled box under a weak affine strain: the FENE factor of every bond is
-    evaluated in its FP64 branch (r^2 > 0.8 R0^2) on every step of the run; a
-    small spring constant (3e-5) keeps the bonds in that range.  Fluid and
-    beads against the oracle."""
+    walled box under a weak affine strain, with FP32 and FP16 population
+    storage (the chain arithmetic is FP64 in every storage): the FENE factor
+    1/(1 - r^2/R0^2) amplifies a separation's error sevenfold there; a small
+    spring constant (3e-5) keeps every bond in 0.81 < r^2/R0^2 < 0.9 for the
+    whole run.  Fluid and beads against the oracle."""
     n, steps = 24, 100
     xc = np.full(3, (n - 1) / 2.0)
     pos = zigzag_chain(8, 1.85, xc)
@@ -477,11 +478,11 @@ def test_fene_near_full_extension(storage):
     assert ob.step(steps) == 0
     p_o, _ = ob.beads()
     r2 = np.sum(np.diff(p_o, axis=0) ** 2, axis=1) / 4.0
-    assert r2.min() > 0.81 and r2.max() < 0.9, r2  # the FP64 branch throughout
+    assert r2.min() > 0.81 and r2.max() < 0.9, r2  # near full extension throughout
     ctx = make_ctx(case, storage)
     ctx.step(steps)
     r = compare(ctx, ob, case, storage)
-    check(r, storage, "FENE FP64 branch")
+    check(r, storage, "FENE near full extension")
     ctx.close()
 
 
