@@ -101,6 +101,7 @@ struct BoxDesc {
   int rect_len[MAX_RECT][3];    // extent along x, y, z
   float dec[3];         // FP16 decode factor per weight class: w 2^-s
   float enc[3];         // FP16 encode factor per weight class: 2^s / w
+  float s2;             // FP16 scale 2^s
   double interior;      // number of interior nodes
   int fast;             // non-periodic and 19*nn*sizeof(T) < 2^32 (32-bit offsets)
   int vec;              // interior rows handled as lane vectors (ITEM_ROWS) incl. the x-face nodes
@@ -148,10 +149,14 @@ enum : int { EC_BEAD_OUT = 1, EC_FENE = 2, EC_UNSTABLE = 3 };
 // with probability equal to the fraction of an ulp makes every store's
 // error zero-mean and independent from step to step, and the accumulation
 // stops (an FP64 emulation of the same box: 1.9e-4, flat from step 100 on).
-// The 13 random bits of a store come from a counter: the node's linear index
-// in its box and the step index, mixed by the 32-bit MurmurHash3 finaliser
-// (Appleby), then a Weyl increment per direction; the state upload and the
-// re-layout of a checkpoint round to nearest (exact values there).
+// The rounding is gfx950's v_cvt_sr_f16_f32: the top 13 bits of a random
+// word are added below the last bit FP16 keeps and the rest is cut, so that
+// a value rounds up with probability equal to its fraction of an FP16 ulp
+// (subnormals included; rates checked on the device).  The random word of a
+// store comes from a counter: the node's linear index in its box and the
+// step index, mixed by the 32-bit MurmurHash3 finaliser (Appleby), plus a
+// Weyl increment per direction.  The state upload and the re-layout of a
+// checkpoint round to nearest (exact values there).
 __device__ __forceinline__ unsigned dither_node(unsigned node, unsigned step) {
   unsigned h = node * 0x9E3779B1u + step * 0x85EBCA77u;
   h ^= h >> 16;
@@ -165,6 +170,8 @@ __device__ __forceinline__ unsigned dither_pop(unsigned h, int i) {
   return h + (unsigned)i * 0x9E3779B9u;
 }
 
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+
 template <int S> struct Store;
 template <> struct Store<0> {
   using T = double;   // storage
@@ -172,6 +179,7 @@ template <> struct Store<0> {
   __device__ static R dec(T v, float) { return v; }
   __device__ static T enc(R v, float) { return v; }
   __device__ static T enc(R v, float, unsigned) { return v; }
+  __device__ static T keep(R v, unsigned) { return v; }
 };
 template <> struct Store<1> {
   using T = float;
@@ -179,6 +187,7 @@ template <> struct Store<1> {
   __device__ static R dec(T v, float) { return v; }
   __device__ static T enc(R v, float) { return v; }
   __device__ static T enc(R v, float, unsigned) { return v; }
+  __device__ static T keep(R v, unsigned) { return v; }
 };
 template <> struct Store<2> {
   using T = _Float16;
@@ -195,17 +204,33 @@ template <> struct Store<2> {
 #pragma clang fp contract(off)
     return (_Float16)(v * k);
   }
-  // stochastic rounding with random bits r (top 13 used): the FP32 bits
-  // plus r >> 19 (sign and magnitude: the sum grows the magnitude, and a
-  // finite value below FP16's range never carries into the sign), cut to the
-  // 10 fraction bits FP16 keeps, are exactly representable in FP16's normal
-  // range (the conversion is then exact); below 2^-14 (|f/w - rho0| <
-  // 2^-14-s) FP16 keeps fewer bits and the conversion rounds the rest to
-  // nearest
+  // stochastic rounding with the random word r (top 13 bits used)
   __device__ static T enc(R v, float k, unsigned r) {
 #pragma clang fp contract(off)
-    const unsigned u = __float_as_uint(v * k);
-    return (_Float16)__uint_as_float((u + (r >> 19)) & 0xffffe000u);
+    const float x = v * k;
+    h16x2 o = {};
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, x, r, false);
+    return o[0];
+  }
+  // a value the collision already produced in storage units, (f/w - rho0) 2^s
+  __device__ static T keep(R x, unsigned r) {
+    h16x2 o = {};
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, x, r, false);
+    return o[0];
+  }
+  // the same into a packed pair: with fresh, the low half starts a new word
+  // (the high half follows); otherwise the other half is kept
+  __device__ static void keep_into(unsigned& word, bool hi, R x, unsigned r, bool fresh) {
+    if (hi || !fresh) {
+      h16x2 o = __builtin_bit_cast(h16x2, word);
+      o = hi ? __builtin_amdgcn_cvt_sr_f16_f32(o, x, r, true)
+             : __builtin_amdgcn_cvt_sr_f16_f32(o, x, r, false);
+      word = __builtin_bit_cast(unsigned, o);
+    } else {
+      h16x2 o = {};
+      o = __builtin_amdgcn_cvt_sr_f16_f32(o, x, r, false);
+      word = __builtin_bit_cast(unsigned, o);
+    }
   }
 };
 
@@ -438,13 +463,19 @@ __host__ __device__ constexpr void mrt_forward(const R d[Q], R m[Q]) {
 }
 
 // Back transform of moments already divided by b_k: d_i = w_i sum_k e_k(c_i) M_k.
-// GZ: the nine ghost moments are zero (not read).
-template <typename R, bool GZ, bool CW = false>
-__host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q]) {
+// GZ: the nine ghost moments are zero (not read).  WS: d_i / w_i scaled by sc
+// (the FP16 storage units) instead: the weights of the transform and the
+// storage's 1/w_i cancel, and the stored value needs no product of its own.
+template <typename R, bool GZ, bool CW = false, bool WS = false>
+__host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q], R sc = R(1)) {
+  auto wout = [&](int c, R x) -> R {
+    if constexpr (WS) return x * sc;
+    else return wmul<R, CW>(c, x);
+  };
   const R g10 = GZ ? R(0) : M[10], g11 = GZ ? R(0) : M[11], g12 = GZ ? R(0) : M[12];
   const R g13 = GZ ? R(0) : M[13], g14 = GZ ? R(0) : M[14], g15 = GZ ? R(0) : M[15];
   const R g16 = GZ ? R(0) : M[16], g17 = GZ ? R(0) : M[17], g18 = GZ ? R(0) : M[18];
-  d[0] = wmul<R, CW>(0, M[0] - M[4] + g16);
+  d[0] = wout(0, M[0] - M[4] + g16);
   const R E1 = M[0] + (M[5] + M[5]) - (g16 + g16) - (g17 + g17);
   const R O1 = M[1] - (g10 + g10);
   const R E2 = M[0] - M[5] + M[6] - (g16 + g16) + g17 - g18;
@@ -465,24 +496,24 @@ __host__ __device__ constexpr void mrt_backward(const R M[Q], R d[Q]) {
   const R O7 = x10 - z12 - g13 - g15;
   const R O8 = y11 + z12 + g14 - g15;
   const R O9 = y11 - z12 + g14 + g15;
-  d[1] = wmul<R, CW>(1, E1 + O1);
-  d[2] = wmul<R, CW>(1, E1 - O1);
-  d[3] = wmul<R, CW>(1, E2 + O2);
-  d[4] = wmul<R, CW>(1, E2 - O2);
-  d[5] = wmul<R, CW>(1, E3 + O3);
-  d[6] = wmul<R, CW>(1, E3 - O3);
-  d[7] = wmul<R, CW>(2, E4 + O4);
-  d[8] = wmul<R, CW>(2, E4 - O4);
-  d[9] = wmul<R, CW>(2, E5 + O5);
-  d[10] = wmul<R, CW>(2, E5 - O5);
-  d[11] = wmul<R, CW>(2, E6 + O6);
-  d[12] = wmul<R, CW>(2, E6 - O6);
-  d[13] = wmul<R, CW>(2, E7 + O7);
-  d[14] = wmul<R, CW>(2, E7 - O7);
-  d[15] = wmul<R, CW>(2, E8 + O8);
-  d[16] = wmul<R, CW>(2, E8 - O8);
-  d[17] = wmul<R, CW>(2, E9 + O9);
-  d[18] = wmul<R, CW>(2, E9 - O9);
+  d[1] = wout(1, E1 + O1);
+  d[2] = wout(1, E1 - O1);
+  d[3] = wout(1, E2 + O2);
+  d[4] = wout(1, E2 - O2);
+  d[5] = wout(1, E3 + O3);
+  d[6] = wout(1, E3 - O3);
+  d[7] = wout(2, E4 + O4);
+  d[8] = wout(2, E4 - O4);
+  d[9] = wout(2, E5 + O5);
+  d[10] = wout(2, E5 - O5);
+  d[11] = wout(2, E6 + O6);
+  d[12] = wout(2, E6 - O6);
+  d[13] = wout(2, E7 + O7);
+  d[14] = wout(2, E7 - O7);
+  d[15] = wout(2, E8 + O8);
+  d[16] = wout(2, E8 - O8);
+  d[17] = wout(2, E9 + O9);
+  d[18] = wout(2, E9 - O9);
 }
 
 __host__ __device__ constexpr bool pair_forward_matches_basis() {
@@ -517,10 +548,10 @@ static_assert(pair_backward_matches_basis(), "pair-form back transform != basis"
 // mode k >= 4 gains sqrt(mu rho b_k (1 - gamma_k^2)) r_k, which keeps its
 // fluctuations at the equilibrium variance mu rho b_k (mu = 3 kT); the ghosts
 // are then formed whatever GZ says.
-template <typename R, bool GZ, bool NOISE = false, bool CW = false>
+template <typename R, bool GZ, bool NOISE = false, bool CW = false, bool WS = false>
 __device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rho0, R omega,
                                                   R om_bulk, R om_ghost,
-                                                  const Ext<R>* ext = nullptr) {
+                                                  const Ext<R>* ext = nullptr, R sc = R(1)) {
   R m[Q];
   mrt_forward<R>(d, m);
   const R drho = m[0];
@@ -577,14 +608,14 @@ __device__ __forceinline__ void collide_mrt_pairs(R d[Q], R gx, R gy, R gz, R rh
     for (int k = 5; k < 10; k++) M[k] += as * r[k - 4] * (R)sqrt(INVB[k]);
 #pragma unroll
     for (int k = 10; k < Q; k++) M[k] += ag * r[k - 4] * (R)sqrt(INVB[k]);
-    mrt_backward<R, false, CW>(M, d);
+    mrt_backward<R, false, CW, WS>(M, d, sc);
   } else {
     if (!GZ) {
       const R gg = (R)1 - om_ghost;
 #pragma unroll
       for (int k = 10; k < Q; k++) M[k] = gg * m[k] * (R)INVB[k];
     }
-    mrt_backward<R, GZ, CW>(M, d);
+    mrt_backward<R, GZ, CW, WS>(M, d, sc);
   }
 }
 

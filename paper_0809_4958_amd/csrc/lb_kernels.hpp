@@ -568,12 +568,22 @@ struct LbArgs {
 
 // Collision dispatcher: 0 BGK, 1 MRT, 2 MRT with ghost rate 1.  CW: the
 // lattice weights applied with their FP32 residual (FP32 storage).
-template <typename R, int COLL, bool CW = false>
+// WS: the post-collision values come out in FP16 storage units,
+// d_i 2^s / w_i with 2^s = sc (the MRT back transform then applies no weights)
+template <typename R, int COLL, bool CW = false, bool WS = false>
 __device__ __forceinline__ void collide_any(R d[Q], R gx, R gy, R gz, R rho0, R omega, R omb,
-                                            R omg) {
-  if (COLL == 0) collide<R, 0, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
-  else if (COLL == 1) collide_mrt_pairs<R, false, false, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
-  else collide_mrt_pairs<R, true, false, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
+                                            R omg, R sc = R(1)) {
+  if (COLL == 0) {
+    collide<R, 0, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
+    if constexpr (WS) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) d[i] *= sc * (R)(WCLS[i] == 0 ? 3 : (WCLS[i] == 1 ? 18 : 36));
+    }
+  } else if (COLL == 1) {
+    collide_mrt_pairs<R, false, false, CW, WS>(d, gx, gy, gz, rho0, omega, omb, omg, nullptr, sc);
+  } else {
+    collide_mrt_pairs<R, true, false, CW, WS>(d, gx, gy, gz, rho0, omega, omb, omg, nullptr, sc);
+  }
 }
 
 // whether the step of storage S applies the weights with their residual
@@ -623,9 +633,9 @@ __device__ __forceinline__ Ext<R> make_ext(const LbArgs& A, const BoxDesc& b, lo
 // Collision with the extensions: the force density of the chains g plus the
 // body force -rho a (rho the node's pre-collision density), and the
 // fluctuating collision when mu > 0 (MRT only).
-template <typename R, int COLL, bool CW = false>
+template <typename R, int COLL, bool CW = false, bool WS = false>
 __device__ __forceinline__ void collide_ext(R d[Q], R gx, R gy, R gz, R rho0, R omega, R omb,
-                                            R omg, const Ext<R>& e) {
+                                            R omg, const Ext<R>& e, R sc = R(1)) {
   R drho = 0;
 #pragma unroll
   for (int i = 0; i < Q; i++) drho += d[i];
@@ -634,9 +644,9 @@ __device__ __forceinline__ void collide_ext(R d[Q], R gx, R gy, R gz, R rho0, R 
   gy -= rho * e.ay;
   gz -= rho * e.az;
   if (COLL != 0 && e.mu > (R)0)
-    collide_mrt_pairs<R, COLL == 2, true, CW>(d, gx, gy, gz, rho0, omega, omb, omg, &e);
+    collide_mrt_pairs<R, COLL == 2, true, CW, WS>(d, gx, gy, gz, rho0, omega, omb, omg, &e, sc);
   else
-    collide_any<R, COLL, CW>(d, gx, gy, gz, rho0, omega, omb, omg);
+    collide_any<R, COLL, CW, WS>(d, gx, gy, gz, rho0, omega, omb, omg, sc);
 }
 
 // Spread force g(x) = - sum_j w_jx dP_j at node (x, y, z): chains whose stencil
@@ -712,7 +722,7 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
     doff[i] = (unsigned)i * nx * SB;
   }
   const float dc0 = b.dec[0], dc1 = b.dec[1], dc2 = b.dec[2];
-  const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
+  const R sc = (R)b.s2;
   const int plane = it.ex * it.ey;
   Ext<R> ext{};
   if constexpr (EXT) ext = make_ext<R>(A, b, step);
@@ -732,15 +742,14 @@ __device__ __forceinline__ void tile_fast(const LbArgs& A, const BoxDesc& b, con
       }
       if constexpr (EXT) {
         ext.node = ((unsigned)z * ny + (unsigned)y) * nx + (unsigned)x;
-        collide_ext<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>(), S == 2>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext, sc);
       } else {
-        collide_any<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>(), S == 2>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, sc);
       }
       const unsigned hn = dither_node(((unsigned)z * ny + (unsigned)y) * nx + (unsigned)x, (unsigned)step);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
-        const float k = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-        *(T*)(d0 + (voff + doff[i])) = St::enc(d[i], k, dither_pop(hn, i));
+        *(T*)(d0 + (voff + doff[i])) = St::keep(d[i], dither_pop(hn, i));
       }
     }
   }
@@ -843,6 +852,31 @@ __device__ __forceinline__ typename Store<S>::T velem(const unsigned (&w)[W], un
   }
 }
 
+// Encode a value into element e of a lane vector: FP16 rounds stochastically
+// straight into its half of the packed word, the other half kept (the x-face
+// node of a row overwrites an element after its neighbour's).
+template <int S, int W>
+__device__ __forceinline__ void vput_enc(unsigned (&w)[W], int e, typename Store<S>::R v, float k,
+                                         unsigned r) {
+  if constexpr (S == 2) {
+#pragma clang fp contract(off)
+    Store<2>::keep_into(w[e >> 1], (e & 1) != 0, v * k, r, false);
+  } else {
+    w[e] = __builtin_bit_cast(unsigned, Store<S>::enc(v, k, r));
+  }
+}
+// the same for a value already in storage units (collide_any with WS), the
+// elements written in order (element 2j starts word j)
+template <int S, int W>
+__device__ __forceinline__ void vput_keep(unsigned (&w)[W], int e, typename Store<S>::R x,
+                                          unsigned r) {
+  if constexpr (S == 2) {
+    Store<2>::keep_into(w[e >> 1], (e & 1) != 0, x, r, true);
+  } else {
+    w[e] = __builtin_bit_cast(unsigned, Store<S>::keep(x, r));
+  }
+}
+
 template <int S, int W>
 __device__ __forceinline__ void vput(unsigned (&w)[W], int e, typename Store<S>::T val) {
   using T = typename Store<S>::T;
@@ -879,6 +913,7 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
   const int q_end = it.x0 + it.ex;
   const float dc0 = b.dec[0], dc1 = b.dec[1], dc2 = b.dec[2];
   const float ec0 = b.enc[0], ec1 = b.enc[1], ec2 = b.enc[2];
+  const R sc = (R)b.s2;
   const int lane = (int)(threadIdx.x & 63);
   const unsigned lane_l = (unsigned)(lane - 1) & 63u, lane_r = (unsigned)(lane + 1) & 63u;
   // population i of the node sits at vo[c_y] + soff(i) from the iteration's
@@ -977,16 +1012,16 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
       const int x = x0 + k;
       if constexpr (EXT) {
         ext.node = ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
-        collide_ext<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>(), S == 2>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, ext, sc);
       } else {
-        collide_any<R, COLL, comp_weights<S>()>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>(), S == 2>(d, (R)0, (R)0, (R)0, rho0, omega, omb, omg, sc);
       }
       const unsigned hn =
           dither_node(((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x, (unsigned)step);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-        vput<S, W>(out[i], k, St::enc(d[i], ke, dither_pop(hn, i)));
+        vput_keep<S, W>(out[i], k, d[i], dither_pop(hn, i));
       }
     }
     // x-face nodes of this row: boundary equilibrium at t_n (faces -x, +x)
@@ -1001,13 +1036,13 @@ __device__ __forceinline__ void tile_rows(const LbArgs& A, const BoxDesc& b, con
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-          vput<S, W>(out[i], 0, St::enc(eq[i], ke, dither_pop(hx, i)));
+          vput_enc<S, W>(out[i], 0, eq[i], ke, dither_pop(hx, i));
         }
       } else {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
           const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-          vput<S, W>(out[i], V - 1, St::enc(eq[i], ke, dither_pop(hx, i)));
+          vput_enc<S, W>(out[i], V - 1, eq[i], ke, dither_pop(hx, i));
         }
       }
     }
@@ -1073,7 +1108,7 @@ __device__ __forceinline__ void face_rows(const BoxDesc& b, const Item& it,
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const float ke = WCLS[i] == 0 ? ec0 : (WCLS[i] == 1 ? ec1 : ec2);
-        vput<S, W>(out[i], k, St::enc(eq[i], ke, dither_pop(hn, i)));
+        vput_enc<S, W>(out[i], k, eq[i], ke, dither_pop(hn, i));
       }
     }
     char* row = (char*)dst + (long long)z * psb + (long long)(y >> yl) * bkb + (long long)(y & ym) * nxb +
@@ -1108,6 +1143,7 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
   using St = Store<S>;
   using R = typename St::R;
   const int plane = it.ex * it.ey;
+  const R sc = (R)b.s2;
   Ext<R> ext{};
   if constexpr (EXT) ext = make_ext<R>(A, b, step);
 #pragma unroll 1
@@ -1122,15 +1158,15 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
       if (cmask) gather_force<R, PER, 1>(A, b, cmask, x, y, z, gx, gy, gz);
       if constexpr (EXT) {
         ext.node = (unsigned)(((int64_t)z * b.ny + y) * b.nx + x);
-        collide_ext<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>(), S == 2>(d, gx, gy, gz, rho0, omega, omb, omg, ext, sc);
       } else {
-        collide_any<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>(), S == 2>(d, gx, gy, gz, rho0, omega, omb, omg, sc);
       }
       const unsigned hn = dither_node((unsigned)(((int64_t)z * b.ny + y) * b.nx + x), (unsigned)step);
       if (aa && !(step & 1)) {
 #pragma unroll
         for (int i = 0; i < Q; i++)
-          dst[aidx(b, OPP[i], x, y, z)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
+          dst[aidx(b, OPP[i], x, y, z)] = St::keep(d[i], dither_pop(hn, i));
       } else if (aa) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
@@ -1140,12 +1176,12 @@ __device__ __forceinline__ void tile_generic(const LbArgs& A, const BoxDesc& b, 
             if (b.pmask & 2) ty = wrapc(ty, b.ny);
             if (b.pmask & 4) tz = wrapc(tz, b.nz);
           }
-          dst[aidx(b, i, tx, ty, tz)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
+          dst[aidx(b, i, tx, ty, tz)] = St::keep(d[i], dither_pop(hn, i));
         }
       } else {
 #pragma unroll
         for (int i = 0; i < Q; i++)
-          dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
+          dst[aidx(b, i, x, y, z)] = St::keep(d[i], dither_pop(hn, i));
       }
     }
   }
@@ -1325,6 +1361,7 @@ __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
     const T* __restrict__ src = (const T*)(par ? A.a1 : A.a0) + b.off;
     T* __restrict__ dst = (T*)(par ? A.a0 : A.a1) + b.off;
     const R rho0 = (R)A.rho0, omega = (R)A.omega, omb = (R)A.om_bulk, omg = (R)A.om_ghost;
+    const R sc = (R)b.s2;
     const unsigned long long all =
         b.chain_count >= MAX_BOX_CHAINS ? ~0ull : (1ull << b.chain_count) - 1ull;
     const int lx = bb[3] - bb[0] + 1, ly = bb[4] - bb[1] + 1, lz = bb[5] - bb[2] + 1;
@@ -1341,14 +1378,14 @@ __global__ __launch_bounds__(WG) void k_force(LbArgs A) {
         // the same body force and noise k_lb gave the node (same counter)
         Ext<R> ext = make_ext<R>(A, b, step);
         ext.node = (unsigned)(((int64_t)z * b.ny + y) * b.nx + x);
-        collide_ext<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg, ext);
+        collide_ext<R, COLL, comp_weights<S>(), S == 2>(d, gx, gy, gz, rho0, omega, omb, omg, ext, sc);
       } else {
-        collide_any<R, COLL, comp_weights<S>()>(d, gx, gy, gz, rho0, omega, omb, omg);
+        collide_any<R, COLL, comp_weights<S>(), S == 2>(d, gx, gy, gz, rho0, omega, omb, omg, sc);
       }
       const unsigned hn = dither_node((unsigned)(((int64_t)z * b.ny + y) * b.nx + x), (unsigned)step);
 #pragma unroll
       for (int i = 0; i < Q; i++)
-        dst[aidx(b, i, x, y, z)] = St::enc(d[i], b.enc[WCLS[i]], dither_pop(hn, i));
+        dst[aidx(b, i, x, y, z)] = St::keep(d[i], dither_pop(hn, i));
     }
   }
   // On steps without a check pass (advance set) the last workgroup to take a

@@ -616,6 +616,7 @@ lb_status upload_boxes(lb_ctx* ctx) {
       d.enc[c] = (float)(s2 / WD[c]);
       d.dec[c] = (float)(WD[c] / s2);
     }
+    d.s2 = (float)s2;
     d.interior = (double)b.interior;
     d.fast = (!ctx->aa && b.dim.periodic_mask == 0 &&
               (double)Q * (double)b.nn * (double)store_bytes(ctx->S) < 4294967296.0) ? 1 : 0;
