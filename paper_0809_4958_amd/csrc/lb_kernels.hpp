@@ -115,7 +115,7 @@ __device__ __forceinline__ void xface_wave(const BoxDesc* __restrict__ boxes,
 // step instead (CB / 64 work items each), so the two independent pieces of
 // work before the fused step share one launch and run side by side.
 template <int S, bool PER, int CB, bool TH = false>
-__global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
+__global__ __launch_bounds__(CB, 3) void k_chain(const BoxDesc* __restrict__ boxes,
                                               const ChainDesc* __restrict__ chains,
                                               const typename Store<S>::T* __restrict__ a0,
                                               const typename Store<S>::T* __restrict__ a1,
@@ -209,9 +209,10 @@ __global__ __launch_bounds__(CB) void k_chain(const BoxDesc* __restrict__ boxes,
 
   // fluid velocity at the bead: sum over the 8 corners of weight x j/rho, in
   // corner order, four corners at a time (their loads in flight together).
-  // All eight at once took 214 VGPRs; four keep the kernel at 158, so the
-  // x-face waves that share its launch run three per SIMD instead of two
-  // (27.6 instead of 30.2 us for the launch on the batch).
+  // All eight at once took 214 VGPRs.  The kernel is compiled for three
+  // waves per SIMD (168 VGPRs with the FP64 chain arithmetic, a few spilled),
+  // so that the x-face waves sharing its launch run three per SIMD, not two
+  // (measured 27.6 against 30.2 us for the launch on the batch).
   R ux = 0, uy = 0, uz = 0;
   if (act) {
 #pragma unroll 1

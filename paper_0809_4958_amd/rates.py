@@ -10,6 +10,11 @@ Workloads (MRT tau = 0.6, KS tracer boundary sampled on 17 x 17 faces every
 
   batch-f32     the 256-box batch (edges from {32, 48, 64, 96}, one 32-bead
                 chain each) with FP32 storage
+  batch-f16-extended
+                the batch with FP16 storage whose chains are random walks
+                of bond 0.8 (spring constant 0.003) instead of collapsed
+                coils: stencil boxes of 5-9 nodes per axis, the force pass's
+                heavy case
   large-f16     512^3, FP16 storage, 32 chains of 256 beads (two buffers)
   large-f16-aa  the same on one buffer updated in place
   single-f32    128^3, FP32 storage, one 64-bead chain
@@ -43,14 +48,26 @@ def _chains_big(n, config_idx=4):
 
 def build(lbm, workload, steps, graph_steps):
     """Context of a workload and its interior node count."""
-    if workload == "batch-f32":
+    if workload in ("batch-f32", "batch-f16-extended"):
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         if root not in sys.path:
             sys.path.insert(0, root)
         import bench
         boxes = bench.batch_inputs(256, steps, TAU)
-        ctx = bench.make_ctx(lbm, boxes, lbm.STORE_F32, TAU, reduce_every=100,
-                             graph_steps=graph_steps)
+        if workload == "batch-f32":
+            ctx = bench.make_ctx(lbm, boxes, lbm.STORE_F32, TAU, reduce_every=100,
+                                 graph_steps=graph_steps)
+            return ctx, float(sum((b["n"] - 2) ** 3 for b in boxes)), True
+        ctx = lbm.Context([(b["n"],) * 3 for b in boxes], collision=lbm.MRT, tau=TAU, tau_bulk=TAU,
+                          ghost_rate=1.0, storage=lbm.STORE_F16DEV, reduce_every=100,
+                          torch_alloc=True, graph_steps=graph_steps)
+        for k, b in enumerate(boxes):
+            ctx.set_initial(k, b["u0"])
+            ctx.set_boundary(k, lbm.BC_SAMPLED, b["faces"], t0=0, dt=20, res=b["faces"].shape[2])
+            pos, _ = inputs.chain_init(len(b["pos"]), b["anchor"], inputs.rng(6, k), bond=0.8)
+            ctx.couple_chain(k, pos, None, substeps=10, fix_com=True, zeta=5.0,
+                             mass=bench.bead_mass(len(pos)), fene_k=0.003, fene_r0=2.0,
+                             anchor=b["anchor"])
         return ctx, float(sum((b["n"] - 2) ** 3 for b in boxes)), True
     if workload in ("large-f16", "large-f16-aa"):
         n, storage, chains = 512, lbm.STORE_F16DEV, _chains_big(512)
