@@ -68,9 +68,13 @@ typedef struct lb_ctx lb_ctx; /* opaque; owns all device memory */
 typedef enum { LB_BGK = 0, LB_MRT = 1 } lb_collision;
 
 /* Population storage.  Collisions are computed in FP64 for LB_STORE_F64 and in
- * FP32 otherwise, always on deviations from rest equilibrium d_i = f_i - w_i rho0.
- * LB_STORE_F16DEV stores h_i = (f_i/w_i - rho0) * 2^s as IEEE half (round to
- * nearest even), s = lb_config.fp16_exp. */
+ * FP32 otherwise, always on deviations from rest equilibrium d_i = f_i - w_i rho0;
+ * the chains (bead state, impulses, spreading weights, gathered force) in FP64
+ * for every storage.  LB_STORE_F16DEV stores h_i = (f_i/w_i - rho0) * 2^s as
+ * IEEE half, s = lb_config.fp16_exp: the step rounds stochastically (up with
+ * probability equal to the fraction of an ulp; the random bits come from a
+ * counter of node, step and direction, so runs are reproducible), state uploads
+ * round to nearest even. */
 typedef enum { LB_STORE_F64 = 0, LB_STORE_F32 = 1, LB_STORE_F16DEV = 2 } lb_storage;
 
 /* Streaming.  LB_STREAM_AB: two population buffers, each step pulls from one
