@@ -49,9 +49,8 @@ struct lbn_ctx {
   int adam_t = 0;
   // activations for max_batch samples
   __bf16 *x0 = nullptr, *a1 = nullptr, *a2 = nullptr, *dy = nullptr, *dz1 = nullptr, *dz2 = nullptr;
-  float *r = nullptr, *base = nullptr, *scale = nullptr, *part = nullptr, *part_b = nullptr;
+  float *r = nullptr, *base = nullptr, *scale = nullptr, *part = nullptr;
   float* part_seg = nullptr;
-  float *wcoarse = nullptr, *wtheta = nullptr;
   double* loss_part = nullptr;
   int last_batch = 0;
   std::vector<void*> owned;
@@ -141,14 +140,13 @@ void dev_to_params(const std::vector<float>& dev, float* out) {
 
 lb_status prep_weights(lbn_ctx* ctx) {
   if (!ctx->weights_dirty) return LB_OK;
-  auto prep = [&](size_t off, int co_n, int ci_n, __bf16* wf, __bf16* wt) {
-    const int n = NTAP * co_n * ci_n;
-    hipLaunchKernelGGL(k_prep_weights, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->p + off, co_n,
-                       ci_n, wf, wt);
-  };
-  prep(OFF_W1, CH, CIN, ctx->w1f, ctx->w1t);
-  prep(OFF_W2, CH, CH, ctx->w2f, ctx->w2t);
-  prep(OFF_W3, COUT, CH, ctx->w3f, ctx->w3t);
+  const PrepLayers L{{ctx->p + OFF_W1, ctx->p + OFF_W2, ctx->p + OFF_W3},
+                     {ctx->w1f, ctx->w2f, ctx->w3f},
+                     {ctx->w1t, ctx->w2t, ctx->w3t},
+                     {CH, CH, COUT},
+                     {CIN, CH, CH}};
+  const int n = (int)(W1N + W2N + W3N);
+  hipLaunchKernelGGL(k_prep_weights, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, L);
   HIPCHK(hipGetLastError());
   ctx->weights_dirty = false;
   return LB_OK;
@@ -157,20 +155,27 @@ lb_status prep_weights(lbn_ctx* ctx) {
 // persistent convolution grid: per_cu workgroups per compute unit (by LDS use)
 int conv_grid(int n_tiles, int per_cu) { return std::min(n_tiles, 256 * per_cu); }
 
-lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int batch) {
+// win.samples != NULL: the window path (inputs gathered by the lift, the
+// face field written by the last layer into u_out; r is not kept)
+lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int batch,
+                  LiftWindow win = LiftWindow{nullptr, 0, 0, 1}, float* u_out = nullptr) {
   lb_status s = prep_weights(ctx);
   if (s) return s;
   const int tiles = batch * (IMG / TR);
   hipStream_t st = ctx->stream;
   const int R = ctx->cfg.coarse;
-  hipLaunchKernelGGL(k_lift, dim3(batch, LIFT_SLICES), dim3(NB), 12 * R * R * sizeof(float), st, coarse, theta, R, ctx->x0,
-                     ctx->base, ctx->scale);
+  hipLaunchKernelGGL(k_lift, dim3(batch, LIFT_SLICES), dim3(NB), 24 * R * R * sizeof(float), st, coarse, theta, R, ctx->x0,
+                     ctx->base, ctx->scale, win);
   hipLaunchKernelGGL((k_conv<CIN, CH, 0>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->x0, ctx->w1f,
                      ctx->p + OFF_B1, nullptr, (void*)ctx->a1, tiles);
   hipLaunchKernelGGL((k_conv<CH, CH, 0>), dim3(conv_grid(tiles, 1)), dim3(NBC), 0, st, ctx->a1, ctx->w2f,
                      ctx->p + OFF_B2, nullptr, (void*)ctx->a2, tiles);
-  hipLaunchKernelGGL((k_conv<CH, COUT, 1>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->a2, ctx->w3f,
-                     ctx->p + OFF_B3, nullptr, (void*)ctx->r, tiles);
+  if (u_out)
+    hipLaunchKernelGGL((k_conv<CH, COUT, 3>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->a2, ctx->w3f,
+                       ctx->p + OFF_B3, nullptr, (void*)u_out, tiles, ctx->base, ctx->scale);
+  else
+    hipLaunchKernelGGL((k_conv<CH, COUT, 1>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->a2, ctx->w3f,
+                       ctx->p + OFF_B3, nullptr, (void*)ctx->r, tiles);
   HIPCHK(hipGetLastError());
   ctx->last_batch = batch;
   return LB_OK;
@@ -182,14 +187,16 @@ lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size
   const int rows = batch * IMG;
   const int grid = std::min(rows, MAX_PART);
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NBC), 0, st, x, dz, ctx->part, ctx->part_b, rows);
-  // two fixed-order stages: RSEG ranges of partials in parallel, then their sum
-  const int nw = NTAP * CO * CI;
+  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NBC), 0, st, x, dz, ctx->part, rows);
+  // two fixed-order stages: RSEG ranges of partials in parallel, then their
+  // sum; weights and biases together (the biases follow the weights, in the
+  // partials as in the parameters)
+  const int nw = NTAP * CO * CI + CO;
+  (void)off_b;  // == off_w + 9 CO CI
   hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, nw,
                      ctx->part_seg);
   hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256), dim3(256), 0, st, ctx->part_seg, RSEG, nw,
                      ctx->g + off_w);
-  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, ctx->part_b, grid, CO, ctx->g + off_b);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
@@ -234,11 +241,8 @@ lb_status lbn_init(const lbn_config* cfg, lbn_ctx** out) {
   ctx->r = dalloc_t<float>(ctx, px * COUT, &ok);
   ctx->base = dalloc_t<float>(ctx, px * 3, &ok);
   ctx->scale = dalloc_t<float>(ctx, B, &ok);
-  ctx->part = dalloc_t<float>(ctx, (size_t)MAX_PART * NTAP * CH * CH, &ok);
-  ctx->part_b = dalloc_t<float>(ctx, (size_t)MAX_PART * CH, &ok);
-  ctx->part_seg = dalloc_t<float>(ctx, (size_t)RSEG * NTAP * CH * CH, &ok);
-  ctx->wcoarse = dalloc_t<float>(ctx, B * 12 * cfg->coarse * cfg->coarse, &ok);
-  ctx->wtheta = dalloc_t<float>(ctx, B, &ok);
+  ctx->part = dalloc_t<float>(ctx, (size_t)MAX_PART * (NTAP * CH * CH + CH), &ok);
+  ctx->part_seg = dalloc_t<float>(ctx, (size_t)RSEG * (NTAP * CH * CH + CH), &ok);
   ctx->loss_part = dalloc_t<double>(ctx, 1024, &ok);
   if (!ok) {
     lbn_free(ctx);
@@ -304,11 +308,7 @@ lb_status lbn_window_forward(lbn_ctx* ctx, const float* samples_dev, int32_t n_s
   if (!samples_dev || !ring_dev) return fail(ctx, LB_ERR_ARG, "null pointer");
   if (dt < 1 || 6 * dt > ctx->cfg.max_batch) return fail(ctx, LB_ERR_ARG, "6 dt must not exceed max_batch");
   if (n_samples < 2 || k < 0 || k >= n_samples - 1) return fail(ctx, LB_ERR_ARG, "window outside the history");
-  const int R = ctx->cfg.coarse;
-  hipLaunchKernelGGL(k_gather_window, dim3(6 * dt), dim3(256), 0, ctx->stream, samples_dev, n_samples, R, k, dt,
-                     ctx->wcoarse, ctx->wtheta);
-  HIPCHK(hipGetLastError());
-  return lbn_forward(ctx, ctx->wcoarse, ctx->wtheta, 6 * dt, ring_dev);
+  return forward(ctx, nullptr, nullptr, 6 * dt, LiftWindow{samples_dev, n_samples, k, dt}, ring_dev);
 }
 
 lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* theta_dev,

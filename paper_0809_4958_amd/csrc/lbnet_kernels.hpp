@@ -57,18 +57,42 @@ __device__ __forceinline__ float from_bf16(__bf16 v) { return (float)v; }
 // One workgroup per sample.  coarse [B][4][3][R][R] (row v, column u),
 // theta [B]; writes x0 [B][64][64][16] bf16, base [B][64][64][3] and s [B].
 // The coarse feature grids (Sb, Duu Sb, Dvv Sb, temporal difference) are
-// formed in LDS first (R <= 64).
+// formed in LDS first (R <= 32).
+// Window mode (win.samples != NULL): the inputs of window k of a box's
+// sampled face history [ns][6][R][R][3] are read from it directly: sample
+// b = j * 6 + f (step t_k + j, face f) takes coarse[b][tau][c][v][u] =
+// samples[clamp(k - 1 + tau)][f][v][u][c] and theta = j / dt.
+struct LiftWindow {
+  const float* samples;
+  int ns, k, dt;
+};
+
 __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
                                              const float* __restrict__ theta, int R,
                                              __bf16* __restrict__ x0, float* __restrict__ base,
-                                             float* __restrict__ scale) {
+                                             float* __restrict__ scale, LiftWindow win) {
   // workgroup (b, slice): rows slice * IMG / gridDim.y ... of image b; every
   // slice recomputes the image's (few) coarse features
   const int b = blockIdx.x, tid = threadIdx.x;
-  const float* c = coarse + (size_t)b * 12 * R * R;
   const int RR = R * R;
   __shared__ double red[NB];
-  extern __shared__ float feat[];  // [12][R][R]: Sb, Duu Sb, Dvv Sb, temporal difference
+  extern __shared__ float dyn[];
+  float* cin = dyn;                // the sample's coarse values [4][3][R][R]
+  float* feat = dyn + 12 * RR;     // [12][R][R]: Sb, Duu Sb, Dvv Sb, temporal difference
+  for (int i = tid; i < 12 * RR; i += NB) {
+    if (win.samples) {
+      const int j = b / 6, f = b - 6 * j;
+      const int tau = i / (3 * RR), rem = i - tau * 3 * RR;
+      const int cc = rem / RR, vu = rem - cc * RR;
+      int ks = win.k - 1 + tau;
+      ks = ks < 0 ? 0 : (ks > win.ns - 1 ? win.ns - 1 : ks);
+      cin[i] = win.samples[(((size_t)ks * 6 + f) * RR + vu) * 3 + cc];
+    } else {
+      cin[i] = coarse[(size_t)b * 12 * RR + i];
+    }
+  }
+  __syncthreads();
+  const float* c = cin;
   double ss = 0.0;
   for (int i = tid; i < 12 * RR; i += NB) ss += (double)c[i] * (double)c[i];
   red[tid] = ss;
@@ -80,7 +104,7 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
   const double rms = sqrt(red[0] / (12.0 * RR));
   const float s = rms > 0.0 ? (float)rms : 1.0f;
   if (tid == 0 && blockIdx.y == 0) scale[b] = s;
-  const float th = theta[b];
+  const float th = win.samples ? (float)(b / 6) / (float)win.dt : theta[b];
   // Sb and the temporal difference
   for (int i = tid; i < 3 * RR; i += NB) {
     const int cmp = i / RR, vu = i - cmp * RR;
@@ -140,14 +164,18 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
 // ---------------------------------------------------------------- conv
 // Implicit-GEMM 3x3 convolution over tiles of TR image rows.  EPI: 0 = bias +
 // ReLU -> bf16; 1 = bias -> fp32 (last layer, all CO channels); 2 = no bias,
-// times the mask (mask_src > 0) -> bf16 (backward data through a ReLU).
+// times the mask (mask_src > 0) -> bf16 (backward data through a ReLU);
+// 3 = the face field u = base + s r of output channels 0..2 -> fp32
+// [B][64][64][3] (last layer, inference).
 // Persistent: workgroup g handles tiles g, g + gridDim.x, ...; eight waves
 // share one LDS copy of the weights, each computes 32 pixels x CO.
 template <int CI, int CO, int EPI>
 __global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
                                               const float* __restrict__ bias,
                                               const __bf16* __restrict__ mask_src,
-                                              void* __restrict__ out, int n_tiles) {
+                                              void* __restrict__ out, int n_tiles,
+                                              const float* __restrict__ base = nullptr,
+                                              const float* __restrict__ scale = nullptr) {
   constexpr int CP = CI + 8;                  // padded channel stride in LDS
   constexpr int KCH = (NTAP * CI + 31) / 32;  // K chunks of 32
   constexpr int NBK = CO / 16;                // 16-column blocks
@@ -241,6 +269,12 @@ __global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, cons
             ((__bf16*)out)[o] = to_bf16(v > 0.0f ? v : 0.0f);
           } else if (EPI == 1) {
             ((float*)out)[o] = v + bias[co];
+          } else if (EPI == 3) {
+            if (co < 3) {
+              const size_t q = ((size_t)b * IMG + y) * IMG + px;
+              const float rv = v + bias[co];
+              ((float*)out)[q * 3 + co] = base[q * 3 + co] + scale[b] * rv;
+            }
           } else {
             ((__bf16*)out)[o] = to_bf16(from_bf16(mask_src[o]) > 0.0f ? v : 0.0f);
           }
@@ -252,12 +286,11 @@ __global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, cons
 // ---------------------------------------------------------------- weight gradient
 // dW[tap][co][ci] = sum_p dz[p][co] x[p + off(tap)][ci], db[co] = sum_p dz[p][co]
 // over the image rows g, g + gridDim.x, ... of workgroup g; one partial per
-// workgroup (part[g][9][CO][CI], part_b[g][CO]), summed in a fixed order by
-// k_reduce_parts.
+// workgroup, part[g][9 CO CI + CO] (the weights, then the biases: the layout
+// of the layer's parameters), summed in a fixed order by k_reduce_parts.
 template <int CI, int CO>
 __global__ __launch_bounds__(NBC) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
-                                              float* __restrict__ part, float* __restrict__ part_b,
-                                              int n_rows) {
+                                              float* __restrict__ part, int n_rows) {
   constexpr int PP = IMG + 8;                       // padded pixel stride
   constexpr int TILES = NTAP * (CO / 16) * (CI / 16);
   constexpr int NW = NBC / 64;                      // waves
@@ -352,7 +385,7 @@ __global__ __launch_bounds__(NBC) void k_wgrad(const __bf16* __restrict__ x, con
       }
     }
   }
-  float* pg = part + (size_t)blockIdx.x * NTAP * CO * CI;
+  float* pg = part + (size_t)blockIdx.x * (NTAP * CO * CI + CO);
 #pragma unroll
   for (int j = 0; j < TPW; j++) {
     const int t = wave + NW * j;
@@ -366,7 +399,7 @@ __global__ __launch_bounds__(NBC) void k_wgrad(const __bf16* __restrict__ x, con
       pg[((size_t)tap * CO + co) * CI + ci] = acc[j][i];
     }
   }
-  if (tid < CO) part_b[(size_t)blockIdx.x * CO + tid] = db;
+  if (tid < CO) pg[NTAP * CO * CI + tid] = db;
 }
 
 // out[s][i] = sum of part[g][i] over the s-th of gridDim.y equal ranges of g,
@@ -447,11 +480,27 @@ __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __re
 }
 
 // bf16 forward weights [tap][co][ci] and backward-data weights
-// wt[tap][ci][co] = w[8 - tap][co][ci] from the FP32 master array
-__global__ void k_prep_weights(const float* __restrict__ w, int co_n, int ci_n,
-                               __bf16* __restrict__ wf, __bf16* __restrict__ wt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= NTAP * co_n * ci_n) return;
+// wt[tap][ci][co] = w[8 - tap][co][ci] from the FP32 master array, for the
+// three layers in one launch (layer l: n[l] weights from w[l])
+struct PrepLayers {
+  const float* w[3];
+  __bf16* wf[3];
+  __bf16* wt[3];
+  int co[3], ci[3];
+};
+
+__global__ void k_prep_weights(PrepLayers L) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int l = 0;
+  while (l < 3 && i >= NTAP * L.co[l] * L.ci[l]) {
+    i -= NTAP * L.co[l] * L.ci[l];
+    l++;
+  }
+  if (l == 3) return;
+  const float* w = L.w[l];
+  __bf16* wf = L.wf[l];
+  __bf16* wt = L.wt[l];
+  const int co_n = L.co[l], ci_n = L.ci[l];
   const int tap = i / (co_n * ci_n), rem = i - tap * co_n * ci_n;
   const int co = rem / ci_n, ci = rem - co * ci_n;
   const __bf16 h = to_bf16(w[i]);
@@ -461,25 +510,3 @@ __global__ void k_prep_weights(const float* __restrict__ w, int co_n, int ci_n,
 
 }  // namespace lbnet
 
-namespace lbnet {
-
-// network inputs of one window k of a box's sampled face history
-// samples [ns][6][R][R][3]: sample b = j * 6 + f (step t_k + j, face f) gets
-// coarse[b][tau][c][v][u] = samples[clamp(k - 1 + tau)][f][v][u][c] and
-// theta[b] = j / dt
-__global__ void k_gather_window(const float* __restrict__ samples, int ns, int R, int k, int dt,
-                                float* __restrict__ coarse, float* __restrict__ theta) {
-  const int b = blockIdx.x;
-  const int j = b / 6, f = b - 6 * j;
-  if (threadIdx.x == 0) theta[b] = (float)j / (float)dt;
-  const int n = 12 * R * R;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int tau = i / (3 * R * R), rem = i - tau * 3 * R * R;
-    const int c = rem / (R * R), vu = rem - c * R * R;
-    int ks = k - 1 + tau;
-    ks = ks < 0 ? 0 : (ks > ns - 1 ? ns - 1 : ks);
-    coarse[(size_t)b * n + i] = samples[(((size_t)ks * 6 + f) * R * R + vu) * 3 + c];
-  }
-}
-
-}  // namespace lbnet
