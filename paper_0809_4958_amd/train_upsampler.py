@@ -20,6 +20,11 @@ Inference speed: one window of lbn_window_forward (6 faces x 20 steps of
 
 Usage:  python -m paper_0809_4958_amd.train_upsampler [--traj 2000] [--out PATH]
 Prints one JSON line; writes the parameter vector (float32, .npy) to --out.
+
+        python -m paper_0809_4958_amd.train_upsampler --speed
+times only the kernels: window inference with the committed weights and
+training iterations of batch 64 on 16 trajectories' samples (no training
+run, nothing written).
 """
 from __future__ import annotations
 
@@ -37,6 +42,7 @@ sys.path.insert(0, os.path.dirname(PKG))
 from paper_0809_4958_amd import inputs, lbm, lbnet  # noqa: E402
 
 CFG_LEARNED = 3
+FLOPS_SAMPLE = 2.0 * 64 * 64 * 9 * (16 * 64 + 64 * 64 + 64 * 16)   # MFMA work per image, padded channels
 WEIGHTS = os.path.join(PKG, "weights", "upsampler_r8.npy")
 HELD_OUT_BASE = 5000
 
@@ -135,6 +141,37 @@ def downstream(net, traj, n=64, tau=0.6, windows=3, dt=20, R=8):
     return rel_l2(us["interp"], us["dense"]), rel_l2(us["learned"], us["dense"])
 
 
+def speed(args, iters=200):
+    """Kernel speed: one inference window and training iterations."""
+    import torch
+    net = lbnet.Upsampler(coarse=8, max_batch=max(args.batch, 120))
+    net.set_params(np.load(WEIGHTS))
+    win_ms, win_images = time_window_inference(net, HELD_OUT_BASE)
+    c, th, truth = inputs.upsampler_samples(CFG_LEARNED, range(16), windows=(0, 1), phases=(0, 10))
+    b = args.batch
+    cd, thd, trd = dev(c[:b]), dev(th[:b]), dev(truth[:b])
+    for _ in range(10):
+        net.loss_grad(cd, thd, trd, want_loss=False)
+        net.adam_step(args.lr)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        net.loss_grad(cd, thd, trd, want_loss=False)
+        net.adam_step(args.lr)
+    e1.record()
+    e1.synchronize()
+    train_ms = e0.elapsed_time(e1) / iters
+    fs = FLOPS_SAMPLE
+    out = {"infer_window_ms": round(win_ms, 4), "infer_window_images": win_images,
+           "infer_tflops_mfma": round(fs * win_images / (win_ms * 1e-3) / 1e12, 2),
+           "infer_mfma_frac_of_bf16_dense_peak": round(fs * win_images / (win_ms * 1e-3) / 2.5e15, 4),
+           "train_ms_per_iter": round(train_ms, 4), "train_batch": b,
+           "train_tflops_mfma": round(3 * fs * b / (train_ms * 1e-3) / 1e12, 2)}
+    print(json.dumps(out), flush=True)
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--traj", type=int, default=2000)
@@ -144,9 +181,12 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--downstream", type=int, default=4, help="held-out boxes run downstream")
     ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--speed", action="store_true", help="time the kernels only")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
+    if args.speed:
+        return speed(args)
     t0 = time.time()
     parts = []
     for a in range(0, args.traj, 250):
@@ -175,7 +215,7 @@ def main():
     p = net.params()
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, p)
-    flops_sample = 2.0 * 64 * 64 * 9 * (16 * 64 + 64 * 64 + 64 * 16)   # MFMA work, padded channels
+    flops_sample = FLOPS_SAMPLE
     out = {
         "workload": "learned boundary upsampler, 8x8 coarse faces every 20 steps -> 64x64 per step",
         "train_trajectories": args.traj, "train_samples": int(c.shape[0]),
