@@ -187,7 +187,7 @@ lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size
   const int rows = batch * IMG;
   const int grid = std::min(rows, MAX_PART);
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NBC), 0, st, x, dz, ctx->part, rows);
+  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NBW), 0, st, x, dz, ctx->part, rows);
   // two fixed-order stages: RSEG ranges of partials in parallel, then their
   // sum; weights and biases together (the biases follow the weights, in the
   // partials as in the parameters)
