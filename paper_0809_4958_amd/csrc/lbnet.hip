@@ -28,7 +28,6 @@ constexpr size_t OFF_W1 = 0, OFF_B1 = OFF_W1 + W1N, OFF_W2 = OFF_B1 + CH, OFF_B2
                  OFF_W3 = OFF_B2 + CH, OFF_B3 = OFF_W3 + W3N, NDEV = OFF_B3 + COUT;
 constexpr int IN_USED = 15, OUT_USED = 3;
 constexpr int MAX_PART = 256;  // weight-gradient partials (workgroups)
-constexpr int LIFT_SLICES = 8;  // workgroups per image of the lift (8 rows each)
 constexpr int RSEG = 16;       // first-stage ranges of the partial reduction
 
 static_assert((size_t)CH * IN_USED * 9 + CH + (size_t)CH * CH * 9 + CH + (size_t)OUT_USED * CH * 9 +
@@ -164,10 +163,14 @@ lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int bat
   const int tiles = batch * (IMG / TR);
   hipStream_t st = ctx->stream;
   const int R = ctx->cfg.coarse;
-  hipLaunchKernelGGL(k_lift, dim3(batch, LIFT_SLICES), dim3(NB), 24 * R * R * sizeof(float), st, coarse, theta, R, ctx->x0,
-                     ctx->base, ctx->scale, win);
-  hipLaunchKernelGGL((k_conv<CIN, CH, 0>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->x0, ctx->w1f,
-                     ctx->p + OFF_B1, nullptr, (void*)ctx->a1, tiles);
+  // lift + layer 1 per (sample, band): bands so that the grid covers the
+  // 256 compute units; x0 kept only outside the window path (training and
+  // lbn_read_buffer read it)
+  int bands = 1;
+  while (bands < IMG / TR && batch * bands < 256) bands *= 2;
+  hipLaunchKernelGGL(k_head, dim3(batch * bands), dim3(NBC), 24 * R * R * sizeof(float), st, coarse, theta, win,
+                     R, ctx->w1f, ctx->p + OFF_B1, ctx->a1, u_out ? nullptr : ctx->x0, ctx->base, ctx->scale,
+                     bands);
   hipLaunchKernelGGL((k_conv<CH, CH, 0>), dim3(conv_grid(tiles, 1)), dim3(NBC), 0, st, ctx->a1, ctx->w2f,
                      ctx->p + OFF_B2, nullptr, (void*)ctx->a2, tiles);
   if (u_out)

@@ -54,10 +54,9 @@ __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }  // rou
 __device__ __forceinline__ float from_bf16(__bf16 v) { return (float)v; }
 
 // ---------------------------------------------------------------- lift
-// One workgroup per sample.  coarse [B][4][3][R][R] (row v, column u),
-// theta [B]; writes x0 [B][64][64][16] bf16, base [B][64][64][3] and s [B].
-// The coarse feature grids (Sb, Duu Sb, Dvv Sb, temporal difference) are
-// formed in LDS first (R <= 32).
+// The lift of one sample b.  coarse [B][4][3][R][R] (row v, column u),
+// theta [B].  The coarse feature grids (Sb, Duu Sb, Dvv Sb, temporal
+// difference) are formed in LDS first (R <= 32).
 // Window mode (win.samples != NULL): the inputs of window k of a box's
 // sampled face history [ns][6][R][R][3] are read from it directly: sample
 // b = j * 6 + f (step t_k + j, face f) takes coarse[b][tau][c][v][u] =
@@ -67,19 +66,16 @@ struct LiftWindow {
   int ns, k, dt;
 };
 
-__global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
-                                             const float* __restrict__ theta, int R,
-                                             __bf16* __restrict__ x0, float* __restrict__ base,
-                                             float* __restrict__ scale, LiftWindow win) {
-  // workgroup (b, slice): rows slice * IMG / gridDim.y ... of image b; every
-  // slice recomputes the image's (few) coarse features
-  const int b = blockIdx.x, tid = threadIdx.x;
-  const int RR = R * R;
-  __shared__ double red[NB];
-  extern __shared__ float dyn[];
-  float* cin = dyn;                // the sample's coarse values [4][3][R][R]
-  float* feat = dyn + 12 * RR;     // [12][R][R]: Sb, Duu Sb, Dvv Sb, temporal difference
-  for (int i = tid; i < 12 * RR; i += NB) {
+// The sample's coarse values into cin [12 R R] and its features into feat
+// [12 R R] (block of NT threads, red: NT doubles of LDS); returns s (the RMS
+// of the coarse values, 1 if they are all zero) and theta.
+template <int NT>
+__device__ __forceinline__ void lift_prepare(int b, int R, const float* __restrict__ coarse,
+                                             const float* __restrict__ theta, const LiftWindow& win,
+                                             float* cin, float* feat, double* red, float& s_out,
+                                             float& th_out) {
+  const int tid = threadIdx.x, RR = R * R;
+  for (int i = tid; i < 12 * RR; i += NT) {
     if (win.samples) {
       const int j = b / 6, f = b - 6 * j;
       const int tau = i / (3 * RR), rem = i - tau * 3 * RR;
@@ -94,19 +90,18 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
   __syncthreads();
   const float* c = cin;
   double ss = 0.0;
-  for (int i = tid; i < 12 * RR; i += NB) ss += (double)c[i] * (double)c[i];
+  for (int i = tid; i < 12 * RR; i += NT) ss += (double)c[i] * (double)c[i];
   red[tid] = ss;
   __syncthreads();
-  for (int o = NB / 2; o > 0; o >>= 1) {
+  for (int o = NT / 2; o > 0; o >>= 1) {
     if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
   const double rms = sqrt(red[0] / (12.0 * RR));
   const float s = rms > 0.0 ? (float)rms : 1.0f;
-  if (tid == 0 && blockIdx.y == 0) scale[b] = s;
   const float th = win.samples ? (float)(b / 6) / (float)win.dt : theta[b];
   // Sb and the temporal difference
-  for (int i = tid; i < 3 * RR; i += NB) {
+  for (int i = tid; i < 3 * RR; i += NT) {
     const int cmp = i / RR, vu = i - cmp * RR;
     const float sm = c[(0 * 3 + cmp) * RR + vu], s0 = c[(1 * 3 + cmp) * RR + vu];
     const float s1 = c[(2 * 3 + cmp) * RR + vu], s2 = c[(3 * 3 + cmp) * RR + vu];
@@ -115,7 +110,7 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
   }
   __syncthreads();
   // second differences of Sb along u and v (edge nodes take the next node's)
-  for (int i = tid; i < 3 * RR; i += NB) {
+  for (int i = tid; i < 3 * RR; i += NT) {
     const int cmp = i / RR, vu = i - cmp * RR;
     const int v = vu / R, u = vu - v * R;
     const float* g = feat + cmp * RR;
@@ -126,39 +121,38 @@ __global__ __launch_bounds__(NB) void k_lift(const float* __restrict__ coarse,
         R >= 3 ? g[(vc + 1) * R + u] - 2.0f * g[vc * R + u] + g[(vc - 1) * R + u] : 0.0f;
   }
   __syncthreads();
-  const int per = IMG * IMG / (int)gridDim.y, p_end = ((int)blockIdx.y + 1) * per;
-  for (int p = (int)blockIdx.y * per + tid; p < p_end; p += NB) {
-    const int v = p / IMG, u = p - v * IMG;
-    // corner-aligned bilinear weights (same integer mapping as the face grid)
-    const int su = u * (R - 1), sv = v * (R - 1);
-    const int pu = su / (IMG - 1), pv = sv / (IMG - 1);
-    const float au = (float)(su - pu * (IMG - 1)) / (float)(IMG - 1);
-    const float av = (float)(sv - pv * (IMG - 1)) / (float)(IMG - 1);
-    const int pu1 = pu + 1 < R ? pu + 1 : pu, pv1 = pv + 1 < R ? pv + 1 : pv;
-    float lifted[12];
+  s_out = s;
+  th_out = th;
+}
+
+// The 16 input channels of pixel (u, v) (two vectors of 8) and the lifted
+// coarse field lifted[0..2] (the plain interpolation, the output's base).
+__device__ __forceinline__ void lift_pixel(const float* feat, int R, float s, float th, int u, int v,
+                                           bf16x8& lo, bf16x8& hi, float base3[3]) {
+  const int RR = R * R;
+  // corner-aligned bilinear weights (same integer mapping as the face grid)
+  const int su = u * (R - 1), sv = v * (R - 1);
+  const int pu = su / (IMG - 1), pv = sv / (IMG - 1);
+  const float au = (float)(su - pu * (IMG - 1)) / (float)(IMG - 1);
+  const float av = (float)(sv - pv * (IMG - 1)) / (float)(IMG - 1);
+  const int pu1 = pu + 1 < R ? pu + 1 : pu, pv1 = pv + 1 < R ? pv + 1 : pv;
+  float lifted[12];
 #pragma unroll
-    for (int ch = 0; ch < 12; ch++) {
-      const float* g = feat + ch * RR;
-      lifted[ch] = (1.0f - au) * (1.0f - av) * g[pv * R + pu] + au * (1.0f - av) * g[pv * R + pu1] +
-                   (1.0f - au) * av * g[pv1 * R + pu] + au * av * g[pv1 * R + pu1];
-    }
-    // the pixel's 16 channels as two 16-byte stores
-    bf16x8 lo, hi;
-#pragma unroll
-    for (int ch = 0; ch < 8; ch++) lo[ch] = to_bf16(lifted[ch] / s);
-#pragma unroll
-    for (int ch = 8; ch < 12; ch++) hi[ch - 8] = to_bf16(lifted[ch] / s);
-    hi[4] = to_bf16(th);
-    hi[5] = to_bf16(4.0f * au * (1.0f - au));
-    hi[6] = to_bf16(4.0f * av * (1.0f - av));
-    hi[7] = to_bf16(0.0f);
-    bf16x8* xo = (bf16x8*)(x0 + ((size_t)b * IMG * IMG + p) * CIN);
-    xo[0] = lo;
-    xo[1] = hi;
-    float* bo = base + ((size_t)b * IMG * IMG + p) * 3;
-#pragma unroll
-    for (int k = 0; k < 3; k++) bo[k] = lifted[k];
+  for (int ch = 0; ch < 12; ch++) {
+    const float* g = feat + ch * RR;
+    lifted[ch] = (1.0f - au) * (1.0f - av) * g[pv * R + pu] + au * (1.0f - av) * g[pv * R + pu1] +
+                 (1.0f - au) * av * g[pv1 * R + pu] + au * av * g[pv1 * R + pu1];
   }
+#pragma unroll
+  for (int ch = 0; ch < 8; ch++) lo[ch] = to_bf16(lifted[ch] / s);
+#pragma unroll
+  for (int ch = 8; ch < 12; ch++) hi[ch - 8] = to_bf16(lifted[ch] / s);
+  hi[4] = to_bf16(th);
+  hi[5] = to_bf16(4.0f * au * (1.0f - au));
+  hi[6] = to_bf16(4.0f * av * (1.0f - av));
+  hi[7] = to_bf16(0.0f);
+#pragma unroll
+  for (int k = 0; k < 3; k++) base3[k] = lifted[k];
 }
 
 // ---------------------------------------------------------------- conv
@@ -325,6 +319,113 @@ __global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, cons
           } else {
             ((__bf16*)out)[o] = to_bf16(from_bf16(mask_src[o]) > 0.0f ? v : 0.0f);
           }
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------- head
+// The lift and layer 1 (16 -> 64, bias, ReLU) in one pass: workgroup
+// (sample b, band) forms the sample's coarse features once, then for each of
+// its 4-row tiles lifts the six staged input rows straight into LDS (zero
+// outside the image) and runs the products of k_conv<16, 64, 0> on them (the
+// same order, so a1 is bitwise what the two-kernel path gives).  It writes
+// base and s, and x0 when x0 != NULL (training reads it; inference does not).
+// grid: B x bands, 16 / bands tiles per workgroup.
+__global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
+                                              const float* __restrict__ theta, LiftWindow win, int R,
+                                              const __bf16* __restrict__ w, const float* __restrict__ bias,
+                                              __bf16* __restrict__ a1, __bf16* __restrict__ x0,
+                                              float* __restrict__ base, float* __restrict__ scale,
+                                              int bands) {
+  constexpr int CI = CIN, CO = CH;
+  constexpr int CP = CI + 8;
+  constexpr int KCH = (NTAP * CI + 31) / 32;
+  constexpr int NBK = CO / 16;
+  constexpr int SR = TR + 2;
+  __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CP];
+  __shared__ __attribute__((aligned(16))) __bf16 sx[SR * (IMG + 2) * CP];
+  __shared__ double red[NBC];
+  extern __shared__ float dyn[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b = blockIdx.x / bands, band = blockIdx.x - b * bands;
+  for (int i = tid; i < NTAP * CO * (CI / 8); i += NBC) {
+    const int row = i / (CI / 8), c8 = i - row * (CI / 8);
+    *(uint4*)&sw[row * CP + 8 * c8] = *(const uint4*)&w[(size_t)row * CI + 8 * c8];
+  }
+  float s, th;
+  lift_prepare<NBC>(b, R, coarse, theta, win, dyn, dyn + 12 * R * R, red, s, th);
+  const float* feat = dyn + 12 * R * R;
+  if (tid == 0 && band == 0) scale[b] = s;
+  const int r = wave >> 1, px0 = (wave & 1) * 32;
+  const int rows = IMG / bands;
+  for (int y0 = band * rows; y0 < (band + 1) * rows; y0 += TR) {
+    __syncthreads();  // the previous tile's reads of sx are done
+    for (int q = tid; q < SR * (IMG + 2); q += NBC) {
+      const int rr = q / (IMG + 2), xx = q - rr * (IMG + 2) - 1, yy = y0 - 1 + rr;
+      uint4 lo4 = make_uint4(0u, 0u, 0u, 0u), hi4 = lo4;
+      if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG) {
+        bf16x8 lo, hi;
+        float b3[3];
+        lift_pixel(feat, R, s, th, xx, yy, lo, hi, b3);
+        lo4 = __builtin_bit_cast(uint4, lo);
+        hi4 = __builtin_bit_cast(uint4, hi);
+        if (rr >= 1 && rr <= TR) {  // the tile's own rows
+          const size_t p = ((size_t)b * IMG + yy) * IMG + xx;
+          float* bo = base + p * 3;
+#pragma unroll
+          for (int k = 0; k < 3; k++) bo[k] = b3[k];
+          if (x0) {
+            *(uint4*)(x0 + p * CIN) = lo4;
+            *(uint4*)(x0 + p * CIN + 8) = hi4;
+          }
+        }
+      }
+      *(uint4*)&sx[q * CP] = lo4;
+      *(uint4*)&sx[q * CP + 8] = hi4;
+    }
+    __syncthreads();
+    f32x4 acc[2][NBK];
+#pragma unroll
+    for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+      for (int nb = 0; nb < NBK; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kc = 0; kc < KCH; kc++) {
+      const int k0 = 32 * kc + 8 * (lane >> 4);
+      const bool kv = k0 < NTAP * CI;
+      const int tap = kv ? k0 / CI : 0, ci = kv ? k0 - tap * CI : 0;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      bf16x8 a[2], bb[NBK];
+#pragma unroll
+      for (int mb = 0; mb < 2; mb++) {
+        const int px = px0 + 16 * mb + (lane & 15);
+        a[mb] = kv ? *(const bf16x8*)&sx[((r + 1 + dy) * (IMG + 2) + px + 1 + dx) * CP + ci]
+                   : bf16x8{};
+      }
+#pragma unroll
+      for (int nb = 0; nb < NBK; nb++) {
+        const int co = 16 * nb + (lane & 15);
+        bb[nb] = kv ? *(const bf16x8*)&sw[(tap * CO + co) * CP + ci] : bf16x8{};
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+        for (int nb = 0; nb < NBK; nb++)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bb[nb], acc[mb][nb], 0, 0, 0);
+    }
+    const int y = y0 + r;
+#pragma unroll
+    for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+      for (int nb = 0; nb < NBK; nb++) {
+        const int co = 16 * nb + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int px = px0 + 16 * mb + 4 * (lane >> 4) + j;
+          const size_t o = (((size_t)b * IMG + y) * IMG + px) * CO + co;
+          const float v = acc[mb][nb][j] + bias[co];
+          a1[o] = to_bf16(v > 0.0f ? v : 0.0f);
         }
       }
   }
