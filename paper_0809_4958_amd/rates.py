@@ -116,7 +116,11 @@ def main(argv=None):
     ctx.sync()
     elapsed = time.perf_counter() - t0
     tm = ctx.timing()
+    status = ctx.sync_status()
+    rec = ctx.read(0, lbm.F_MASS_MOM) if status == lbm.OK else None
     out = {"workload": args.workload, "steps": args.steps, "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+           "status": int(status), "step_index": int(ctx.read(0, lbm.F_STEP, strict=False)[0]),
+           "box0_mass_momentum_record": None if rec is None else [float(v) for v in rec],
            "mlups": round(interior * args.steps / elapsed / 1e6, 1), "k_lb_ms": round(tm[1], 4),
            "pre_lb_kernels_ms": round(tm[2], 4),
            "algorithmic_gbs": round(tm[3] / (tm[1] * 1e-3) / 1e9, 1),
