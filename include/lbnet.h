@@ -98,9 +98,10 @@ lb_status lbn_adam_step(lbn_ctx* ctx, float lr, float beta1, float beta2, float 
  * (n values, LB_ERR_BUFSIZE if it does not match): 0 = lifted input
  * [batch][64][64][16], 1 = layer-1 output [batch][64][64][64], 2 = layer-2
  * output, 3 = network output r [batch][64][64][16], 4 = base [batch][64][64][3],
- * 5 = scale s [batch].  lbn_window_forward keeps 1, 2, 4 and 5 only: it
- * lifts straight into layer 1 and writes the face field from the last
- * layer, so 0 and 3 still hold the last lbn_forward or lbn_loss_grad. */
+ * 5 = scale s [batch].  lbn_window_forward keeps 1, 4 and 5 only: it lifts
+ * straight into layer 1, keeps the layer-2 output on chip and writes the
+ * face field from the last layer, so 0, 2 and 3 still hold the last
+ * lbn_forward or lbn_loss_grad. */
 lb_status lbn_read_buffer(lbn_ctx* ctx, int32_t which, int32_t batch, float* out, size_t n);
 
 lb_status lbn_sync(lbn_ctx* ctx);

@@ -151,8 +151,14 @@ lb_status prep_weights(lbn_ctx* ctx) {
   return LB_OK;
 }
 
-// persistent convolution grid: per_cu workgroups per compute unit (by LDS use)
-int conv_grid(int n_tiles, int per_cu) { return std::min(n_tiles, 256 * per_cu); }
+// bands per image of a convolution launch (one workgroup per band): the
+// fewest (a power of two, at most 64 / TR) for which the grid reaches about
+// per_cu workgroups per compute unit (per_cu by LDS and register use)
+int conv_bands(int batch, int per_cu) {
+  int bands = 1;
+  while (bands < IMG / TR && batch * bands < 240 * per_cu) bands *= 2;
+  return bands;
+}
 
 // win.samples != NULL: the window path (inputs gathered by the lift, the
 // face field written by the last layer into u_out; r is not kept)
@@ -160,7 +166,6 @@ lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int bat
                   LiftWindow win = LiftWindow{nullptr, 0, 0, 1}, float* u_out = nullptr) {
   lb_status s = prep_weights(ctx);
   if (s) return s;
-  const int tiles = batch * (IMG / TR);
   hipStream_t st = ctx->stream;
   const int R = ctx->cfg.coarse;
   // lift + layer 1 per (sample, band): bands so that the grid covers the
@@ -171,14 +176,15 @@ lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int bat
   hipLaunchKernelGGL(k_head, dim3(batch * bands), dim3(NBC), 24 * R * R * sizeof(float), st, coarse, theta, win,
                      R, ctx->w1f, ctx->p + OFF_B1, ctx->a1, u_out ? nullptr : ctx->x0, ctx->base, ctx->scale,
                      bands);
-  hipLaunchKernelGGL((k_conv<CH, CH, 0>), dim3(conv_grid(tiles, 1)), dim3(NBC), 0, st, ctx->a1, ctx->w2f,
-                     ctx->p + OFF_B2, nullptr, (void*)ctx->a2, tiles);
+  // layers 2 and 3 in one pass; the layer-2 output is stored only outside
+  // the window path (the backward pass and lbn_read_buffer read it)
+  const int b1 = conv_bands(batch, 1);
   if (u_out)
-    hipLaunchKernelGGL((k_conv<CH, COUT, 3>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->a2, ctx->w3f,
-                       ctx->p + OFF_B3, nullptr, (void*)u_out, tiles, ctx->base, ctx->scale);
+    hipLaunchKernelGGL((k_conv23<3>), dim3(batch * b1), dim3(NBC), 0, st, ctx->a1, ctx->w2f, ctx->p + OFF_B2,
+                       ctx->w3f, ctx->p + OFF_B3, nullptr, (void*)u_out, b1, ctx->base, ctx->scale);
   else
-    hipLaunchKernelGGL((k_conv<CH, COUT, 1>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->a2, ctx->w3f,
-                       ctx->p + OFF_B3, nullptr, (void*)ctx->r, tiles);
+    hipLaunchKernelGGL((k_conv23<1>), dim3(batch * b1), dim3(NBC), 0, st, ctx->a1, ctx->w2f, ctx->p + OFF_B2,
+                       ctx->w3f, ctx->p + OFF_B3, ctx->a2, (void*)ctx->r, b1, ctx->base, ctx->scale);
   HIPCHK(hipGetLastError());
   ctx->last_batch = batch;
   return LB_OK;
@@ -328,15 +334,15 @@ lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* thet
   hipLaunchKernelGGL(k_loss, dim3(lgrid), dim3(NB), 0, st, ctx->r, ctx->base, ctx->scale, truth_dev, n_px,
                      inv_count, ctx->dy, ctx->loss_part);
   HIPCHK(hipGetLastError());
-  const int tiles = batch * (IMG / TR);
+  const int b1 = conv_bands(batch, 1), b2 = conv_bands(batch, 2);
   // layer 3: weights from (a2, dy); data gradient through ReLU(a2)
   if ((s = wgrad<CH, COUT>(ctx, ctx->a2, ctx->dy, batch, OFF_W3, OFF_B3))) return s;
-  hipLaunchKernelGGL((k_conv<COUT, CH, 2>), dim3(conv_grid(tiles, 2)), dim3(NBC), 0, st, ctx->dy, ctx->w3t,
-                     nullptr, ctx->a2, (void*)ctx->dz2, tiles);
+  hipLaunchKernelGGL((k_conv<COUT, CH, 2>), dim3(batch * b2), dim3(NBC), 0, st, ctx->dy, ctx->w3t, nullptr,
+                     ctx->a2, ctx->dz2, b2);
   // layer 2
   if ((s = wgrad<CH, CH>(ctx, ctx->a1, ctx->dz2, batch, OFF_W2, OFF_B2))) return s;
-  hipLaunchKernelGGL((k_conv<CH, CH, 2>), dim3(conv_grid(tiles, 1)), dim3(NBC), 0, st, ctx->dz2, ctx->w2t,
-                     nullptr, ctx->a1, (void*)ctx->dz1, tiles);
+  hipLaunchKernelGGL((k_conv<CH, CH, 2>), dim3(batch * b1), dim3(NBC), 0, st, ctx->dz2, ctx->w2t, nullptr,
+                     ctx->a1, ctx->dz1, b1);
   // layer 1
   if ((s = wgrad<CIN, CH>(ctx, ctx->x0, ctx->dz1, batch, OFF_W1, OFF_B1))) return s;
   HIPCHK(hipGetLastError());

@@ -53,6 +53,23 @@ constexpr int NTAP = 9;
 __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }  // round to nearest even
 __device__ __forceinline__ float from_bf16(__bf16 v) { return (float)v; }
 
+// LDS rows of C bf16 values (a pixel's channels, a weight row's input
+// channels), read as 16-byte fragments: lane l takes row p0 + l % 16 and
+// chunk c0 + l / 16.  A 128-bit LDS read is served 16 lanes per cycle over 64
+// banks, lanes grouped within each half wave by the parity of bits 2..4 of the
+// lane index ({0-3, 12-15, 20-27}, {4-11, 16-19, 28-31}; measured with the
+// bank-conflict counter on the device), so rows of 128 bytes (C = 64) take
+// 4-way conflicts and rows padded to 144 bytes 2-way.  With C = 64, chunk c of
+// row p is stored at chunk c ^ (p & 7): the 16 lanes of every group then hit
+// 16 distinct bank quads for any row offset.  Rows of 32 bytes (C = 16) are
+// conflict-free as they are.  Returns the element offset of chunk c8 of row.
+template <int C>
+__device__ __forceinline__ int lds_at(int row, int c8) {
+  static_assert(C == 16 || C == 64, "LDS rows of 16 or 64 channels");
+  if constexpr (C == 64) return row * 64 + 8 * (c8 ^ (row & 7));
+  else return row * C + 8 * c8;
+}
+
 // ---------------------------------------------------------------- lift
 // The lift of one sample b.  coarse [B][4][3][R][R] (row v, column u),
 // theta [B].  The coarse feature grids (Sb, Duu Sb, Dvv Sb, temporal
@@ -156,171 +173,347 @@ __device__ __forceinline__ void lift_pixel(const float* feat, int R, float s, fl
 }
 
 // ---------------------------------------------------------------- conv
-// Implicit-GEMM 3x3 convolution over tiles of TR image rows.  EPI: 0 = bias +
-// ReLU -> bf16; 1 = bias -> fp32 (last layer, all CO channels); 2 = no bias,
-// times the mask (mask_src > 0) -> bf16 (backward data through a ReLU);
-// 3 = the face field u = base + s r of output channels 0..2 -> fp32
-// [B][64][64][3] (last layer, inference).
-// Persistent: workgroup g handles tiles g, g + gridDim.x, ...; eight waves
-// share one LDS copy of the weights, each computes 32 pixels x CO.
+// Products with the weights as the A operand and the pixels as B: the
+// accumulator of block (mb, nb) holds, in lane l, pixel 16 mb + l % 16 and
+// output slots 16 nb + 4 (l / 16) + j, j = 0..3.  The weights are staged into
+// LDS with their rows permuted so that slot 16 nb + 4 g + j carries channel
+// co_of<CO>(slot) = 16 g + 4 nb + j: lane l then holds the 4 NBK consecutive
+// channels from first_co<CO>(l) of one pixel, which leave as whole 16-byte
+// (CO = 64) or 8-byte (CO = 16) vectors.
+template <int CO>
+__device__ __forceinline__ int co_of(int slot) {
+  if constexpr (CO == 64) return 16 * ((slot & 15) >> 2) + 4 * (slot >> 4) + (slot & 3);
+  else return slot;
+}
+template <int CO>
+__device__ __forceinline__ int first_co(int lane) { return (CO == 64 ? 16 : 4) * (lane >> 4); }
+
+// Epilogue of one pixel's NC = 4 NBK consecutive channels c0 .. c0 + NC - 1
+// (v[q] = channel c0 + q) at pixel index p (b * 64 + y) * 64 + x, to bf16:
+// EPI 0 = bias + ReLU; 2 = no bias, times the mask (mask_src > 0; backward
+// data through a ReLU).
+template <int CO, int EPI, int NC>
+__device__ __forceinline__ void store_pixel(const float (&v)[NC], size_t p, int c0,
+                                            const float* __restrict__ bias,
+                                            const __bf16* __restrict__ mask_src, __bf16* __restrict__ out) {
+  static_assert(EPI == 0 || EPI == 2, "bf16 epilogues");
+  constexpr int VS = NC >= 8 ? 8 : NC;  // bf16 values per vector access
+  const size_t o = p * CO + c0;
+  __bf16 h[NC];
+  if constexpr (EPI == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; q++) {
+      const float t = v[q] + bias[c0 + q];
+      h[q] = to_bf16(t > 0.0f ? t : 0.0f);
+    }
+  } else {
+    __bf16 m[NC];
+#pragma unroll
+    for (int q = 0; q < NC; q += VS) {
+      if constexpr (VS == 8) *(uint4*)&m[q] = *(const uint4*)&mask_src[o + q];
+      else *(uint2*)&m[q] = *(const uint2*)&mask_src[o + q];
+    }
+#pragma unroll
+    for (int q = 0; q < NC; q++) h[q] = to_bf16(from_bf16(m[q]) > 0.0f ? v[q] : 0.0f);
+  }
+#pragma unroll
+  for (int q = 0; q < NC; q += VS) {
+    if constexpr (VS == 8) *(uint4*)&out[o + q] = *(const uint4*)&h[q];
+    else *(uint2*)&out[o + q] = *(const uint2*)&h[q];
+  }
+}
+
+// The products of one tile row for a wave: 32 pixels (px0 ..) of output row
+// y against all CO output slots of the staged weights, K = 9 CI in chunks of
+// 32 (with PF, the fragments of the next two chunks load while a chunk
+// multiplies).  The input
+// row y + dy starts at LDS pixel row_at[dy + 1] (rows of IMG + 2 pixels, zero
+// halo).
+template <int CI, int CO, bool PF = true, int MB = 2, int NBK = CO / 16>
+__device__ __forceinline__ void conv_products(const __bf16* sx, const __bf16* sw, const int (&row_at)[3], int px0,
+                                              int lane, f32x4 (&acc)[MB][NBK], int nb0 = 0) {
+  constexpr int KCH = (NTAP * CI + 31) / 32;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int nb = 0; nb < NBK; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto frag = [&](int kc, bf16x8 (&a)[MB], bf16x8 (&bb)[NBK]) {
+    const int k0 = 32 * kc + 8 * (lane >> 4);
+    const bool kv = k0 < NTAP * CI;
+    const int tap = kv ? k0 / CI : 0, ci = kv ? k0 - tap * CI : 0;
+    const int dyi = tap / 3, dx = tap % 3 - 1;
+    const int rb = dyi == 0 ? row_at[0] : (dyi == 1 ? row_at[1] : row_at[2]);
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+      const int px = px0 + 16 * mb + (lane & 15);
+      a[mb] = kv ? *(const bf16x8*)&sx[lds_at<CI>(rb + px + 1 + dx, ci >> 3)] : bf16x8{};
+    }
+#pragma unroll
+    for (int nb = 0; nb < NBK; nb++) {
+      const int slot = 16 * (nb0 + nb) + (lane & 15);
+      bb[nb] = kv ? *(const bf16x8*)&sw[lds_at<CI>(tap * CO + slot, ci >> 3)] : bf16x8{};
+    }
+  };
+  auto mult = [&](const bf16x8 (&a)[MB], const bf16x8 (&bb)[NBK]) {
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int nb = 0; nb < NBK; nb++)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bb[nb], a[mb], acc[mb][nb], 0, 0, 0);
+  };
+  if constexpr (PF) {
+    // fragments of chunks kc + 1 and kc + 2 in flight while chunk kc multiplies
+    bf16x8 fa[3][MB], fb[3][NBK];
+    frag(0, fa[0], fb[0]);
+    if (KCH > 1) frag(1, fa[1], fb[1]);
+#pragma unroll
+    for (int kc = 0; kc < KCH; kc++) {
+      if (kc + 2 < KCH) frag(kc + 2, fa[(kc + 2) % 3], fb[(kc + 2) % 3]);
+      mult(fa[kc % 3], fb[kc % 3]);
+    }
+  } else {
+#pragma unroll 2
+    for (int kc = 0; kc < KCH; kc++) {
+      bf16x8 a[MB], bb[NBK];
+      frag(kc, a, bb);
+      mult(a, bb);
+    }
+  }
+}
+
+// Stage the weights [tap][co][ci] into LDS with their rows in slot order.
+template <int CI, int CO>
+__device__ __forceinline__ void stage_weights(const __bf16* __restrict__ w, __bf16* sw, int tid) {
+  for (int i = tid; i < NTAP * CO * (CI / 8); i += NBC) {
+    const int row = i / (CI / 8), c8 = i - row * (CI / 8);
+    const int tap = row / CO, slot = row - tap * CO;
+    *(uint4*)&sw[lds_at<CI>(row, c8)] = *(const uint4*)&w[((size_t)tap * CO + co_of<CO>(slot)) * CI + 8 * c8];
+  }
+}
+
+// The epilogue of a wave's tile row: pixels px0 .. px0 + 31 of image row y.
+template <int CO, int EPI, int MB = 2>
+__device__ __forceinline__ void store_row(const f32x4 (&acc)[MB][CO / 16], int b, int y, int px0, int lane,
+                                          const float* __restrict__ bias, const __bf16* __restrict__ mask_src,
+                                          __bf16* __restrict__ out) {
+  constexpr int NBK = CO / 16, NC = 4 * NBK;
+  const int c0 = first_co<CO>(lane);
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++) {
+    float v[NC];
+#pragma unroll
+    for (int nb = 0; nb < NBK; nb++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) v[4 * nb + j] = acc[mb][nb][j];
+    const int px = px0 + 16 * mb + (lane & 15);
+    store_pixel<CO, EPI, NC>(v, ((size_t)b * IMG + y) * IMG + px, c0, bias, mask_src, out);
+  }
+}
+
+// Implicit-GEMM 3x3 convolution, epilogue EPI as in store_pixel.  Workgroup
+// g convolves the 64 / bands rows of band g % bands of image g / bands, TR
+// rows per tile (eight waves, each 32 pixels x CO of one row).  The input
+// rows live in a ring of RS = 2 TR + 2 LDS row slots (image row yy in slot
+// (yy + 1) % RS; rows outside the image are zero): a tile reads rows y0 - 1
+// .. y0 + TR, and the TR rows the next tile adds, loaded from memory one
+// tile ahead, go into the other slots after the tile's products, so each
+// input row is loaded once per band (plus two halo rows) and one barrier per
+// tile suffices.
 template <int CI, int CO, int EPI>
 __global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
                                               const float* __restrict__ bias,
-                                              const __bf16* __restrict__ mask_src,
-                                              void* __restrict__ out, int n_tiles,
-                                              const float* __restrict__ base = nullptr,
-                                              const float* __restrict__ scale = nullptr) {
-  constexpr int CP = CI + 8;                  // padded channel stride in LDS
-  constexpr int KCH = (NTAP * CI + 31) / 32;  // K chunks of 32
-  constexpr int NBK = CO / 16;                // 16-column blocks
-  constexpr int SR = TR + 2;                  // staged input rows per tile
-  constexpr int XV = SR * (IMG + 2) * (CI / 8);
-  constexpr int XS = (XV + NBC - 1) / NBC;    // 8-channel vectors per thread
-  // the masked bf16 output of the thin backward layer leaves through LDS:
-  // each wave's 32 pixels x CO channels are written there, then stored (and
-  // masked) as whole 16-byte vectors (the 32 pixels' CO channels are
-  // contiguous in the NHWC output); the staging reuses sx.  Measured: 23.3 ->
-  // 16.9 us for k_conv<16, 64, 2> at batch 64; the other bf16 outputs ran
-  // 1-4 us slower this way (the extra barrier), so they store directly.
-  constexpr bool STAGE = EPI == 2 && CI == 16;
-  constexpr int OP = CO + 8;                  // padded channel stride of the staging
-  constexpr int SXN = SR * (IMG + 2) * CP, STN = STAGE ? (NBC / 64) * 32 * OP : 0;
-  __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CP];
-  __shared__ __attribute__((aligned(16))) __bf16 sx[SXN > STN ? SXN : STN];
+                                              const __bf16* __restrict__ mask_src, __bf16* __restrict__ out,
+                                              int bands) {
+  constexpr int RS = 2 * TR + 2;              // ring row slots
+  constexpr int RV = (IMG + 2) * (CI / 8);    // 16-byte vectors of one staged row
+  constexpr int XS = (TR * RV + NBC - 1) / NBC;
+  __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CI];
+  __shared__ __attribute__((aligned(16))) __bf16 sx[RS * (IMG + 2) * CI];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // weights once per workgroup
-  for (int i = tid; i < NTAP * CO * (CI / 8); i += NBC) {
-    const int row = i / (CI / 8), c8 = i - row * (CI / 8);
-    *(uint4*)&sw[row * CP + 8 * c8] = *(const uint4*)&w[(size_t)row * CI + 8 * c8];
-  }
-  // wave: row r of the tile, pixels px0 .. px0 + 31
-  const int r = wave >> 1, px0 = (wave & 1) * 32;
-  // input rows y0-1 .. y0+TR, columns -1 .. 64 (zero outside the image); the
-  // next tile's rows travel in registers while the current tile computes
+  const int b = blockIdx.x / bands, band = blockIdx.x - b * bands;
+  const int rows = IMG / bands, ybeg = band * rows;
+  stage_weights<CI, CO>(w, sw, tid);
+  // image rows y .. y + n - 1 (n <= TR) into registers, then into the ring
   uint4 xr[XS];
-  auto load_tile = [&](int tile) {
-    const int b = tile / (IMG / TR), y0 = TR * (tile - b * (IMG / TR));
+  auto load_rows = [&](int y, int n) {
 #pragma unroll
     for (int j = 0; j < XS; j++) {
       const int v = tid + j * NBC;
       xr[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (v < XV) {
+      if (v < n * RV) {
         const int c8 = v % (CI / 8), q = v / (CI / 8);
-        const int xx = q % (IMG + 2) - 1, rr = q / (IMG + 2), yy = y0 - 1 + rr;
+        const int xx = q % (IMG + 2) - 1, yy = y + q / (IMG + 2);
         if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
           xr[j] = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
       }
     }
   };
-  if ((int)blockIdx.x < n_tiles) load_tile(blockIdx.x);
-  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int b = tile / (IMG / TR), y0 = TR * (tile - b * (IMG / TR));
-    __syncthreads();  // the previous tile's reads of sx are done (and sw is complete)
+  auto put_rows = [&](int y, int n) {
 #pragma unroll
     for (int j = 0; j < XS; j++) {
       const int v = tid + j * NBC;
-      if (v < XV) {
+      if (v < n * RV) {
         const int c8 = v % (CI / 8), q = v / (CI / 8);
-        *(uint4*)&sx[q * CP + 8 * c8] = xr[j];
+        const int col = q % (IMG + 2), yy = y + q / (IMG + 2);
+        *(uint4*)&sx[lds_at<CI>(((yy + 1) % RS) * (IMG + 2) + col, c8)] = xr[j];
       }
     }
-    __syncthreads();
-    if (tile + (int)gridDim.x < n_tiles) load_tile(tile + gridDim.x);
-    f32x4 acc[2][NBK];
+  };
+  const int r = wave >> 1, px0 = (wave & 1) * 32;
+  const int ntiles = rows / TR;
+  // the first tile's TR + 2 rows, then the second tile's new rows in flight
+  load_rows(ybeg - 1, TR);
+  put_rows(ybeg - 1, TR);
+  load_rows(ybeg + TR - 1, 2);
+  put_rows(ybeg + TR - 1, 2);
+  if (ntiles > 1) load_rows(ybeg + TR + 1, TR);
+  __syncthreads();
+  for (int i = 0; i < ntiles; i++) {
+    const int y0 = ybeg + TR * i, y = y0 + r;
+    const int row_at[3] = {(y % RS) * (IMG + 2), ((y + 1) % RS) * (IMG + 2), ((y + 2) % RS) * (IMG + 2)};
+    f32x4 acc[2][CO / 16];
+    conv_products<CI, CO>(sx, sw, row_at, px0, lane, acc);
+    if (i + 1 < ntiles) {
+      put_rows(y0 + TR + 1, TR);
+      if (i + 2 < ntiles) load_rows(y0 + 2 * TR + 1, TR);
+    }
+    store_row<CO, EPI>(acc, b, y, px0, lane, bias, mask_src, out);
+    __syncthreads();  // the next tile's rows are in; this tile's slots are free
+  }
+}
+
+// ---------------------------------------------------------------- layers 2 + 3
+// Layer 2 (64 -> 64, bias, ReLU) and layer 3 (64 -> 16) in one pass, so the
+// layer-2 activations stay on chip.  Workgroup g takes the 64 / bands output
+// rows [yb, ye) of band g % bands of image g / bands in steps of two rows:
+// step s makes layer-2 rows ya, ya + 1 (ya = yb - 1 + 2 s) from layer-1 rows
+// ya - 1 .. ya + 2 and then layer-3 rows ya - 1, ya (for s >= 1) from layer-2
+// rows ya - 2 .. ya + 1.  Both activations live in LDS rings of four rows
+// (row yy in slot (yy + 4) % 4, 66 pixels with a zero halo); the weights of
+// both layers are staged once (159,744 bytes of LDS in all).  The layer-1
+// rows of the next step travel in registers one step ahead.  Layer-2 rows
+// outside the image are zero (layer 3's padding); the two layer-2 rows past
+// each end of a band are computed by both neighbours.  The products and
+// their order are those of k_conv<64, 64, 0> and k_conv<64, 16, EPI3>, so the
+// results are bitwise theirs.  a2_out != NULL also stores the band's
+// layer-2 rows (the backward pass reads them).  EPI3: 1 (r) or 3 (u).
+template <int EPI3>
+__global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, const __bf16* __restrict__ w2,
+                                                const float* __restrict__ b2, const __bf16* __restrict__ w3,
+                                                const float* __restrict__ b3, __bf16* __restrict__ a2_out,
+                                                void* __restrict__ out, int bands,
+                                                const float* __restrict__ base,
+                                                const float* __restrict__ scale) {
+  constexpr int C = CH, RW = IMG + 2;          // channels, pixels of a staged row
+  constexpr int RV = RW * (C / 8);             // 16-byte vectors of one staged row
+  constexpr int XS = (2 * RV + NBC - 1) / NBC;
+  __shared__ __attribute__((aligned(16))) __bf16 s_w2[NTAP * C * C];
+  __shared__ __attribute__((aligned(16))) __bf16 s_w3[NTAP * COUT * C];
+  __shared__ __attribute__((aligned(16))) __bf16 s_a1[4 * RW * C];
+  __shared__ __attribute__((aligned(16))) __bf16 s_a2[4 * RW * C];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b = blockIdx.x / bands, band = blockIdx.x - b * bands;
+  const int rows = IMG / bands, yb = band * rows, ye = yb + rows;
+  stage_weights<C, C>(w2, s_w2, tid);
+  stage_weights<C, COUT>(w3, s_w3, tid);
+  for (int i = tid; i < 4 * RV; i += NBC) *(uint4*)&s_a2[8 * i] = make_uint4(0u, 0u, 0u, 0u);
+  uint4 xr[XS];
+  auto load_rows = [&](int y) {  // layer-1 rows y, y + 1 into registers
 #pragma unroll
-    for (int mb = 0; mb < 2; mb++)
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NBC;
+      xr[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (v < 2 * RV) {
+        const int c8 = v % (C / 8), q = v / (C / 8);
+        const int xx = q % RW - 1, yy = y + q / RW;
+        if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
+          xr[j] = *(const uint4*)&a1[(((size_t)b * IMG + yy) * IMG + xx) * C + 8 * c8];
+      }
+    }
+  };
+  auto put_rows = [&](int y) {
 #pragma unroll
-      for (int nb = 0; nb < NBK; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int kc = 0; kc < KCH; kc++) {
-      const int k0 = 32 * kc + 8 * (lane >> 4);
-      const bool kv = k0 < NTAP * CI;
-      const int tap = kv ? k0 / CI : 0, ci = kv ? k0 - tap * CI : 0;
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      bf16x8 a[2], bb[NBK];
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NBC;
+      if (v < 2 * RV) {
+        const int c8 = v % (C / 8), q = v / (C / 8);
+        const int yy = y + q / RW;
+        *(uint4*)&s_a1[lds_at<C>(((yy + 4) & 3) * RW + q % RW, c8)] = xr[j];
+      }
+    }
+  };
+  // layer-1 rows yb - 2 .. yb + 1 for step 0, rows yb + 2, yb + 3 in flight
+  load_rows(yb - 2);
+  put_rows(yb - 2);
+  load_rows(yb);
+  put_rows(yb);
+  load_rows(yb + 2);
+  // layer 2: wave = (row r2, pixel half, channel half); layer 3: (row r3, pixel block)
+  const int r2 = wave >> 2, q = wave & 3, px2 = 32 * (q & 1), nb2 = 2 * (q >> 1);
+  const int px3 = 16 * q;
+  const int g = lane >> 4, c2 = 16 * g + 8 * (q >> 1);  // the 8 layer-2 channels a lane holds
+  const int c3 = 4 * g;                                  // the 4 layer-3 channels a lane holds
+  float bb2[8], bb3[4];                                  // their biases, loaded once
+#pragma unroll
+  for (int k = 0; k < 8; k++) bb2[k] = b2[c2 + k];
+#pragma unroll
+  for (int k = 0; k < 4; k++) bb3[k] = b3[c3 + k];
+  __syncthreads();
+  const int nsteps = rows / 2 + 1;
+  for (int st = 0; st < nsteps; st++) {
+    const int ya = yb - 1 + 2 * st;
+    {
+      const int y = ya + r2;  // layer-2 row of this wave
+      const int row_at[3] = {((y + 3) & 3) * RW, ((y + 4) & 3) * RW, ((y + 5) & 3) * RW};
+      f32x4 acc[2][2];
+      conv_products<C, C, true, 2, 2>(s_a1, s_w2, row_at, px2, lane, acc, nb2);
+      const bool inside = y >= 0 && y < IMG;
 #pragma unroll
       for (int mb = 0; mb < 2; mb++) {
-        const int px = px0 + 16 * mb + (lane & 15);
-        a[mb] = kv ? *(const bf16x8*)&sx[((r + 1 + dy) * (IMG + 2) + px + 1 + dx) * CP + ci]
-                   : bf16x8{};
-      }
+        const int px = px2 + 16 * mb + (lane & 15);
+        __bf16 h[8];
 #pragma unroll
-      for (int nb = 0; nb < NBK; nb++) {
-        const int co = 16 * nb + (lane & 15);
-        bb[nb] = kv ? *(const bf16x8*)&sw[(tap * CO + co) * CP + ci] : bf16x8{};
-      }
-#pragma unroll
-      for (int mb = 0; mb < 2; mb++)
-#pragma unroll
-        for (int nb = 0; nb < NBK; nb++)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bb[nb], acc[mb][nb], 0, 0, 0);
-    }
-    // epilogue: lane holds pixels px0 + 16 mb + 4 (lane / 16) + j of column co
-    const int y = y0 + r;
-    if constexpr (STAGE) {
-      __syncthreads();  // every wave's products have read sx
-      __bf16* st = sx + wave * 32 * OP;
-#pragma unroll
-      for (int mb = 0; mb < 2; mb++)
-#pragma unroll
-        for (int nb = 0; nb < NBK; nb++) {
-          const int co = 16 * nb + (lane & 15);
+        for (int nb = 0; nb < 2; nb++)
 #pragma unroll
           for (int j = 0; j < 4; j++) {
-            const int pl = 16 * mb + 4 * (lane >> 4) + j;
-            float v = acc[mb][nb][j];
-            if (EPI == 0) {
-              v += bias[co];
-              v = v > 0.0f ? v : 0.0f;
-            }
-            st[pl * OP + co] = to_bf16(v);
+            const float t = acc[mb][nb][j] + bb2[4 * nb + j];
+            h[4 * nb + j] = to_bf16(inside && t > 0.0f ? t : 0.0f);
           }
-        }
-      // 32 pixels x CO / 8 vectors of 16 bytes, contiguous in the output
-      constexpr int NV = 32 * CO / 8;
-      const size_t o0 = (((size_t)b * IMG + y) * IMG + px0) * CO;
-#pragma unroll
-      for (int k = 0; k < NV / 64; k++) {
-        const int vi = lane + 64 * k, pl = vi / (CO / 8), c8 = vi - pl * (CO / 8);
-        uint4 v = *(const uint4*)&st[pl * OP + 8 * c8];
-        if (EPI == 2) {
-          // through the ReLU of the forward pass: zero where its output was 0
-          const uint4 m = *(const uint4*)&mask_src[o0 + (size_t)pl * CO + 8 * c8];
-          const __bf16* mv = (const __bf16*)&m;
-          __bf16* vv = (__bf16*)&v;
-#pragma unroll
-          for (int e = 0; e < 8; e++) vv[e] = from_bf16(mv[e]) > 0.0f ? vv[e] : to_bf16(0.0f);
-        }
-        *(uint4*)&((__bf16*)out)[o0 + (size_t)pl * CO + 8 * c8] = v;
+        const uint4 hv = *(const uint4*)h;
+        *(uint4*)&s_a2[lds_at<C>(((y + 4) & 3) * RW + px + 1, c2 >> 3)] = hv;
+        if (a2_out && y >= yb && y < ye)
+          *(uint4*)&a2_out[(((size_t)b * IMG + y) * IMG + px) * C + c2] = hv;
       }
-      continue;
     }
+    __syncthreads();  // layer-2 rows ya, ya + 1 in; layer-1 rows ya - 1, ya free
+    if (st + 1 < nsteps) {
+      put_rows(ya + 3);
+      if (st + 2 < nsteps) load_rows(ya + 5);
+    }
+    if (st >= 1) {
+      const int y = ya - 1 + r2;  // layer-3 row of this wave
+      const int row_at[3] = {((y + 3) & 3) * RW, ((y + 4) & 3) * RW, ((y + 5) & 3) * RW};
+      const size_t p = ((size_t)b * IMG + y) * IMG + px3 + (lane & 15);
+      // the epilogue's inputs are loaded before the products
+      float bs[3] = {0.f, 0.f, 0.f}, sb = 0.f;
+      if (EPI3 == 3 && g == 0) {
+        sb = scale[b];
 #pragma unroll
-    for (int mb = 0; mb < 2; mb++)
-#pragma unroll
-      for (int nb = 0; nb < NBK; nb++) {
-        const int co = 16 * nb + (lane & 15);
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int px = px0 + 16 * mb + 4 * (lane >> 4) + j;
-          const size_t o = (((size_t)b * IMG + y) * IMG + px) * CO + co;
-          float v = acc[mb][nb][j];
-          if (EPI == 0) {
-            v += bias[co];
-            ((__bf16*)out)[o] = to_bf16(v > 0.0f ? v : 0.0f);
-          } else if (EPI == 1) {
-            ((float*)out)[o] = v + bias[co];
-          } else if (EPI == 3) {
-            if (co < 3) {
-              const size_t q = ((size_t)b * IMG + y) * IMG + px;
-              const float rv = v + bias[co];
-              ((float*)out)[q * 3 + co] = base[q * 3 + co] + scale[b] * rv;
-            }
-          } else {
-            ((__bf16*)out)[o] = to_bf16(from_bf16(mask_src[o]) > 0.0f ? v : 0.0f);
-          }
-        }
+        for (int k = 0; k < 3; k++) bs[k] = base[p * 3 + k];
       }
+      f32x4 acc[1][1];
+      conv_products<C, COUT, true, 1, 1>(s_a2, s_w3, row_at, px3, lane, acc, 0);
+      if constexpr (EPI3 == 3) {
+        if (g == 0) {
+#pragma unroll
+          for (int k = 0; k < 3; k++) ((float*)out)[p * 3 + k] = bs[k] + sb * (acc[0][0][k] + bb3[k]);
+        }
+      } else {
+        *(float4*)&((float*)out)[p * COUT + c3] = make_float4(acc[0][0][0] + bb3[0], acc[0][0][1] + bb3[1],
+                                                               acc[0][0][2] + bb3[2], acc[0][0][3] + bb3[3]);
+      }
+    }
+    __syncthreads();  // layer-1 rows of the next step in; layer-3 reads of s_a2 done
   }
 }
 
@@ -339,20 +532,14 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
                                               float* __restrict__ base, float* __restrict__ scale,
                                               int bands) {
   constexpr int CI = CIN, CO = CH;
-  constexpr int CP = CI + 8;
-  constexpr int KCH = (NTAP * CI + 31) / 32;
-  constexpr int NBK = CO / 16;
   constexpr int SR = TR + 2;
-  __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CP];
-  __shared__ __attribute__((aligned(16))) __bf16 sx[SR * (IMG + 2) * CP];
+  __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CI];
+  __shared__ __attribute__((aligned(16))) __bf16 sx[SR * (IMG + 2) * CI];
   __shared__ double red[NBC];
   extern __shared__ float dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = blockIdx.x / bands, band = blockIdx.x - b * bands;
-  for (int i = tid; i < NTAP * CO * (CI / 8); i += NBC) {
-    const int row = i / (CI / 8), c8 = i - row * (CI / 8);
-    *(uint4*)&sw[row * CP + 8 * c8] = *(const uint4*)&w[(size_t)row * CI + 8 * c8];
-  }
+  stage_weights<CI, CO>(w, sw, tid);
   float s, th;
   lift_prepare<NBC>(b, R, coarse, theta, win, dyn, dyn + 12 * R * R, red, s, th);
   const float* feat = dyn + 12 * R * R;
@@ -381,53 +568,14 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
           }
         }
       }
-      *(uint4*)&sx[q * CP] = lo4;
-      *(uint4*)&sx[q * CP + 8] = hi4;
+      *(uint4*)&sx[lds_at<CI>(q, 0)] = lo4;
+      *(uint4*)&sx[lds_at<CI>(q, 1)] = hi4;
     }
     __syncthreads();
-    f32x4 acc[2][NBK];
-#pragma unroll
-    for (int mb = 0; mb < 2; mb++)
-#pragma unroll
-      for (int nb = 0; nb < NBK; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int kc = 0; kc < KCH; kc++) {
-      const int k0 = 32 * kc + 8 * (lane >> 4);
-      const bool kv = k0 < NTAP * CI;
-      const int tap = kv ? k0 / CI : 0, ci = kv ? k0 - tap * CI : 0;
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      bf16x8 a[2], bb[NBK];
-#pragma unroll
-      for (int mb = 0; mb < 2; mb++) {
-        const int px = px0 + 16 * mb + (lane & 15);
-        a[mb] = kv ? *(const bf16x8*)&sx[((r + 1 + dy) * (IMG + 2) + px + 1 + dx) * CP + ci]
-                   : bf16x8{};
-      }
-#pragma unroll
-      for (int nb = 0; nb < NBK; nb++) {
-        const int co = 16 * nb + (lane & 15);
-        bb[nb] = kv ? *(const bf16x8*)&sw[(tap * CO + co) * CP + ci] : bf16x8{};
-      }
-#pragma unroll
-      for (int mb = 0; mb < 2; mb++)
-#pragma unroll
-        for (int nb = 0; nb < NBK; nb++)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bb[nb], acc[mb][nb], 0, 0, 0);
-    }
-    const int y = y0 + r;
-#pragma unroll
-    for (int mb = 0; mb < 2; mb++)
-#pragma unroll
-      for (int nb = 0; nb < NBK; nb++) {
-        const int co = 16 * nb + (lane & 15);
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int px = px0 + 16 * mb + 4 * (lane >> 4) + j;
-          const size_t o = (((size_t)b * IMG + y) * IMG + px) * CO + co;
-          const float v = acc[mb][nb][j] + bias[co];
-          a1[o] = to_bf16(v > 0.0f ? v : 0.0f);
-        }
-      }
+    f32x4 acc[2][CO / 16];
+    const int row_at[3] = {r * (IMG + 2), (r + 1) * (IMG + 2), (r + 2) * (IMG + 2)};
+    conv_products<CI, CO, false>(sx, sw, row_at, px0, lane, acc);
+    store_row<CO, 0>(acc, b, y0 + r, px0, lane, bias, nullptr, a1);
   }
 }
 
@@ -445,7 +593,9 @@ constexpr int NBW = NTAP * 64;  // threads of the weight-gradient workgroup
 template <int CI, int CO>
 __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
                                               float* __restrict__ part, int n_rows) {
-  constexpr int PP = IMG + 8;                       // padded pixel stride
+  constexpr int PP = IMG + 16;                      // padded pixel stride: 160-byte rows, whose
+                                                    // 16-byte fragment reads (row l % 16, chunk
+                                                    // l / 16) meet no bank conflict (see lds_at)
   constexpr int MB = CO / 16, NBT = CI / 16;        // tiles of a tap: MB x NBT
   constexpr int XV = 3 * (IMG + 2) * (CI / 8);      // 8-channel vectors of the three x rows
   constexpr int DV = IMG * (CO / 8);                // 8-channel vectors of the dz row

@@ -58,6 +58,10 @@ def short_name(name: str) -> str:
             return name[i:i + 60].split("(")[0]
     # other kernels: the name without return type, namespace and argument list
     n = name.split("(")[0]
+    m = re.match(r"_ZN\d+\w*?(\d+)(\w+)", n)  # an unmangled-by-the-tool C++ name: its last component
+    if m and n.startswith("_ZN"):
+        k = int(m.group(1))
+        return m.group(2)[:k]
     n = n[5:] if n.startswith("void ") else n
     return n.split("::")[-1][:60] if "<" not in n else n[n.find("::") + 2:][:60]
 
