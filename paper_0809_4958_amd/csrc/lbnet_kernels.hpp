@@ -83,7 +83,10 @@ struct LiftWindow {
   int ns, k, dt;
 };
 
-// The sample's coarse values into cin [12 R R] and its features into feat
+// The sample's coarse values into cin [12 R R] and its features into feat,
+// node-major: feat[(v R + u) 12 + ch], ch = 3 grid + component (grids Sb,
+// Duu Sb, Dvv Sb, temporal difference), so a node's 12 features are three
+// 16-byte LDS reads
 // [12 R R] (block of NT threads, red: NT doubles of LDS); returns s (the RMS
 // of the coarse values, 1 if they are all zero) and theta.
 template <int NT>
@@ -122,20 +125,22 @@ __device__ __forceinline__ void lift_prepare(int b, int R, const float* __restri
     const int cmp = i / RR, vu = i - cmp * RR;
     const float sm = c[(0 * 3 + cmp) * RR + vu], s0 = c[(1 * 3 + cmp) * RR + vu];
     const float s1 = c[(2 * 3 + cmp) * RR + vu], s2 = c[(3 * 3 + cmp) * RR + vu];
-    feat[(0 * 3 + cmp) * RR + vu] = (1.0f - th) * s0 + th * s1;
-    feat[(3 * 3 + cmp) * RR + vu] = (s2 - s1) - (s0 - sm);
+    feat[vu * 12 + 0 * 3 + cmp] = (1.0f - th) * s0 + th * s1;
+    feat[vu * 12 + 3 * 3 + cmp] = (s2 - s1) - (s0 - sm);
   }
   __syncthreads();
   // second differences of Sb along u and v (edge nodes take the next node's)
   for (int i = tid; i < 3 * RR; i += NT) {
     const int cmp = i / RR, vu = i - cmp * RR;
     const int v = vu / R, u = vu - v * R;
-    const float* g = feat + cmp * RR;
+    const float* g = feat + cmp;  // Sb of component cmp, node stride 12
     const int uc = u < 1 ? 1 : (u > R - 2 ? R - 2 : u), vc = v < 1 ? 1 : (v > R - 2 ? R - 2 : v);
-    feat[(1 * 3 + cmp) * RR + vu] =
-        R >= 3 ? g[v * R + uc + 1] - 2.0f * g[v * R + uc] + g[v * R + uc - 1] : 0.0f;
-    feat[(2 * 3 + cmp) * RR + vu] =
-        R >= 3 ? g[(vc + 1) * R + u] - 2.0f * g[vc * R + u] + g[(vc - 1) * R + u] : 0.0f;
+    feat[vu * 12 + 1 * 3 + cmp] = R >= 3 ? g[(v * R + uc + 1) * 12] - 2.0f * g[(v * R + uc) * 12] +
+                                               g[(v * R + uc - 1) * 12]
+                                         : 0.0f;
+    feat[vu * 12 + 2 * 3 + cmp] = R >= 3 ? g[((vc + 1) * R + u) * 12] - 2.0f * g[(vc * R + u) * 12] +
+                                               g[((vc - 1) * R + u) * 12]
+                                         : 0.0f;
   }
   __syncthreads();
   s_out = s;
@@ -146,20 +151,25 @@ __device__ __forceinline__ void lift_prepare(int b, int R, const float* __restri
 // coarse field lifted[0..2] (the plain interpolation, the output's base).
 __device__ __forceinline__ void lift_pixel(const float* feat, int R, float s, float th, int u, int v,
                                            bf16x8& lo, bf16x8& hi, float base3[3]) {
-  const int RR = R * R;
   // corner-aligned bilinear weights (same integer mapping as the face grid)
   const int su = u * (R - 1), sv = v * (R - 1);
   const int pu = su / (IMG - 1), pv = sv / (IMG - 1);
   const float au = (float)(su - pu * (IMG - 1)) / (float)(IMG - 1);
   const float av = (float)(sv - pv * (IMG - 1)) / (float)(IMG - 1);
   const int pu1 = pu + 1 < R ? pu + 1 : pu, pv1 = pv + 1 < R ? pv + 1 : pv;
+  float c00[12], c01[12], c10[12], c11[12];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    *(float4*)&c00[4 * k] = *(const float4*)&feat[(pv * R + pu) * 12 + 4 * k];
+    *(float4*)&c01[4 * k] = *(const float4*)&feat[(pv * R + pu1) * 12 + 4 * k];
+    *(float4*)&c10[4 * k] = *(const float4*)&feat[(pv1 * R + pu) * 12 + 4 * k];
+    *(float4*)&c11[4 * k] = *(const float4*)&feat[(pv1 * R + pu1) * 12 + 4 * k];
+  }
   float lifted[12];
 #pragma unroll
-  for (int ch = 0; ch < 12; ch++) {
-    const float* g = feat + ch * RR;
-    lifted[ch] = (1.0f - au) * (1.0f - av) * g[pv * R + pu] + au * (1.0f - av) * g[pv * R + pu1] +
-                 (1.0f - au) * av * g[pv1 * R + pu] + au * av * g[pv1 * R + pu1];
-  }
+  for (int ch = 0; ch < 12; ch++)
+    lifted[ch] = (1.0f - au) * (1.0f - av) * c00[ch] + au * (1.0f - av) * c01[ch] + (1.0f - au) * av * c10[ch] +
+                 au * av * c11[ch];
 #pragma unroll
   for (int ch = 0; ch < 8; ch++) lo[ch] = to_bf16(lifted[ch] / s);
 #pragma unroll
@@ -536,7 +546,7 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
   __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CI];
   __shared__ __attribute__((aligned(16))) __bf16 sx[SR * (IMG + 2) * CI];
   __shared__ double red[NBC];
-  extern __shared__ float dyn[];
+  extern __shared__ __attribute__((aligned(16))) float dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = blockIdx.x / bands, band = blockIdx.x - b * bands;
   stage_weights<CI, CO>(w, sw, tid);
