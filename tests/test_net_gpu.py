@@ -71,6 +71,37 @@ def test_forward_matches_oracle(samples):
     net.close()
 
 
+def test_forward_is_independent_of_the_batch_split():
+    """Layers 2 and 3 walk bands of image rows whose number depends on the
+    batch (one band per image at 256 samples, two at 120, four at 64, sixteen
+    at 12 or 1); every output comes from the same products in the same order
+    whatever band computes it, so a sample's face field and layer-2
+    activations are bitwise the same in any batch."""
+    g = np.random.Generator(np.random.PCG64(5))
+    N = 256
+    c = (g.standard_normal((N, 4, 3, 8, 8)) * 1e-3).astype(np.float32)
+    th = g.random(N).astype(np.float32)
+    p = lbnet.init_params(2)
+    p[-(3 * 64 * 9 + 3):] = g.standard_normal(3 * 64 * 9 + 3) * 0.05
+    net = lbnet.Upsampler(coarse=8, max_batch=N)
+    net.set_params(p)
+    full = torch.zeros((N, 64, 64, 3), device="cuda")
+    say("case forward batch 256")
+    net.forward(dev(c), dev(th), full)
+    torch.cuda.synchronize()
+    full = full.cpu().numpy()
+    a2_full = net.read_buffer(lbnet.BUF_A2, N)
+    assert np.isfinite(full).all() and np.abs(full).max() > 0
+    for lo, n in ((0, 120), (120, 64), (184, 12), (255, 1)):
+        part = torch.zeros((n, 64, 64, 3), device="cuda")
+        say("case forward batch", n, "samples", lo, "..", lo + n - 1)
+        net.forward(dev(c[lo:lo + n]), dev(th[lo:lo + n]), part)
+        torch.cuda.synchronize()
+        assert np.array_equal(part.cpu().numpy(), full[lo:lo + n]), n
+        assert np.array_equal(net.read_buffer(lbnet.BUF_A2, n), a2_full[lo:lo + n]), n
+    net.close()
+
+
 def test_gradients_and_adam_match_oracle(samples):
     c, th, truth = samples
     B = 6
