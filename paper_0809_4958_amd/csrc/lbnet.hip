@@ -4,9 +4,10 @@
 // channel counts padded to the MFMA tiles with zero weights), the Adam
 // moments, the bfloat16 forward and backward-data weight copies, and the
 // activation and gradient buffers for max_batch samples.  A training step is
-// lift -> 3 convolutions -> loss -> per layer (weight gradient, backward data
-// through the ReLU) -> fixed-order reduction of the weight-gradient partials
-// -> Adam; every step is a kernel of lbnet_kernels.hpp on the context stream.
+// lift + layer 1 (k_head) -> layers 2 + 3 (k_conv23) -> loss -> per layer
+// (weight gradient, backward data through the ReLU) -> fixed-order reduction
+// of the weight-gradient partials -> Adam; every step is a kernel of
+// lbnet_kernels.hpp on the context stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -403,9 +403,10 @@ __global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, cons
 // both layers are staged once (159,744 bytes of LDS in all).  The layer-1
 // rows of the next step travel in registers one step ahead.  Layer-2 rows
 // outside the image are zero (layer 3's padding); the two layer-2 rows past
-// each end of a band are computed by both neighbours.  The products and
-// their order are those of k_conv<64, 64, 0> and k_conv<64, 16, EPI3>, so the
-// results are bitwise theirs.  a2_out != NULL also stores the band's
+// each end of a band are computed by both neighbours.  Each output is the
+// same chain of products (conv_products, chunks in order of increasing K) as
+// a convolution of one layer at a time would compute, so the results do not
+// depend on the band split or the fusion.  a2_out != NULL also stores the band's
 // layer-2 rows (the backward pass reads them).  EPI3: 1 (r) or 3 (u).
 template <int EPI3>
 __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, const __bf16* __restrict__ w2,
@@ -531,8 +532,8 @@ __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, c
 // The lift and layer 1 (16 -> 64, bias, ReLU) in one pass: workgroup
 // (sample b, band) forms the sample's coarse features once, then for each of
 // its 4-row tiles lifts the six staged input rows straight into LDS (zero
-// outside the image) and runs the products of k_conv<16, 64, 0> on them (the
-// same order, so a1 is bitwise what the two-kernel path gives).  It writes
+// outside the image) and runs conv_products on them (so a1 is bitwise what
+// a separate lift and convolution would give).  It writes
 // base and s, and x0 when x0 != NULL (training reads it; inference does not).
 // grid: B x bands, 16 / bands tiles per workgroup.
 __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
