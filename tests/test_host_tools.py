@@ -25,6 +25,18 @@ def test_code_only_ignores_comments_and_blank_lines():
     assert prof_summary._code_only("int a = 1;") != prof_summary._code_only("int a = 2;")
 
 
+def test_short_kernel_names():
+    """The summaries name kernels as the trace gives them, shortened: template
+    arguments of the step kernels kept, namespaces and argument lists
+    dropped, and a name the tool left mangled reduced to its last component."""
+    sn = prof_summary.short_name
+    assert sn("void k_lb<2, 1, false, 256, false, false>(LbArgs)") == "k_lb<2, 1, false, 256, false, false>"
+    assert sn("void lbnet::k_conv<64, 64, 2>(bool _Accum const*, _P, float const, bool _Accum const*)") == \
+        "k_conv<64, 64, 2>"
+    assert sn("lbnet::k_reduce_parts(float const*, int, int, float*)") == "k_reduce_parts"
+    assert sn("_ZN5lbnet6k_headEPKfS1_NS_10LiftWindowEiPKDF16bS1_PDF16bS5_PfS6_i") == "k_head"
+
+
 def test_kernel_source_hash_is_stable():
     h = prof_summary.kernel_source_hash()
     assert len(h) == 16 and all(ch in "0123456789abcdef" for ch in h)
