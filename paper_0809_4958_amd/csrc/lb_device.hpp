@@ -379,8 +379,11 @@ __device__ __forceinline__ void collide(R d[Q], R gx, R gy, R gz, R rho0, R omeg
 __device__ __forceinline__ void philox4x32(unsigned (&c)[4], unsigned k0, unsigned k1) {
 #pragma unroll
   for (int r = 0; r < 10; r++) {
-    const unsigned lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-    const unsigned lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    // each product whole (one v_mad_u64_u32, not a low and a high multiply)
+    const unsigned long long p0 = (unsigned long long)0xD2511F53u * c[0];
+    const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c[2];
+    const unsigned lo0 = (unsigned)p0, hi0 = (unsigned)(p0 >> 32);
+    const unsigned lo1 = (unsigned)p1, hi1 = (unsigned)(p1 >> 32);
     const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
     c[0] = n0;
     c[1] = lo1;

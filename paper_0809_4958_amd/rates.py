@@ -15,6 +15,13 @@ Workloads (MRT tau = 0.6, KS tracer boundary sampled on 17 x 17 faces every
                 of bond 0.8 (spring constant 0.003) instead of collapsed
                 coils: stencil boxes of 5-9 nodes per axis, the force pass's
                 heavy case
+  batch-f16-thermal
+                the benchmark's batch (FP16 storage, one 32-bead chain per box)
+                with thermal fluctuations (kT = 1e-5 in lattice units:
+                fluctuating MRT and bead Langevin noise, Philox draws) and the
+                accelerated-frame body force -rho dv/dt (a seeded tracer
+                acceleration history per box, rms 1e-6 per step^2, sampled
+                every 20 steps): the extended step kernels
   large-f16     512^3, FP16 storage, 32 chains of 256 beads (two buffers)
   large-f16-aa  the same on one buffer updated in place
   single-f32    128^3, FP32 storage, one 64-bead chain
@@ -48,7 +55,7 @@ def _chains_big(n, config_idx=4):
 
 def build(lbm, workload, steps, graph_steps):
     """Context of a workload and its interior node count."""
-    if workload in ("batch-f32", "batch-f16-extended"):
+    if workload in ("batch-f32", "batch-f16-extended", "batch-f16-thermal"):
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         if root not in sys.path:
             sys.path.insert(0, root)
@@ -57,6 +64,14 @@ def build(lbm, workload, steps, graph_steps):
         if workload == "batch-f32":
             ctx = bench.make_ctx(lbm, boxes, lbm.STORE_F32, TAU, reduce_every=100,
                                  graph_steps=graph_steps)
+            return ctx, float(sum((b["n"] - 2) ** 3 for b in boxes)), True
+        if workload == "batch-f16-thermal":
+            ctx = bench.make_ctx(lbm, boxes, lbm.STORE_F16DEV, TAU, reduce_every=100,
+                                 graph_steps=graph_steps)
+            n_samples = steps // 20 + 2
+            for k in range(len(boxes)):
+                ctx.set_body_force(k, inputs.rng(7, k).standard_normal((n_samples, 3)) * 1e-6, t0=0, dt=20)
+            ctx.set_thermal(1e-5, 2024)
             return ctx, float(sum((b["n"] - 2) ** 3 for b in boxes)), True
         ctx = lbm.Context([(b["n"],) * 3 for b in boxes], collision=lbm.MRT, tau=TAU, tau_bulk=TAU,
                           ghost_rate=1.0, storage=lbm.STORE_F16DEV, reduce_every=100,
