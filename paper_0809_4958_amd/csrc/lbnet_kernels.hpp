@@ -601,18 +601,41 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
 // tile count of a row or column).
 constexpr int NBW = NTAP * 64;  // threads of the weight-gradient workgroup
 
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// A K-major MFMA fragment from a row-major LDS tile t[k][n] (row stride ld
+// elements): lane l receives t[k0 + 8 (l / 16) + e][n0 + l % 16], e = 0..7, as
+// the eight K values of a 16x16x32 operand.  gfx950's transposing LDS read
+// (ds_read_b64_tr_b16) serves each group of 16 lanes: lane j of the group
+// names four consecutive values S[j][0..3], and lane i receives S[(i >> 2) +
+// 4 r][i & 3], r = 0..3 (measured on the device).  So lane j points at row
+// k + (j >> 2), columns n0 + 4 (j & 3), and two reads (rows k .. k+3, k+4 ..
+// k+7) make the fragment.
+__device__ __forceinline__ bf16x8 tr_frag(const __bf16* t, int ld, int k0, int n0, int lane) {
+  const int j = lane & 15, k = k0 + 8 * (lane >> 4) + (j >> 2), n = n0 + 4 * (j & 3);
+  typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+  const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(t + k * ld + n));
+  const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(t + (k + 4) * ld + n));
+  // rows k .. k+3 in elements 0..3, k+4 .. k+7 in 4..7 (native vector types
+  // only: the HIP vector structs are unions and do not carry the bits)
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 template <int CI, int CO>
 __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
                                               float* __restrict__ part, int n_rows) {
-  constexpr int PP = IMG + 16;                      // padded pixel stride: 160-byte rows, whose
-                                                    // 16-byte fragment reads (row l % 16, chunk
-                                                    // l / 16) meet no bank conflict (see lds_at)
+  // x rows y-1 .. y+1 and the dz row staged as they lie in memory (pixel-major,
+  // channels contiguous; x with a zero pixel on either side); the products read
+  // both K-major (K = pixels) through tr_frag, and the tap's dx is a row offset
   constexpr int MB = CO / 16, NBT = CI / 16;        // tiles of a tap: MB x NBT
-  constexpr int XV = 3 * (IMG + 2) * (CI / 8);      // 8-channel vectors of the three x rows
+  constexpr int XW = IMG + 2;                       // staged pixels of an x row
+  constexpr int XV = 3 * XW * (CI / 8);             // 8-channel vectors of the three x rows
   constexpr int DV = IMG * (CO / 8);                // 8-channel vectors of the dz row
   constexpr int XS = (XV + NBW - 1) / NBW, DS = (DV + NBW - 1) / NBW;
-  __shared__ __attribute__((aligned(16))) __bf16 sdz[CO * PP];          // [co][px]
-  __shared__ __attribute__((aligned(16))) __bf16 sxs[NTAP * CI * PP];  // [dx][dy][ci][px]
+  // two LDS copies of the tiles: row r + 1 is staged into one while row r is
+  // multiplied from the other, one barrier per row
+  __shared__ __attribute__((aligned(16))) __bf16 sdz[2][IMG * CO];     // [px][co]
+  __shared__ __attribute__((aligned(16))) __bf16 sxr[2][3 * XW * CI];  // [dy][px + 1][ci]
   const int tid = threadIdx.x, lane = tid & 63, tap = tid >> 6;
   const int dyi = tap / 3, dxi = tap % 3;
   f32x4 acc[MB][NBT];
@@ -621,7 +644,7 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
 #pragma unroll
     for (int nb = 0; nb < NBT; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   float db = 0.0f;
-  // the next row's vectors travel in registers while the current row computes
+  // the row after the one being staged travels in registers
   uint4 xr[XS], dr[DS];
   auto load_row = [&](int row) {
     const int b = row / IMG, y = row - b * IMG;
@@ -630,9 +653,8 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
       const int v = tid + j * NBW;
       xr[j] = make_uint4(0u, 0u, 0u, 0u);
       if (v < XV) {
-        // pixel fastest: neighbouring lanes fill neighbouring LDS columns
-        const int xx = v % (IMG + 2) - 1, q = v / (IMG + 2);
-        const int c8 = q % (CI / 8), dyr = q / (CI / 8), yy = y + dyr - 1;
+        const int c8 = v % (CI / 8), q = v / (CI / 8);
+        const int xx = q % XW - 1, dyr = q / XW, yy = y + dyr - 1;
         if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
           xr[j] = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
       }
@@ -641,64 +663,56 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
     for (int j = 0; j < DS; j++) {
       const int v = tid + j * NBW;
       dr[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (v < DV) {
-        const int px = v % IMG, c8 = v / IMG;
-        dr[j] = *(const uint4*)&dz[(((size_t)b * IMG + y) * IMG + px) * CO + 8 * c8];
-      }
+      if (v < DV) dr[j] = *(const uint4*)&dz[((size_t)row * IMG) * CO + 8 * v];
     }
   };
-  if ((int)blockIdx.x < n_rows) load_row(blockIdx.x);
-  for (int row = blockIdx.x; row < n_rows; row += gridDim.x) {
-    __syncthreads();  // previous row's reads of the LDS tiles are done
-    // x rows y-1 .. y+1 transposed to [ci][px], once per dx shift: element xx
-    // feeds output pixel px = xx - dx; every (dx, dy, ci, px) slot has exactly
-    // one source xx = px + dx in -1 .. 64
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < XS; j++) {
       const int v = tid + j * NBW;
-      if (v >= XV) continue;
-      const int xx = v % (IMG + 2) - 1, q = v / (IMG + 2);
-      const int c8 = q % (CI / 8), dyr = q / (CI / 8);
-      const __bf16* e = (const __bf16*)&xr[j];
-#pragma unroll
-      for (int dxr = 0; dxr < 3; dxr++) {
-        const int px = xx - (dxr - 1);
-        if (px < 0 || px >= IMG) continue;
-#pragma unroll
-        for (int k = 0; k < 8; k++) sxs[((dxr * 3 + dyr) * CI + 8 * c8 + k) * PP + px] = e[k];
-      }
+      if (v < XV) *(uint4*)&sxr[buf][8 * v] = xr[j];
     }
 #pragma unroll
     for (int j = 0; j < DS; j++) {
       const int v = tid + j * NBW;
-      if (v >= DV) continue;
-      const int px = v % IMG, c8 = v / IMG;
-      const __bf16* e = (const __bf16*)&dr[j];
-#pragma unroll
-      for (int k = 0; k < 8; k++) sdz[(8 * c8 + k) * PP + px] = e[k];
+      if (v < DV) *(uint4*)&sdz[buf][8 * v] = dr[j];
     }
-    __syncthreads();
-    if (row + (int)gridDim.x < n_rows) load_row(row + gridDim.x);
+  };
+  const int g0 = blockIdx.x, gs = gridDim.x;
+  if (g0 < n_rows) {
+    load_row(g0);
+    stage(0);
+    if (g0 + gs < n_rows) load_row(g0 + gs);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int row = g0; row < n_rows; row += gs, buf ^= 1) {
+    if (row + gs < n_rows) {
+      stage(buf ^ 1);  // the next row; its buffer was last read before the previous barrier
+      if (row + 2 * gs < n_rows) load_row(row + 2 * gs);
+    }
+    const __bf16* tz = sdz[buf];
     if (tid < CO) {
       float s = 0.0f;
-      for (int px = 0; px < IMG; px++) s += from_bf16(sdz[tid * PP + px]);
+      for (int px = 0; px < IMG; px++) s += from_bf16(tz[px * CO + tid]);
       db += s;
     }
+    // x row dyi, pixel p + dxi - 1 sits at staged pixel p + dxi
+    const __bf16* xt = sxr[buf] + (dyi * XW + dxi) * CI;
 #pragma unroll
     for (int kc = 0; kc < IMG / 32; kc++) {
-      const int p0 = 32 * kc + 8 * (lane >> 4);
       bf16x8 a[MB], bv[NBT];
 #pragma unroll
-      for (int mb = 0; mb < MB; mb++) a[mb] = *(const bf16x8*)&sdz[(16 * mb + (lane & 15)) * PP + p0];
+      for (int mb = 0; mb < MB; mb++) a[mb] = tr_frag(tz, CO, 32 * kc, 16 * mb, lane);
 #pragma unroll
-      for (int nb = 0; nb < NBT; nb++)
-        bv[nb] = *(const bf16x8*)&sxs[((dxi * 3 + dyi) * CI + 16 * nb + (lane & 15)) * PP + p0];
+      for (int nb = 0; nb < NBT; nb++) bv[nb] = tr_frag(xt, CI, 32 * kc, 16 * nb, lane);
 #pragma unroll
       for (int mb = 0; mb < MB; mb++)
 #pragma unroll
         for (int nb = 0; nb < NBT; nb++)
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bv[nb], acc[mb][nb], 0, 0, 0);
     }
+    __syncthreads();  // this row's reads done; the next row's tiles are in
   }
   float* pg = part + (size_t)blockIdx.x * (NTAP * CO * CI + CO);
 #pragma unroll
