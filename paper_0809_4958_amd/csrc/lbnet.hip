@@ -152,6 +152,9 @@ lb_status prep_weights(lbn_ctx* ctx) {
   return LB_OK;
 }
 
+// workgroups (and partials) of a weight-gradient launch
+int wgrad_grid(int batch) { return std::min(batch * IMG, MAX_PART); }
+
 // bands per image of a convolution launch (one workgroup per band): the
 // fewest (a power of two, at most 64 / TR) for which the grid reaches about
 // per_cu workgroups per compute unit (per_cu by LDS and register use)
@@ -191,22 +194,28 @@ lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int bat
   return LB_OK;
 }
 
-// weight and bias gradient of one layer into ctx->g (fixed-order reduction)
+// partial weight and bias gradients of one layer: workgroup g writes its
+// partial into row g of ctx->part (NDEV values per row, each layer at its
+// parameter offset, the biases after the weights as in the parameters)
 template <int CI, int CO>
 lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size_t off_w, size_t off_b) {
   const int rows = batch * IMG;
-  const int grid = std::min(rows, MAX_PART);
-  hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(grid), dim3(NBW), 0, st, x, dz, ctx->part, rows);
-  // two fixed-order stages: RSEG ranges of partials in parallel, then their
-  // sum; weights and biases together (the biases follow the weights, in the
-  // partials as in the parameters)
-  const int nw = NTAP * CO * CI + CO;
   (void)off_b;  // == off_w + 9 CO CI
-  hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, nw,
+  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(wgrad_grid(batch)), dim3(NBW), 0, ctx->stream, x, dz,
+                     ctx->part + off_w, (int)NDEV, rows);
+  HIPCHK(hipGetLastError());
+  return LB_OK;
+}
+
+// every layer's partials summed into ctx->g in two fixed-order stages: RSEG
+// ranges of partials in parallel, then their sum (each parameter's sum is
+// the same sequence as a reduction of its layer alone)
+lb_status reduce_grads(lbn_ctx* ctx, int batch) {
+  const int n = (int)NDEV, grid = wgrad_grid(batch);
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, n,
                      ctx->part_seg);
-  hipLaunchKernelGGL(k_reduce_parts, dim3((nw + 255) / 256), dim3(256), 0, st, ctx->part_seg, RSEG, nw,
-                     ctx->g + off_w);
+  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256), dim3(256), 0, st, ctx->part_seg, RSEG, n, ctx->g);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
@@ -251,8 +260,8 @@ lb_status lbn_init(const lbn_config* cfg, lbn_ctx** out) {
   ctx->r = dalloc_t<float>(ctx, px * COUT, &ok);
   ctx->base = dalloc_t<float>(ctx, px * 3, &ok);
   ctx->scale = dalloc_t<float>(ctx, B, &ok);
-  ctx->part = dalloc_t<float>(ctx, (size_t)MAX_PART * (NTAP * CH * CH + CH), &ok);
-  ctx->part_seg = dalloc_t<float>(ctx, (size_t)RSEG * (NTAP * CH * CH + CH), &ok);
+  ctx->part = dalloc_t<float>(ctx, (size_t)MAX_PART * NDEV, &ok);
+  ctx->part_seg = dalloc_t<float>(ctx, (size_t)RSEG * NDEV, &ok);
   ctx->loss_part = dalloc_t<double>(ctx, 1024, &ok);
   if (!ok) {
     lbn_free(ctx);
@@ -346,7 +355,7 @@ lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* thet
                      ctx->a1, ctx->dz1, b1);
   // layer 1
   if ((s = wgrad<CIN, CH>(ctx, ctx->x0, ctx->dz1, batch, OFF_W1, OFF_B1))) return s;
-  HIPCHK(hipGetLastError());
+  if ((s = reduce_grads(ctx, batch))) return s;
   ctx->has_grad = true;
   if (loss) {
     std::vector<double> part(lgrid);

@@ -593,8 +593,9 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
 // ---------------------------------------------------------------- weight gradient
 // dW[tap][co][ci] = sum_p dz[p][co] x[p + off(tap)][ci], db[co] = sum_p dz[p][co]
 // over the image rows g, g + gridDim.x, ... of workgroup g; one partial per
-// workgroup, part[g][9 CO CI + CO] (the weights, then the biases: the layout
-// of the layer's parameters), summed in a fixed order by k_reduce_parts.
+// workgroup at part + g pstride: 9 CO CI + CO values (the weights, then the
+// biases: the layout of the layer's parameters), summed in a fixed order by
+// k_reduce_parts.
 // Nine waves, one per tap: a wave holds all (CO/16) x (CI/16) output tiles of
 // its tap, so each pixel chunk's dz and x fragments are loaded from LDS once
 // and used by every tile they meet (the LDS reads per product fall by the
@@ -623,7 +624,7 @@ __device__ __forceinline__ bf16x8 tr_frag(const __bf16* t, int ld, int k0, int n
 
 template <int CI, int CO>
 __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
-                                              float* __restrict__ part, int n_rows) {
+                                              float* __restrict__ part, int pstride, int n_rows) {
   // x rows y-1 .. y+1 and the dz row staged as they lie in memory (pixel-major,
   // channels contiguous; x with a zero pixel on either side); the products read
   // both K-major (K = pixels) through tr_frag, and the tap's dx is a row offset
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
     }
     __syncthreads();  // this row's reads done; the next row's tiles are in
   }
-  float* pg = part + (size_t)blockIdx.x * (NTAP * CO * CI + CO);
+  float* pg = part + (size_t)blockIdx.x * pstride;
 #pragma unroll
   for (int mb = 0; mb < MB; mb++)
 #pragma unroll
