@@ -4,9 +4,10 @@
 // channel counts padded to the MFMA tiles with zero weights), the Adam
 // moments, the bfloat16 forward and backward-data weight copies, and the
 // activation and gradient buffers for max_batch samples.  A training step is
-// lift + layer 1 (k_head) -> layers 2 + 3 (k_conv23) -> loss -> per layer
-// (weight gradient, backward data through the ReLU) -> fixed-order reduction
-// of the weight-gradient partials -> Adam; every step is a kernel of
+// lift + layer 1 (k_head) -> layers 2 + 3 (k_conv23) -> loss -> weight
+// gradients of the three layers (k_wgrad) around the data gradients of layers
+// 3 and 2 through their ReLUs (k_back32) -> one fixed-order reduction of the
+// weight-gradient partials -> Adam; every step is a kernel of
 // lbnet_kernels.hpp on the context stream.
 #include <hip/hip_runtime.h>
 
@@ -344,15 +345,14 @@ lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* thet
   hipLaunchKernelGGL(k_loss, dim3(lgrid), dim3(NB), 0, st, ctx->r, ctx->base, ctx->scale, truth_dev, n_px,
                      inv_count, ctx->dy, ctx->loss_part);
   HIPCHK(hipGetLastError());
-  const int b1 = conv_bands(batch, 1), b2 = conv_bands(batch, 2);
-  // layer 3: weights from (a2, dy); data gradient through ReLU(a2)
+  const int b1 = conv_bands(batch, 1);
+  // layer 3: weights from (a2, dy)
   if ((s = wgrad<CH, COUT>(ctx, ctx->a2, ctx->dy, batch, OFF_W3, OFF_B3))) return s;
-  hipLaunchKernelGGL((k_conv<COUT, CH, 2>), dim3(batch * b2), dim3(NBC), 0, st, ctx->dy, ctx->w3t, nullptr,
-                     ctx->a2, ctx->dz2, b2);
+  // data gradients through ReLU(a2) and ReLU(a1) in one pass
+  hipLaunchKernelGGL(k_back32, dim3(batch * b1), dim3(NBC), 0, st, ctx->dy, ctx->w3t, ctx->w2t, ctx->a2, ctx->a1,
+                     ctx->dz2, ctx->dz1, b1);
   // layer 2
   if ((s = wgrad<CH, CH>(ctx, ctx->a1, ctx->dz2, batch, OFF_W2, OFF_B2))) return s;
-  hipLaunchKernelGGL((k_conv<CH, CH, 2>), dim3(batch * b1), dim3(NBC), 0, st, ctx->dz2, ctx->w2t, nullptr,
-                     ctx->a1, ctx->dz1, b1);
   // layer 1
   if ((s = wgrad<CIN, CH>(ctx, ctx->x0, ctx->dz1, batch, OFF_W1, OFF_B1))) return s;
   if ((s = reduce_grads(ctx, batch))) return s;

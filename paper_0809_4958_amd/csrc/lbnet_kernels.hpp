@@ -199,32 +199,18 @@ template <int CO>
 __device__ __forceinline__ int first_co(int lane) { return (CO == 64 ? 16 : 4) * (lane >> 4); }
 
 // Epilogue of one pixel's NC = 4 NBK consecutive channels c0 .. c0 + NC - 1
-// (v[q] = channel c0 + q) at pixel index p (b * 64 + y) * 64 + x, to bf16:
-// EPI 0 = bias + ReLU; 2 = no bias, times the mask (mask_src > 0; backward
-// data through a ReLU).
-template <int CO, int EPI, int NC>
+// (v[q] = channel c0 + q) at pixel index p (b * 64 + y) * 64 + x: bias + ReLU
+// -> bf16, whole 16- or 8-byte vectors.
+template <int CO, int NC>
 __device__ __forceinline__ void store_pixel(const float (&v)[NC], size_t p, int c0,
-                                            const float* __restrict__ bias,
-                                            const __bf16* __restrict__ mask_src, __bf16* __restrict__ out) {
-  static_assert(EPI == 0 || EPI == 2, "bf16 epilogues");
+                                            const float* __restrict__ bias, __bf16* __restrict__ out) {
   constexpr int VS = NC >= 8 ? 8 : NC;  // bf16 values per vector access
   const size_t o = p * CO + c0;
   __bf16 h[NC];
-  if constexpr (EPI == 0) {
 #pragma unroll
-    for (int q = 0; q < NC; q++) {
-      const float t = v[q] + bias[c0 + q];
-      h[q] = to_bf16(t > 0.0f ? t : 0.0f);
-    }
-  } else {
-    __bf16 m[NC];
-#pragma unroll
-    for (int q = 0; q < NC; q += VS) {
-      if constexpr (VS == 8) *(uint4*)&m[q] = *(const uint4*)&mask_src[o + q];
-      else *(uint2*)&m[q] = *(const uint2*)&mask_src[o + q];
-    }
-#pragma unroll
-    for (int q = 0; q < NC; q++) h[q] = to_bf16(from_bf16(m[q]) > 0.0f ? v[q] : 0.0f);
+  for (int q = 0; q < NC; q++) {
+    const float t = v[q] + bias[c0 + q];
+    h[q] = to_bf16(t > 0.0f ? t : 0.0f);
   }
 #pragma unroll
   for (int q = 0; q < NC; q += VS) {
@@ -302,10 +288,9 @@ __device__ __forceinline__ void stage_weights(const __bf16* __restrict__ w, __bf
 }
 
 // The epilogue of a wave's tile row: pixels px0 .. px0 + 31 of image row y.
-template <int CO, int EPI, int MB = 2>
+template <int CO, int MB = 2>
 __device__ __forceinline__ void store_row(const f32x4 (&acc)[MB][CO / 16], int b, int y, int px0, int lane,
-                                          const float* __restrict__ bias, const __bf16* __restrict__ mask_src,
-                                          __bf16* __restrict__ out) {
+                                          const float* __restrict__ bias, __bf16* __restrict__ out) {
   constexpr int NBK = CO / 16, NC = 4 * NBK;
   const int c0 = first_co<CO>(lane);
 #pragma unroll
@@ -316,79 +301,7 @@ __device__ __forceinline__ void store_row(const f32x4 (&acc)[MB][CO / 16], int b
 #pragma unroll
       for (int j = 0; j < 4; j++) v[4 * nb + j] = acc[mb][nb][j];
     const int px = px0 + 16 * mb + (lane & 15);
-    store_pixel<CO, EPI, NC>(v, ((size_t)b * IMG + y) * IMG + px, c0, bias, mask_src, out);
-  }
-}
-
-// Implicit-GEMM 3x3 convolution, epilogue EPI as in store_pixel.  Workgroup
-// g convolves the 64 / bands rows of band g % bands of image g / bands, TR
-// rows per tile (eight waves, each 32 pixels x CO of one row).  The input
-// rows live in a ring of RS = 2 TR + 2 LDS row slots (image row yy in slot
-// (yy + 1) % RS; rows outside the image are zero): a tile reads rows y0 - 1
-// .. y0 + TR, and the TR rows the next tile adds, loaded from memory one
-// tile ahead, go into the other slots after the tile's products, so each
-// input row is loaded once per band (plus two halo rows) and one barrier per
-// tile suffices.
-template <int CI, int CO, int EPI>
-__global__ __launch_bounds__(NBC) void k_conv(const __bf16* __restrict__ x, const __bf16* __restrict__ w,
-                                              const float* __restrict__ bias,
-                                              const __bf16* __restrict__ mask_src, __bf16* __restrict__ out,
-                                              int bands) {
-  constexpr int RS = 2 * TR + 2;              // ring row slots
-  constexpr int RV = (IMG + 2) * (CI / 8);    // 16-byte vectors of one staged row
-  constexpr int XS = (TR * RV + NBC - 1) / NBC;
-  __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CI];
-  __shared__ __attribute__((aligned(16))) __bf16 sx[RS * (IMG + 2) * CI];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int b = blockIdx.x / bands, band = blockIdx.x - b * bands;
-  const int rows = IMG / bands, ybeg = band * rows;
-  stage_weights<CI, CO>(w, sw, tid);
-  // image rows y .. y + n - 1 (n <= TR) into registers, then into the ring
-  uint4 xr[XS];
-  auto load_rows = [&](int y, int n) {
-#pragma unroll
-    for (int j = 0; j < XS; j++) {
-      const int v = tid + j * NBC;
-      xr[j] = make_uint4(0u, 0u, 0u, 0u);
-      if (v < n * RV) {
-        const int c8 = v % (CI / 8), q = v / (CI / 8);
-        const int xx = q % (IMG + 2) - 1, yy = y + q / (IMG + 2);
-        if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
-          xr[j] = *(const uint4*)&x[(((size_t)b * IMG + yy) * IMG + xx) * CI + 8 * c8];
-      }
-    }
-  };
-  auto put_rows = [&](int y, int n) {
-#pragma unroll
-    for (int j = 0; j < XS; j++) {
-      const int v = tid + j * NBC;
-      if (v < n * RV) {
-        const int c8 = v % (CI / 8), q = v / (CI / 8);
-        const int col = q % (IMG + 2), yy = y + q / (IMG + 2);
-        *(uint4*)&sx[lds_at<CI>(((yy + 1) % RS) * (IMG + 2) + col, c8)] = xr[j];
-      }
-    }
-  };
-  const int r = wave >> 1, px0 = (wave & 1) * 32;
-  const int ntiles = rows / TR;
-  // the first tile's TR + 2 rows, then the second tile's new rows in flight
-  load_rows(ybeg - 1, TR);
-  put_rows(ybeg - 1, TR);
-  load_rows(ybeg + TR - 1, 2);
-  put_rows(ybeg + TR - 1, 2);
-  if (ntiles > 1) load_rows(ybeg + TR + 1, TR);
-  __syncthreads();
-  for (int i = 0; i < ntiles; i++) {
-    const int y0 = ybeg + TR * i, y = y0 + r;
-    const int row_at[3] = {(y % RS) * (IMG + 2), ((y + 1) % RS) * (IMG + 2), ((y + 2) % RS) * (IMG + 2)};
-    f32x4 acc[2][CO / 16];
-    conv_products<CI, CO>(sx, sw, row_at, px0, lane, acc);
-    if (i + 1 < ntiles) {
-      put_rows(y0 + TR + 1, TR);
-      if (i + 2 < ntiles) load_rows(y0 + 2 * TR + 1, TR);
-    }
-    store_row<CO, EPI>(acc, b, y, px0, lane, bias, mask_src, out);
-    __syncthreads();  // the next tile's rows are in; this tile's slots are free
+    store_pixel<CO, NC>(v, ((size_t)b * IMG + y) * IMG + px, c0, bias, out);
   }
 }
 
@@ -528,6 +441,118 @@ __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, c
   }
 }
 
+// ---------------------------------------------------------------- backward data, layers 3 + 2
+// The data gradients of layers 3 and 2 in one pass (the mirror of k_conv23):
+// dz2 = [a2 > 0] (dy conv w3t) (16 -> 64) and dz1 = [a1 > 0] (dz2 conv w2t)
+// (64 -> 64), bf16, no bias.  Workgroup g walks the 64 / bands rows [yb, ye)
+// of band g % bands of image g / bands in steps of two rows: step s makes
+// dz2 rows ya, ya + 1 (ya = yb - 1 + 2 s) from dy rows ya - 1 .. ya + 2, then
+// (s >= 1) dz1 rows ya - 1, ya from dz2 rows ya - 2 .. ya + 1.  dy and dz2
+// live in LDS rings of four rows (row yy in slot (yy + 4) % 4, 66 pixels with
+// a zero halo); dz2 rows outside the image are zero (the padding of the second
+// convolution); the band's own dz2 rows are also stored (the weight gradient
+// of layer 2 reads them).  Each output is the same chain of products as a
+// convolution of one layer at a time, so the results are bitwise those.
+__global__ __launch_bounds__(NBC) void k_back32(const __bf16* __restrict__ dy, const __bf16* __restrict__ w3t,
+                                                const __bf16* __restrict__ w2t, const __bf16* __restrict__ a2,
+                                                const __bf16* __restrict__ a1, __bf16* __restrict__ dz2,
+                                                __bf16* __restrict__ dz1, int bands) {
+  constexpr int CA = COUT, C = CH, RW = IMG + 2;   // dy channels, hidden channels, staged row
+  constexpr int RV = RW * (CA / 8);                // 16-byte vectors of one staged dy row
+  constexpr int XS = (2 * RV + NBC - 1) / NBC;
+  __shared__ __attribute__((aligned(16))) __bf16 s_wa[NTAP * C * CA];
+  __shared__ __attribute__((aligned(16))) __bf16 s_wb[NTAP * C * C];
+  __shared__ __attribute__((aligned(16))) __bf16 s_dy[4 * RW * CA];
+  __shared__ __attribute__((aligned(16))) __bf16 s_dz[4 * RW * C];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b = blockIdx.x / bands, band = blockIdx.x - b * bands;
+  const int rows = IMG / bands, yb = band * rows, ye = yb + rows;
+  stage_weights<CA, C>(w3t, s_wa, tid);
+  stage_weights<C, C>(w2t, s_wb, tid);
+  for (int i = tid; i < 4 * RW * (C / 8); i += NBC) *(uint4*)&s_dz[8 * i] = make_uint4(0u, 0u, 0u, 0u);
+  uint4 xr[XS];
+  auto load_rows = [&](int y) {  // dy rows y, y + 1 into registers
+#pragma unroll
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NBC;
+      xr[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (v < 2 * RV) {
+        const int c8 = v % (CA / 8), q = v / (CA / 8);
+        const int xx = q % RW - 1, yy = y + q / RW;
+        if (yy >= 0 && yy < IMG && xx >= 0 && xx < IMG)
+          xr[j] = *(const uint4*)&dy[(((size_t)b * IMG + yy) * IMG + xx) * CA + 8 * c8];
+      }
+    }
+  };
+  auto put_rows = [&](int y) {
+#pragma unroll
+    for (int j = 0; j < XS; j++) {
+      const int v = tid + j * NBC;
+      if (v < 2 * RV) {
+        const int c8 = v % (CA / 8), q = v / (CA / 8);
+        const int yy = y + q / RW;
+        *(uint4*)&s_dy[lds_at<CA>(((yy + 4) & 3) * RW + q % RW, c8)] = xr[j];
+      }
+    }
+  };
+  load_rows(yb - 2);
+  put_rows(yb - 2);
+  load_rows(yb);
+  put_rows(yb);
+  load_rows(yb + 2);
+  // both convolutions: wave = (row r, pixel half, channel half), 32 x 32 outputs
+  const int r = wave >> 2, q = wave & 3, px0 = 32 * (q & 1), nb0 = 2 * (q >> 1);
+  const int g = lane >> 4, c0 = 16 * g + 8 * (q >> 1);  // the 8 channels a lane holds
+  // masked bf16 of a lane's 8 channels of pixel px of row y (mask row of m)
+  auto masked = [&](const f32x4 (&acc)[2][2], int mb, const __bf16* __restrict__ m, int y, int px) {
+    const uint4 mv = *(const uint4*)&m[(((size_t)b * IMG + y) * IMG + px) * C + c0];
+    const __bf16* me = (const __bf16*)&mv;
+    __bf16 h[8];
+#pragma unroll
+    for (int nb = 0; nb < 2; nb++)
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        h[4 * nb + j] = to_bf16(from_bf16(me[4 * nb + j]) > 0.0f ? acc[mb][nb][j] : 0.0f);
+    return *(const uint4*)h;
+  };
+  __syncthreads();
+  const int nsteps = rows / 2 + 1;
+  for (int st = 0; st < nsteps; st++) {
+    const int ya = yb - 1 + 2 * st;
+    {
+      const int y = ya + r;  // dz2 row of this wave
+      const int row_at[3] = {((y + 3) & 3) * RW, ((y + 4) & 3) * RW, ((y + 5) & 3) * RW};
+      f32x4 acc[2][2];
+      conv_products<CA, C, true, 2, 2>(s_dy, s_wa, row_at, px0, lane, acc, nb0);
+      const bool inside = y >= 0 && y < IMG;
+#pragma unroll
+      for (int mb = 0; mb < 2; mb++) {
+        const int px = px0 + 16 * mb + (lane & 15);
+        const uint4 hv = inside ? masked(acc, mb, a2, y, px) : make_uint4(0u, 0u, 0u, 0u);
+        *(uint4*)&s_dz[lds_at<C>(((y + 4) & 3) * RW + px + 1, c0 >> 3)] = hv;
+        if (y >= yb && y < ye) *(uint4*)&dz2[(((size_t)b * IMG + y) * IMG + px) * C + c0] = hv;
+      }
+    }
+    __syncthreads();  // dz2 rows ya, ya + 1 in; dy rows ya - 1, ya free
+    if (st + 1 < nsteps) {
+      put_rows(ya + 3);
+      if (st + 2 < nsteps) load_rows(ya + 5);
+    }
+    if (st >= 1) {
+      const int y = ya - 1 + r;  // dz1 row of this wave
+      const int row_at[3] = {((y + 3) & 3) * RW, ((y + 4) & 3) * RW, ((y + 5) & 3) * RW};
+      f32x4 acc[2][2];
+      conv_products<C, C, true, 2, 2>(s_dz, s_wb, row_at, px0, lane, acc, nb0);
+#pragma unroll
+      for (int mb = 0; mb < 2; mb++) {
+        const int px = px0 + 16 * mb + (lane & 15);
+        *(uint4*)&dz1[(((size_t)b * IMG + y) * IMG + px) * C + c0] = masked(acc, mb, a1, y, px);
+      }
+    }
+    __syncthreads();  // dy rows of the next step in; the reads of s_dz done
+  }
+}
+
 // ---------------------------------------------------------------- head
 // The lift and layer 1 (16 -> 64, bias, ReLU) in one pass: workgroup
 // (sample b, band) forms the sample's coarse features once, then for each of
@@ -586,7 +611,7 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
     f32x4 acc[2][CO / 16];
     const int row_at[3] = {r * (IMG + 2), (r + 1) * (IMG + 2), (r + 2) * (IMG + 2)};
     conv_products<CI, CO, false>(sx, sw, row_at, px0, lane, acc);
-    store_row<CO, 0>(acc, b, y0 + r, px0, lane, bias, nullptr, a1);
+    store_row<CO>(acc, b, y0 + r, px0, lane, bias, a1);
   }
 }
 
