@@ -139,15 +139,20 @@ void dev_to_params(const std::vector<float>& dev, float* out) {
   std::memcpy(q, dev.data() + OFF_B3, OUT_USED * sizeof(float));
 }
 
+// the three layers' weights and their bf16 copies
+PrepLayers prep_layers(lbn_ctx* ctx) {
+  return PrepLayers{{ctx->p + OFF_W1, ctx->p + OFF_W2, ctx->p + OFF_W3},
+                    {ctx->w1f, ctx->w2f, ctx->w3f},
+                    {ctx->w1t, ctx->w2t, ctx->w3t},
+                    {CH, CH, COUT},
+                    {CIN, CH, CH},
+                    {(int)OFF_W1, (int)OFF_W2, (int)OFF_W3}};
+}
+
 lb_status prep_weights(lbn_ctx* ctx) {
   if (!ctx->weights_dirty) return LB_OK;
-  const PrepLayers L{{ctx->p + OFF_W1, ctx->p + OFF_W2, ctx->p + OFF_W3},
-                     {ctx->w1f, ctx->w2f, ctx->w3f},
-                     {ctx->w1t, ctx->w2t, ctx->w3t},
-                     {CH, CH, COUT},
-                     {CIN, CH, CH}};
   const int n = (int)(W1N + W2N + W3N);
-  hipLaunchKernelGGL(k_prep_weights, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, L);
+  hipLaunchKernelGGL(k_prep_weights, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, prep_layers(ctx));
   HIPCHK(hipGetLastError());
   ctx->weights_dirty = false;
   return LB_OK;
@@ -382,10 +387,11 @@ lb_status lbn_adam_step(lbn_ctx* ctx, float lr, float beta1, float beta2, float 
   ctx->adam_t++;
   const float c1 = 1.0f - (float)std::pow((double)beta1, ctx->adam_t);
   const float c2 = 1.0f - (float)std::pow((double)beta2, ctx->adam_t);
+  // the step also writes the bf16 copies of the updated weights
   hipLaunchKernelGGL(k_adam, dim3((NDEV + 255) / 256), dim3(256), 0, ctx->stream, ctx->p, ctx->m, ctx->v,
-                     ctx->g, (int)NDEV, lr, beta1, beta2, eps, c1, c2);
+                     ctx->g, (int)NDEV, lr, beta1, beta2, eps, c1, c2, prep_layers(ctx));
   HIPCHK(hipGetLastError());
-  ctx->weights_dirty = true;
+  ctx->weights_dirty = false;
   return LB_OK;
 }
 

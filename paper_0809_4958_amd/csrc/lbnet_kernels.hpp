@@ -817,9 +817,31 @@ __global__ void k_combine(const float* __restrict__ r, const float* __restrict__
 // Adam (Kingma and Ba) on the FP32 master parameters, bias-corrected with
 // step t: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
 // p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+struct PrepLayers {
+  const float* w[3];
+  __bf16* wf[3];
+  __bf16* wt[3];
+  int co[3], ci[3];
+  int off[3];  // offset of each layer's weights in the parameter vector
+};
+
+// The bf16 copies of weight i of layer l ([tap][co][ci]): the forward copy
+// in the same layout, and the backward-data copy with the tap mirrored and
+// co/ci exchanged.
+__device__ __forceinline__ void put_weight_copies(const PrepLayers& L, int l, int i, float w) {
+  const int co_n = L.co[l], ci_n = L.ci[l];
+  const int tap = i / (co_n * ci_n), rem = i - tap * co_n * ci_n;
+  const int co = rem / ci_n, ci = rem - co * ci_n;
+  const __bf16 h = to_bf16(w);
+  L.wf[l][i] = h;
+  L.wt[l][((size_t)(NTAP - 1 - tap) * ci_n + ci) * co_n + co] = h;
+}
+
+// One Adam step of parameter i, and the bf16 copies of the updated weight
+// (the biases stay FP32), so the next forward pass needs no preparation.
 __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
-                       float c1, float c2) {
+                       float c1, float c2, PrepLayers L) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -827,19 +849,16 @@ __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __re
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+#pragma unroll
+  for (int l = 0; l < 3; l++) {
+    const int k = i - L.off[l];
+    if (k >= 0 && k < NTAP * L.co[l] * L.ci[l]) put_weight_copies(L, l, k, pi);
+  }
 }
 
-// bf16 forward weights [tap][co][ci] and backward-data weights
-// wt[tap][ci][co] = w[8 - tap][co][ci] from the FP32 master array, for the
-// three layers in one launch (layer l: n[l] weights from w[l])
-struct PrepLayers {
-  const float* w[3];
-  __bf16* wf[3];
-  __bf16* wt[3];
-  int co[3], ci[3];
-};
-
+// The bf16 copies of every weight (after the parameters are set).
 __global__ void k_prep_weights(PrepLayers L) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int l = 0;
@@ -848,15 +867,7 @@ __global__ void k_prep_weights(PrepLayers L) {
     l++;
   }
   if (l == 3) return;
-  const float* w = L.w[l];
-  __bf16* wf = L.wf[l];
-  __bf16* wt = L.wt[l];
-  const int co_n = L.co[l], ci_n = L.ci[l];
-  const int tap = i / (co_n * ci_n), rem = i - tap * co_n * ci_n;
-  const int co = rem / ci_n, ci = rem - co * ci_n;
-  const __bf16 h = to_bf16(w[i]);
-  wf[i] = h;
-  wt[((size_t)(NTAP - 1 - tap) * ci_n + ci) * co_n + co] = h;
+  put_weight_copies(L, l, i, L.w[l][i]);
 }
 
 }  // namespace lbnet
