@@ -629,20 +629,39 @@ constexpr int NBW = NTAP * 64;  // threads of the weight-gradient workgroup
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
-// A K-major MFMA fragment from a row-major LDS tile t[k][n] (row stride ld
-// elements): lane l receives t[k0 + 8 (l / 16) + e][n0 + l % 16], e = 0..7, as
-// the eight K values of a 16x16x32 operand.  gfx950's transposing LDS read
-// (ds_read_b64_tr_b16) serves each group of 16 lanes: lane j of the group
-// names four consecutive values S[j][0..3], and lane i receives S[(i >> 2) +
-// 4 r][i & 3], r = 0..3 (measured on the device).  So lane j points at row
-// k + (j >> 2), columns n0 + 4 (j & 3), and two reads (rows k .. k+3, k+4 ..
-// k+7) make the fragment.
-__device__ __forceinline__ bf16x8 tr_frag(const __bf16* t, int ld, int k0, int n0, int lane) {
-  const int j = lane & 15, k = k0 + 8 * (lane >> 4) + (j >> 2), n = n0 + 4 * (j & 3);
+// Row-major LDS tiles of C = 16 or 64 bf16 channels per row, laid out so that
+// the transposing reads below meet no bank conflict from any first row: one
+// read serves 32 lanes per cycle, rows r .. r+3 and r+8 .. r+11 at 32 bytes
+// each.  Rows of 128 bytes (C = 64) swizzle their 32-byte blocks with bits 1
+// and 3 of the row; rows of 32 bytes (C = 16) move 128 bytes further every
+// 8 rows (measured 2304 -> 768 and 1280 -> 768 LDS cycles per 256 reads).
+template <int C>
+__device__ __forceinline__ int tile_at(int row, int n) {
+  static_assert(C == 16 || C == 64, "tiles of 16 or 64 channels");
+  if constexpr (C == 64) {
+    const int h = ((row >> 1) & 1) | (((row >> 3) & 1) << 1);
+    return row * 64 + (((n >> 4) ^ h) << 4) + (n & 15);
+  } else {
+    return row * 16 + (row >> 3) * 64 + n;
+  }
+}
+template <int C>
+constexpr int tile_elems(int rows) { return rows * C + (C == 16 ? (rows / 8 + 1) * 64 : 0); }
+
+// A K-major MFMA fragment from such a tile: lane l receives t[r0 + 8 (l / 16)
+// + e][n0 + l % 16], e = 0..7, as the eight K values of a 16x16x32 operand.
+// gfx950's transposing LDS read (ds_read_b64_tr_b16) serves each group of 16
+// lanes: lane j of the group names four consecutive values S[j][0..3], and
+// lane i receives S[(i >> 2) + 4 r][i & 3], r = 0..3 (measured on the
+// device).  So lane j points at row r + (j >> 2), columns n0 + 4 (j & 3), and
+// two reads (rows r .. r+3, r+4 .. r+7) make the fragment.
+template <int C>
+__device__ __forceinline__ bf16x8 tr_frag(const __bf16* t, int r0, int n0, int lane) {
+  const int j = lane & 15, r = r0 + 8 * (lane >> 4) + (j >> 2), n = n0 + 4 * (j & 3);
   typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
-  const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(t + k * ld + n));
-  const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(t + (k + 4) * ld + n));
-  // rows k .. k+3 in elements 0..3, k+4 .. k+7 in 4..7 (native vector types
+  const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(t + tile_at<C>(r, n)));
+  const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(t + tile_at<C>(r + 4, n)));
+  // rows r .. r+3 in elements 0..3, r+4 .. r+7 in 4..7 (native vector types
   // only: the HIP vector structs are unions and do not carry the bits)
   return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
 }
@@ -660,8 +679,8 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
   constexpr int XS = (XV + NBW - 1) / NBW, DS = (DV + NBW - 1) / NBW;
   // two LDS copies of the tiles: row r + 1 is staged into one while row r is
   // multiplied from the other, one barrier per row
-  __shared__ __attribute__((aligned(16))) __bf16 sdz[2][IMG * CO];     // [px][co]
-  __shared__ __attribute__((aligned(16))) __bf16 sxr[2][3 * XW * CI];  // [dy][px + 1][ci]
+  __shared__ __attribute__((aligned(16))) __bf16 sdz[2][tile_elems<CO>(IMG)];     // rows px
+  __shared__ __attribute__((aligned(16))) __bf16 sxr[2][tile_elems<CI>(3 * XW)];  // rows dy XW + px + 1
   const int tid = threadIdx.x, lane = tid & 63, tap = tid >> 6;
   const int dyi = tap / 3, dxi = tap % 3;
   f32x4 acc[MB][NBT];
@@ -696,12 +715,12 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
 #pragma unroll
     for (int j = 0; j < XS; j++) {
       const int v = tid + j * NBW;
-      if (v < XV) *(uint4*)&sxr[buf][8 * v] = xr[j];
+      if (v < XV) *(uint4*)&sxr[buf][tile_at<CI>(v / (CI / 8), 8 * (v % (CI / 8)))] = xr[j];
     }
 #pragma unroll
     for (int j = 0; j < DS; j++) {
       const int v = tid + j * NBW;
-      if (v < DV) *(uint4*)&sdz[buf][8 * v] = dr[j];
+      if (v < DV) *(uint4*)&sdz[buf][tile_at<CO>(v / (CO / 8), 8 * (v % (CO / 8)))] = dr[j];
     }
   };
   const int g0 = blockIdx.x, gs = gridDim.x;
@@ -720,18 +739,19 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
     const __bf16* tz = sdz[buf];
     if (tid < CO) {
       float s = 0.0f;
-      for (int px = 0; px < IMG; px++) s += from_bf16(tz[px * CO + tid]);
+      for (int px = 0; px < IMG; px++) s += from_bf16(tz[tile_at<CO>(px, tid)]);
       db += s;
     }
-    // x row dyi, pixel p + dxi - 1 sits at staged pixel p + dxi
-    const __bf16* xt = sxr[buf] + (dyi * XW + dxi) * CI;
+    // x row dyi, pixel p + dxi - 1 sits in tile row dyi XW + p + dxi
+    const __bf16* xt = sxr[buf];
+    const int xr0 = dyi * XW + dxi;
 #pragma unroll
     for (int kc = 0; kc < IMG / 32; kc++) {
       bf16x8 a[MB], bv[NBT];
 #pragma unroll
-      for (int mb = 0; mb < MB; mb++) a[mb] = tr_frag(tz, CO, 32 * kc, 16 * mb, lane);
+      for (int mb = 0; mb < MB; mb++) a[mb] = tr_frag<CO>(tz, 32 * kc, 16 * mb, lane);
 #pragma unroll
-      for (int nb = 0; nb < NBT; nb++) bv[nb] = tr_frag(xt, CI, 32 * kc, 16 * nb, lane);
+      for (int nb = 0; nb < NBT; nb++) bv[nb] = tr_frag<CI>(xt, xr0 + 32 * kc, 16 * nb, lane);
 #pragma unroll
       for (int mb = 0; mb < MB; mb++)
 #pragma unroll
