@@ -4,10 +4,11 @@
 // channel counts padded to the MFMA tiles with zero weights), the Adam
 // moments, the bfloat16 forward and backward-data weight copies, and the
 // activation and gradient buffers for max_batch samples.  A training step is
-// lift + layer 1 (k_head) -> layers 2 + 3 (k_conv23) -> loss -> weight
-// gradients of the three layers (k_wgrad) around the data gradients of layers
-// 3 and 2 through their ReLUs (k_back32) -> one fixed-order reduction of the
-// weight-gradient partials -> Adam; every step is a kernel of
+// lift + layer 1 (k_head) -> layers 2 + 3 with the loss and dy (k_conv23)
+// -> weight gradients of the three layers (k_wgrad) around the data
+// gradients of layers 3 and 2 through their ReLUs (k_back32) -> the first
+// stage of one fixed-order reduction of the weight-gradient partials -> Adam,
+// which sums the stage's range sums; every step is a kernel of
 // lbnet_kernels.hpp on the context stream.
 #include <hip/hip_runtime.h>
 
@@ -172,8 +173,11 @@ int conv_bands(int batch, int per_cu) {
 
 // win.samples != NULL: the window path (inputs gathered by the lift, the
 // face field written by the last layer into u_out; r is not kept)
+// loss.truth != NULL: the training forward, whose last layer also writes dy
+// and the loss partials
 lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int batch,
-                  LiftWindow win = LiftWindow{nullptr, 0, 0, 1}, float* u_out = nullptr) {
+                  LiftWindow win = LiftWindow{nullptr, 0, 0, 1}, float* u_out = nullptr,
+                  LossOut loss = LossOut{nullptr, 0.0f, nullptr, nullptr}) {
   lb_status s = prep_weights(ctx);
   if (s) return s;
   hipStream_t st = ctx->stream;
@@ -191,10 +195,13 @@ lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int bat
   const int b1 = conv_bands(batch, 1);
   if (u_out)
     hipLaunchKernelGGL((k_conv23<3>), dim3(batch * b1), dim3(NBC), 0, st, ctx->a1, ctx->w2f, ctx->p + OFF_B2,
-                       ctx->w3f, ctx->p + OFF_B3, nullptr, (void*)u_out, b1, ctx->base, ctx->scale);
+                       ctx->w3f, ctx->p + OFF_B3, nullptr, (void*)u_out, b1, ctx->base, ctx->scale, loss);
+  else if (loss.truth)
+    hipLaunchKernelGGL((k_conv23<2>), dim3(batch * b1), dim3(NBC), 0, st, ctx->a1, ctx->w2f, ctx->p + OFF_B2,
+                       ctx->w3f, ctx->p + OFF_B3, ctx->a2, (void*)ctx->r, b1, ctx->base, ctx->scale, loss);
   else
     hipLaunchKernelGGL((k_conv23<1>), dim3(batch * b1), dim3(NBC), 0, st, ctx->a1, ctx->w2f, ctx->p + OFF_B2,
-                       ctx->w3f, ctx->p + OFF_B3, ctx->a2, (void*)ctx->r, b1, ctx->base, ctx->scale);
+                       ctx->w3f, ctx->p + OFF_B3, ctx->a2, (void*)ctx->r, b1, ctx->base, ctx->scale, loss);
   HIPCHK(hipGetLastError());
   ctx->last_batch = batch;
   return LB_OK;
@@ -213,15 +220,24 @@ lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size
   return LB_OK;
 }
 
-// every layer's partials summed into ctx->g in two fixed-order stages: RSEG
-// ranges of partials in parallel, then their sum (each parameter's sum is
-// the same sequence as a reduction of its layer alone)
+// every layer's partials summed in two fixed-order stages: RSEG ranges of
+// partials in parallel into ctx->part_seg here, then their sum in increasing
+// range order, which the Adam step does itself (finish_grads writes it into
+// ctx->g when the gradient is read); each parameter's sum is the same sequence
+// as a reduction of its layer alone
 lb_status reduce_grads(lbn_ctx* ctx, int batch) {
   const int n = (int)NDEV, grid = wgrad_grid(batch);
   hipStream_t st = ctx->stream;
   hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, n,
                      ctx->part_seg);
-  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256), dim3(256), 0, st, ctx->part_seg, RSEG, n, ctx->g);
+  HIPCHK(hipGetLastError());
+  return LB_OK;
+}
+
+lb_status finish_grads(lbn_ctx* ctx) {
+  const int n = (int)NDEV;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->part_seg, RSEG, n,
+                     ctx->g);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
@@ -268,7 +284,8 @@ lb_status lbn_init(const lbn_config* cfg, lbn_ctx** out) {
   ctx->scale = dalloc_t<float>(ctx, B, &ok);
   ctx->part = dalloc_t<float>(ctx, (size_t)MAX_PART * NDEV, &ok);
   ctx->part_seg = dalloc_t<float>(ctx, (size_t)RSEG * NDEV, &ok);
-  ctx->loss_part = dalloc_t<double>(ctx, 1024, &ok);
+  // one loss partial per workgroup of the last layer: batch x bands <= max(480, batch)
+  ctx->loss_part = dalloc_t<double>(ctx, std::max(1024, ctx->cfg.max_batch), &ok);
   if (!ok) {
     lbn_free(ctx);
     return LB_ERR_OOM;
@@ -341,16 +358,15 @@ lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* thet
   lb_status s = check_batch(ctx, batch);
   if (s) return s;
   if (!coarse_dev || !theta_dev || !truth_dev) return fail(ctx, LB_ERR_ARG, "null pointer");
-  s = forward(ctx, coarse_dev, theta_dev, batch);
+  const int n_px = batch * IMG * IMG;
+  const double inv_count = 1.0 / (3.0 * n_px);
+  // the loss and dy = dL/dr come out of the forward's last layer
+  s = forward(ctx, coarse_dev, theta_dev, batch, LiftWindow{nullptr, 0, 0, 1}, nullptr,
+              LossOut{truth_dev, (float)(2.0 * inv_count), ctx->dy, ctx->loss_part});
   if (s) return s;
   hipStream_t st = ctx->stream;
-  const int n_px = batch * IMG * IMG;
-  const int lgrid = std::min(1024, (n_px + NB - 1) / NB);
-  const double inv_count = 1.0 / (3.0 * n_px);
-  hipLaunchKernelGGL(k_loss, dim3(lgrid), dim3(NB), 0, st, ctx->r, ctx->base, ctx->scale, truth_dev, n_px,
-                     inv_count, ctx->dy, ctx->loss_part);
-  HIPCHK(hipGetLastError());
   const int b1 = conv_bands(batch, 1);
+  const int lgrid = batch * b1;  // loss partials: one per workgroup of the last layer
   // layer 3: weights from (a2, dy)
   if ((s = wgrad<CH, COUT>(ctx, ctx->a2, ctx->dy, batch, OFF_W3, OFF_B3))) return s;
   // data gradients through ReLU(a2) and ReLU(a1) in one pass
@@ -371,6 +387,7 @@ lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* thet
     *loss = sum * inv_count;
   }
   if (grad) {
+    if ((s = finish_grads(ctx))) return s;
     std::vector<float> dev(NDEV);
     HIPCHK(hipMemcpyAsync(dev.data(), ctx->g, NDEV * sizeof(float), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -389,7 +406,7 @@ lb_status lbn_adam_step(lbn_ctx* ctx, float lr, float beta1, float beta2, float 
   const float c2 = 1.0f - (float)std::pow((double)beta2, ctx->adam_t);
   // the step also writes the bf16 copies of the updated weights
   hipLaunchKernelGGL(k_adam, dim3((NDEV + 255) / 256), dim3(256), 0, ctx->stream, ctx->p, ctx->m, ctx->v,
-                     ctx->g, (int)NDEV, lr, beta1, beta2, eps, c1, c2, prep_layers(ctx));
+                     ctx->part_seg, RSEG, (int)NDEV, lr, beta1, beta2, eps, c1, c2, prep_layers(ctx));
   HIPCHK(hipGetLastError());
   ctx->weights_dirty = false;
   return LB_OK;

@@ -320,14 +320,44 @@ __device__ __forceinline__ void store_row(const f32x4 (&acc)[MB][CO / 16], int b
 // same chain of products (conv_products, chunks in order of increasing K) as
 // a convolution of one layer at a time would compute, so the results do not
 // depend on the band split or the fusion.  a2_out != NULL also stores the band's
-// layer-2 rows (the backward pass reads them).  EPI3: 1 (r) or 3 (u).
+// layer-2 rows (the backward pass reads them).  EPI3: 1 (r), 2 (r and the
+// loss: dy and one partial of sum e^2 per workgroup, see loss_epilogue) or 3 (u).
+struct LossOut {
+  const float* truth;  // [B][64][64][3]
+  float dy_scale;      // 2 / count
+  __bf16* dy;          // [B][64][64][16]
+  double* part;        // one partial per workgroup
+};
+
+// e = (pred - truth) / s with pred = base + s r (channels 0..2 of the fp32
+// last-layer output r): the error in units of the sample's coarse RMS; the
+// loss is the mean of e^2 and dy = dL/dr = 2 e / count (bf16, channels 3..15
+// zero).  A lane holds channels c3 .. c3 + 3 of pixel p; returns its e^2 sum.
+__device__ __forceinline__ double loss_epilogue(const float (&r)[4], int c3, size_t p, float s,
+                                                const float (&bs)[3], const float (&tr)[3],
+                                                const LossOut& L) {
+  __bf16 d[4] = {to_bf16(0.0f), to_bf16(0.0f), to_bf16(0.0f), to_bf16(0.0f)};
+  double acc = 0.0;
+  if (c3 == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const float pred = bs[c] + s * r[c];
+      const float e = (pred - tr[c]) / s;
+      acc += (double)e * (double)e;
+      d[c] = to_bf16(L.dy_scale * e);
+    }
+  }
+  *(uint2*)&L.dy[p * COUT + c3] = *(const uint2*)d;
+  return acc;
+}
+
 template <int EPI3>
 __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, const __bf16* __restrict__ w2,
                                                 const float* __restrict__ b2, const __bf16* __restrict__ w3,
                                                 const float* __restrict__ b3, __bf16* __restrict__ a2_out,
                                                 void* __restrict__ out, int bands,
                                                 const float* __restrict__ base,
-                                                const float* __restrict__ scale) {
+                                                const float* __restrict__ scale, LossOut L) {
   constexpr int C = CH, RW = IMG + 2;          // channels, pixels of a staged row
   constexpr int RV = RW * (C / 8);             // 16-byte vectors of one staged row
   constexpr int XS = (2 * RV + NBC - 1) / NBC;
@@ -383,6 +413,7 @@ __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, c
 #pragma unroll
   for (int k = 0; k < 4; k++) bb3[k] = b3[c3 + k];
   __syncthreads();
+  double lsum = 0.0;  // this lane's sum of e^2 (EPI3 2)
   const int nsteps = rows / 2 + 1;
   for (int st = 0; st < nsteps; st++) {
     const int ya = yb - 1 + 2 * st;
@@ -419,11 +450,15 @@ __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, c
       const int row_at[3] = {((y + 3) & 3) * RW, ((y + 4) & 3) * RW, ((y + 5) & 3) * RW};
       const size_t p = ((size_t)b * IMG + y) * IMG + px3 + (lane & 15);
       // the epilogue's inputs are loaded before the products
-      float bs[3] = {0.f, 0.f, 0.f}, sb = 0.f;
-      if (EPI3 == 3 && g == 0) {
+      float bs[3] = {0.f, 0.f, 0.f}, tr[3] = {0.f, 0.f, 0.f}, sb = 0.f;
+      if (EPI3 >= 2 && g == 0) {
         sb = scale[b];
 #pragma unroll
         for (int k = 0; k < 3; k++) bs[k] = base[p * 3 + k];
+        if (EPI3 == 2) {
+#pragma unroll
+          for (int k = 0; k < 3; k++) tr[k] = L.truth[p * 3 + k];
+        }
       }
       f32x4 acc[1][1];
       conv_products<C, COUT, true, 1, 1>(s_a2, s_w3, row_at, px3, lane, acc, 0);
@@ -433,11 +468,27 @@ __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, c
           for (int k = 0; k < 3; k++) ((float*)out)[p * 3 + k] = bs[k] + sb * (acc[0][0][k] + bb3[k]);
         }
       } else {
-        *(float4*)&((float*)out)[p * COUT + c3] = make_float4(acc[0][0][0] + bb3[0], acc[0][0][1] + bb3[1],
-                                                               acc[0][0][2] + bb3[2], acc[0][0][3] + bb3[3]);
+        const float rr[4] = {acc[0][0][0] + bb3[0], acc[0][0][1] + bb3[1], acc[0][0][2] + bb3[2],
+                             acc[0][0][3] + bb3[3]};
+        *(float4*)&((float*)out)[p * COUT + c3] = make_float4(rr[0], rr[1], rr[2], rr[3]);
+        if constexpr (EPI3 == 2) lsum += loss_epilogue(rr, c3, p, sb, bs, tr, L);
       }
     }
     __syncthreads();  // layer-1 rows of the next step in; layer-3 reads of s_a2 done
+  }
+  if constexpr (EPI3 == 2) {
+    // the workgroup's partial: lanes, then waves, in a fixed order (the
+    // layer-1 ring is free after the last barrier)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+    double* red = (double*)s_a1;
+    if (lane == 0) red[wave] = lsum;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NBC / 64; w++) t += red[w];
+      L.part[blockIdx.x] = t;
+    }
   }
 }
 
@@ -617,8 +668,8 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
 
 // ---------------------------------------------------------------- weight gradient
 // dW[tap][co][ci] = sum_p dz[p][co] x[p + off(tap)][ci], db[co] = sum_p dz[p][co]
-// over the image rows g, g + gridDim.x, ... of workgroup g; one partial per
-// workgroup at part + g pstride: 9 CO CI + CO values (the weights, then the
+// over the image rows g, g + gridDim.x, ... of logical workgroup g; one
+// partial per workgroup at part + g pstride: 9 CO CI + CO values (the weights, then the
 // biases: the layout of the layer's parameters), summed in a fixed order by
 // k_reduce_parts.
 // Nine waves, one per tap: a wave holds all (CO/16) x (CI/16) output tiles of
@@ -681,14 +732,21 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
   // multiplied from the other, one barrier per row
   __shared__ __attribute__((aligned(16))) __bf16 sdz[2][tile_elems<CO>(IMG)];     // rows px
   __shared__ __attribute__((aligned(16))) __bf16 sxr[2][tile_elems<CI>(3 * XW)];  // rows dy XW + px + 1
-  const int tid = threadIdx.x, lane = tid & 63, tap = tid >> 6;
+  // the wave's tap as a scalar: the per-wave choices below are then branches
+  // around whole waves (an MFMA does not honour the execution mask)
+  const int tid = threadIdx.x, lane = tid & 63, tap = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int dyi = tap / 3, dxi = tap % 3;
   f32x4 acc[MB][NBT];
 #pragma unroll
   for (int mb = 0; mb < MB; mb++)
 #pragma unroll
     for (int nb = 0; nb < NBT; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float db = 0.0f;
+  // bias gradient db = dz^T 1 on the matrix cores: wave w < MB takes output
+  // block w, one more product per dz fragment against a B operand of ones
+  f32x4 accb = {0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int e = 0; e < 8; e++) ones[e] = (__bf16)1.0f;
   // the row after the one being staged travels in registers
   uint4 xr[XS], dr[DS];
   auto load_row = [&](int row) {
@@ -723,7 +781,12 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
       if (v < DV) *(uint4*)&sdz[buf][tile_at<CO>(v / (CO / 8), 8 * (v % (CO / 8)))] = dr[j];
     }
   };
-  const int g0 = blockIdx.x, gs = gridDim.x;
+  // workgroups are dealt to the 8 XCDs in turn; logical index g0 gives each
+  // XCD a contiguous range, so the three workgroups that share an x row read
+  // it through the same L2.  Partial g0 holds rows g0, g0 + gs, ... whichever
+  // workgroup runs it.
+  const int gs = gridDim.x;
+  const int g0 = gs % 8 == 0 ? (blockIdx.x % 8) * (gs / 8) + blockIdx.x / 8 : blockIdx.x;
   if (g0 < n_rows) {
     load_row(g0);
     stage(0);
@@ -737,11 +800,6 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
       if (row + 2 * gs < n_rows) load_row(row + 2 * gs);
     }
     const __bf16* tz = sdz[buf];
-    if (tid < CO) {
-      float s = 0.0f;
-      for (int px = 0; px < IMG; px++) s += from_bf16(tz[tile_at<CO>(px, tid)]);
-      db += s;
-    }
     // x row dyi, pixel p + dxi - 1 sits in tile row dyi XW + p + dxi
     const __bf16* xt = sxr[buf];
     const int xr0 = dyi * XW + dxi;
@@ -757,10 +815,13 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
 #pragma unroll
         for (int nb = 0; nb < NBT; nb++)
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++)
+        if (tap == mb) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], ones, accb, 0, 0, 0);
     }
     __syncthreads();  // this row's reads done; the next row's tiles are in
   }
-  float* pg = part + (size_t)blockIdx.x * pstride;
+  float* pg = part + (size_t)g0 * pstride;
 #pragma unroll
   for (int mb = 0; mb < MB; mb++)
 #pragma unroll
@@ -770,7 +831,11 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
         const int co = 16 * mb + 4 * (lane >> 4) + i, ci = 16 * nb + (lane & 15);
         pg[((size_t)tap * CO + co) * CI + ci] = acc[mb][nb][i];
       }
-  if (tid < CO) pg[NTAP * CO * CI + tid] = db;
+  // every column of accb holds the sums; lanes of column 0 store them
+  if (tap < MB && (lane & 15) == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) pg[NTAP * CO * CI + 16 * tap + 4 * (lane >> 4) + i] = accb[i];
+  }
 }
 
 // out[s][i] = sum of part[g][i] over the s-th of gridDim.y equal ranges of g,
@@ -789,40 +854,6 @@ __global__ void k_reduce_parts(const float* __restrict__ part, int n_parts, int 
   out[(size_t)blockIdx.y * n + i] = s;
 }
 
-// ---------------------------------------------------------------- loss
-// e = (pred - truth) / s with pred = base + s r (channels 0..2 of the fp32
-// last-layer output r [B][64][64][16]): the error in units of the sample's
-// coarse RMS.  Per-workgroup partial of sum e^2 (double) and
-// dy = dL/dr = 2 e / count as bf16 [B][64][64][16] (channels 3..15 zero).
-__global__ __launch_bounds__(NB) void k_loss(const float* __restrict__ r, const float* __restrict__ base,
-                                             const float* __restrict__ scale,
-                                             const float* __restrict__ truth, int n_px,
-                                             double inv_count, __bf16* __restrict__ dy,
-                                             double* __restrict__ part) {
-  __shared__ double red[NB];
-  double acc = 0.0;
-  for (int p = blockIdx.x * NB + threadIdx.x; p < n_px; p += gridDim.x * NB) {
-    const float s = scale[p / (IMG * IMG)];
-    __bf16* d = dy + (size_t)p * COUT;
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      const float pred = base[(size_t)p * 3 + c] + s * r[(size_t)p * COUT + c];
-      const float e = (pred - truth[(size_t)p * 3 + c]) / s;
-      acc += (double)e * (double)e;
-      d[c] = to_bf16((float)(2.0 * inv_count) * e);
-    }
-#pragma unroll
-    for (int c = 3; c < COUT; c++) d[c] = to_bf16(0.0f);
-  }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = NB / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
 // u = base + s r for channels 0..2: out [B][64][64][3]
 __global__ void k_combine(const float* __restrict__ r, const float* __restrict__ base,
                           const float* __restrict__ scale, int n_px, float* __restrict__ out) {
@@ -836,7 +867,8 @@ __global__ void k_combine(const float* __restrict__ r, const float* __restrict__
 // ---------------------------------------------------------------- parameters
 // Adam (Kingma and Ba) on the FP32 master parameters, bias-corrected with
 // step t: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
-// p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+// p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps); g is the sum of
+// the nseg range sums seg[s][i] in increasing s, as k_reduce_parts takes it
 struct PrepLayers {
   const float* w[3];
   __bf16* wf[3];
@@ -860,11 +892,13 @@ __device__ __forceinline__ void put_weight_copies(const PrepLayers& L, int l, in
 // One Adam step of parameter i, and the bf16 copies of the updated weight
 // (the biases stay FP32), so the next forward pass needs no preparation.
 __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
-                       float c1, float c2, PrepLayers L) {
+                       const float* __restrict__ seg, int nseg, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, PrepLayers L) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
+  float gi = 0.0f;
+#pragma unroll 8
+  for (int s = 0; s < nseg; s++) gi += seg[(size_t)s * n + i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;

@@ -132,6 +132,21 @@ def test_gradients_and_adam_match_oracle(samples):
     net.close()
 
 
+def test_training_is_bitwise_reproducible(samples):
+    """Two trainings from the same parameters on the same batches end in the
+    same bits: every reduction of the backward pass runs in a fixed order."""
+    c, th, truth = samples
+    runs = []
+    for rep in range(2):
+        say(f"case upsampler training reproducibility, run {rep}")
+        net = lbnet.Upsampler(coarse=8, max_batch=64)
+        net.set_params(lbnet.init_params(5))
+        train(net, c, th, truth, iters=40, batch=min(32, c.shape[0]), lr=3e-4, seed=3)
+        runs.append(net.params())
+        net.close()
+    assert np.array_equal(runs[0], runs[1])
+
+
 def test_window_forward_matches_gathered_samples():
     """The window entry point gathers S_{k-1..k+2} (clamped) and the phases
     itself; its result equals lbn_forward on the same inputs gathered here."""
