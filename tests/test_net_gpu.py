@@ -13,7 +13,7 @@ below as ~3e-2 relative on r.
 import numpy as np
 import pytest
 
-from lbcase import rel_l2
+from lbcase import max_rel, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -57,11 +57,17 @@ def test_forward_matches_oracle(samples):
     a2 = net.read_buffer(lbnet.BUF_A2, B)
     r = net.read_buffer(lbnet.BUF_R, B)
     chw = lambda a: a.transpose(0, 3, 1, 2)  # noqa: E731
-    e = {"x0": rel_l2(chw(x0[..., :15]), fw["x0"]), "a1": rel_l2(chw(a1), fw["a1"]),
-         "a2": rel_l2(chw(a2), fw["a2"]), "r": rel_l2(chw(r[..., :3]), fw["r"]),
-         "u": rel_l2(out.cpu().numpy(), fw["u"].transpose(0, 2, 3, 1))}
+    pairs = {"x0": (chw(x0[..., :15]), fw["x0"]), "a1": (chw(a1), fw["a1"]), "a2": (chw(a2), fw["a2"]),
+             "r": (chw(r[..., :3]), fw["r"]), "u": (out.cpu().numpy(), fw["u"].transpose(0, 2, 3, 1))}
+    e = {k: rel_l2(a, b) for k, (a, b) in pairs.items()}
+    m = {k: max_rel(a, b) for k, (a, b) in pairs.items()}
     say("forward rel-L2 vs bf16-emulating oracle", e)
+    say("forward max-norm (largest error over the field's largest value)", m)
     assert max(e.values()) < 2e-3
+    # a bf16 activation can land one bf16 step (2^-8 of its value) away where
+    # the FP32 sum and the oracle's FP64 sum round to neighbouring values
+    # (measured 2.6e-3 for a1 and a2)
+    assert max(m.values()) < 5e-3
     assert np.all(x0[..., 15:] == 0) and np.all(r[..., 3:] == 0)
     # the bfloat16 precision itself, against the unrounded FP64 network
     fw64 = no.forward(p.astype(np.float64), c, th, bf=False)
@@ -117,8 +123,12 @@ def test_gradients_and_adam_match_oracle(samples):
     assert abs(loss - L) <= 1e-4 * L
     blocks = ["W1", "b1", "W2", "b2", "W3", "b3"]
     errs = {n: rel_l2(a, b) for n, a, b in zip(blocks, lbnet.split_params(grad), no.split(g_or))}
+    errm = {n: max_rel(a, b) for n, a, b in zip(blocks, lbnet.split_params(grad), no.split(g_or))}
     say("gradient rel-L2 per block", errs)
+    say("gradient max-norm per block", errm)
     assert max(errs.values()) < 5e-3
+    # the same bf16 products summed in FP32 against FP64 (measured <= 5.3e-6)
+    assert max(errm.values()) < 1e-4
     # one Adam step from the same parameters (oracle: its own gradient)
     net.adam_step(lr=1e-3)
     p1 = net.params()
