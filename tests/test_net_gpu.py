@@ -142,6 +142,36 @@ def test_gradients_and_adam_match_oracle(samples):
     net.close()
 
 
+def test_loss_matches_the_forward_output_at_any_batch(samples):
+    """The loss the forward's last layer forms equals the mean of
+    ((u - truth) / s)^2 recomputed in FP64 on the host from lbn_forward's face
+    field u and scales s, at one band per image (batch 256: one loss partial
+    per image), several bands and a single image; and r after lbn_loss_grad is
+    bitwise the r of lbn_forward (the same last-layer arithmetic)."""
+    c, th, truth = samples
+    p = lbnet.init_params(4)
+    p[-(3 * 64 * 9 + 3):] = np.random.Generator(np.random.PCG64(23)).standard_normal(3 * 64 * 9 + 3) * 0.05
+    net = lbnet.Upsampler(coarse=8, max_batch=256)
+    net.set_params(p)
+    for batch in (1, 37, 256):
+        idx = np.arange(batch) % c.shape[0]
+        cb, thb, tb = c[idx], th[idx], truth[idx]
+        say(f"case upsampler loss at batch {batch}")
+        out = torch.zeros((batch, 64, 64, 3), device="cuda")
+        net.forward(dev(cb), dev(thb), out)
+        torch.cuda.synchronize()
+        u = out.cpu().numpy().astype(np.float64)
+        s = net.read_buffer(lbnet.BUF_SCALE, batch).astype(np.float64)
+        r_fwd = net.read_buffer(lbnet.BUF_R, batch)
+        l_host = float(np.mean(((u - tb) / s[:, None, None, None]) ** 2))
+        loss, _ = net.loss_grad(dev(cb), dev(thb), dev(tb), want_loss=True)
+        say("loss gpu", loss, "host from the forward output", l_host)
+        # e in FP32 on the GPU against FP64 here: rounding of e only
+        assert abs(loss - l_host) <= 1e-5 * l_host
+        assert np.array_equal(net.read_buffer(lbnet.BUF_R, batch), r_fwd)
+    net.close()
+
+
 def test_training_is_bitwise_reproducible(samples):
     """Two trainings from the same parameters on the same batches end in the
     same bits: every reduction of the backward pass runs in a fixed order."""
