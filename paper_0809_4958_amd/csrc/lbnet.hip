@@ -214,8 +214,9 @@ template <int CI, int CO>
 lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size_t off_w, size_t off_b) {
   const int rows = batch * IMG;
   (void)off_b;  // == off_w + 9 CO CI
+  // the last layer's padded output channels have zero gradients: not stored
   hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(wgrad_grid(batch)), dim3(NBW), 0, ctx->stream, x, dz,
-                     ctx->part + off_w, (int)NDEV, rows);
+                     ctx->part + off_w, (int)NDEV, rows, CO == COUT ? OUT_USED : CO);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
@@ -228,16 +229,20 @@ lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size
 lb_status reduce_grads(lbn_ctx* ctx, int batch) {
   const int n = (int)NDEV, grid = wgrad_grid(batch);
   hipStream_t st = ctx->stream;
+  // the partials of the last layer's padded output channels are not stored
+  // nor read; their range sums stay at the zero they start with
+  const PadRows pad{(int)OFF_W3, (int)OFF_B3, COUT, CH, OUT_USED};
   hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, n,
-                     ctx->part_seg);
+                     ctx->part_seg, pad);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
 
 lb_status finish_grads(lbn_ctx* ctx) {
   const int n = (int)NDEV;
+  const PadRows none{n, n, 1, 1, 1};
   hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->part_seg, RSEG, n,
-                     ctx->g);
+                     ctx->g, none);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
@@ -296,7 +301,9 @@ lb_status lbn_init(const lbn_config* cfg, lbn_ctx** out) {
       lbn_free(ctx);
       return LB_ERR_HIP;
     }
-  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+  // the range sums of the partial reduction: zero where it never writes
+  if (hipMemsetAsync(ctx->part_seg, 0, (size_t)RSEG * NDEV * sizeof(float), ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
     lbn_free(ctx);
     return LB_ERR_HIP;
   }

@@ -719,7 +719,7 @@ __device__ __forceinline__ bf16x8 tr_frag(const __bf16* t, int r0, int n0, int l
 
 template <int CI, int CO>
 __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, const __bf16* __restrict__ dz,
-                                              float* __restrict__ part, int pstride, int n_rows) {
+                                              float* __restrict__ part, int pstride, int n_rows, int co_used) {
   // x rows y-1 .. y+1 and the dz row staged as they lie in memory (pixel-major,
   // channels contiguous; x with a zero pixel on either side); the products read
   // both K-major (K = pixels) through tr_frag, and the tap's dx is a row offset
@@ -829,21 +829,37 @@ __global__ __launch_bounds__(NBW) void k_wgrad(const __bf16* __restrict__ x, con
 #pragma unroll
       for (int i = 0; i < 4; i++) {
         const int co = 16 * mb + 4 * (lane >> 4) + i, ci = 16 * nb + (lane & 15);
-        pg[((size_t)tap * CO + co) * CI + ci] = acc[mb][nb][i];
+        if (co < co_used) pg[((size_t)tap * CO + co) * CI + ci] = acc[mb][nb][i];
       }
   // every column of accb holds the sums; lanes of column 0 store them
   if (tap < MB && (lane & 15) == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; i++) pg[NTAP * CO * CI + 16 * tap + 4 * (lane >> 4) + i] = accb[i];
+    for (int i = 0; i < 4; i++) {
+      const int co = 16 * tap + 4 * (lane >> 4) + i;
+      if (co < co_used) pg[NTAP * CO * CI + co] = accb[i];
+    }
   }
 }
 
+// Output channels of a layer that only pad its tile (the last layer's
+// channels past the used ones): zero weights and biases with zero gradients,
+// which the weight-gradient kernel does not store and the reduction skips.
+// Weights at w_off, [tap][co][ci]; biases at b_off; channels used .. co - 1.
+struct PadRows {
+  int w_off, b_off, co, ci, used;
+  __device__ bool skips(int i) const {
+    if (i >= w_off && i < w_off + NTAP * co * ci) return ((i - w_off) / ci) % co >= used;
+    return i >= b_off + used && i < b_off + co;
+  }
+};
+
 // out[s][i] = sum of part[g][i] over the s-th of gridDim.y equal ranges of g,
-// in increasing g (fixed order), i < n; with gridDim.y = 1 the full sum
+// in increasing g (fixed order), i < n; with gridDim.y = 1 the full sum.
+// Entries pad.skips(i) are not read and keep their zero in out.
 __global__ void k_reduce_parts(const float* __restrict__ part, int n_parts, int n,
-                               float* __restrict__ out) {
+                               float* __restrict__ out, PadRows pad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || pad.skips(i)) return;
   const int per = (n_parts + gridDim.y - 1) / gridDim.y;
   const int g0 = blockIdx.y * per, g1 = min(n_parts, g0 + per);
   float s = 0.0f;
