@@ -621,7 +621,9 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
   constexpr int CI = CIN, CO = CH;
   constexpr int SR = TR + 2;
   __shared__ __attribute__((aligned(16))) __bf16 sw[NTAP * CO * CI];
-  __shared__ __attribute__((aligned(16))) __bf16 sx[SR * (IMG + 2) * CI];
+  // two lifted tiles: tile t + 1 is lifted (VALU) while tile t is multiplied
+  // (MFMA), one barrier per tile
+  __shared__ __attribute__((aligned(16))) __bf16 sx[2][SR * (IMG + 2) * CI];
   __shared__ double red[NBC];
   extern __shared__ __attribute__((aligned(16))) float dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -632,9 +634,9 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
   const float* feat = dyn + 12 * R * R;
   if (tid == 0 && band == 0) scale[b] = s;
   const int r = wave >> 1, px0 = (wave & 1) * 32;
-  const int rows = IMG / bands;
-  for (int y0 = band * rows; y0 < (band + 1) * rows; y0 += TR) {
-    __syncthreads();  // the previous tile's reads of sx are done
+  const int rows = IMG / bands, ntiles = rows / TR;
+  // the tile of rows y0 .. y0 + TR - 1 lifted with a row either side
+  auto lift_tile = [&](int y0, __bf16* st) {
     for (int q = tid; q < SR * (IMG + 2); q += NBC) {
       const int rr = q / (IMG + 2), xx = q - rr * (IMG + 2) - 1, yy = y0 - 1 + rr;
       uint4 lo4 = make_uint4(0u, 0u, 0u, 0u), hi4 = lo4;
@@ -655,13 +657,20 @@ __global__ __launch_bounds__(NBC) void k_head(const float* __restrict__ coarse,
           }
         }
       }
-      *(uint4*)&sx[lds_at<CI>(q, 0)] = lo4;
-      *(uint4*)&sx[lds_at<CI>(q, 1)] = hi4;
+      *(uint4*)&st[lds_at<CI>(q, 0)] = lo4;
+      *(uint4*)&st[lds_at<CI>(q, 1)] = hi4;
     }
+  };
+  lift_tile(band * rows, sx[0]);
+  for (int t = 0; t < ntiles; t++) {
+    // tile t is lifted; the products of tile t - 1, which read the other
+    // buffer, are done
     __syncthreads();
+    const int y0 = band * rows + t * TR;
+    if (t + 1 < ntiles) lift_tile(y0 + TR, sx[(t + 1) & 1]);
     f32x4 acc[2][CO / 16];
     const int row_at[3] = {r * (IMG + 2), (r + 1) * (IMG + 2), (r + 2) * (IMG + 2)};
-    conv_products<CI, CO, false>(sx, sw, row_at, px0, lane, acc);
+    conv_products<CI, CO, false>(sx[t & 1], sw, row_at, px0, lane, acc);
     store_row<CO>(acc, b, y0 + r, px0, lane, bias, a1);
   }
 }
