@@ -554,9 +554,18 @@ __global__ __launch_bounds__(NBC) void k_back32(const __bf16* __restrict__ dy, c
   // both convolutions: wave = (row r, pixel half, channel half), 32 x 32 outputs
   const int r = wave >> 2, q = wave & 3, px0 = 32 * (q & 1), nb0 = 2 * (q >> 1);
   const int g = lane >> 4, c0 = 16 * g + 8 * (q >> 1);  // the 8 channels a lane holds
-  // masked bf16 of a lane's 8 channels of pixel px of row y (mask row of m)
-  auto masked = [&](const f32x4 (&acc)[2][2], int mb, const __bf16* __restrict__ m, int y, int px) {
-    const uint4 mv = *(const uint4*)&m[(((size_t)b * IMG + y) * IMG + px) * C + c0];
+  // a lane's mask values (8 channels of pixel px0 + 16 mb + lane % 16 of row
+  // y of m), loaded before the products that they then mask
+  auto mask_load = [&](uint4 (&mv)[2], const __bf16* __restrict__ m, int y) {
+#pragma unroll
+    for (int mb = 0; mb < 2; mb++) {
+      const int px = px0 + 16 * mb + (lane & 15);
+      mv[mb] = *(const uint4*)&m[(((size_t)b * IMG + y) * IMG + px) * C + c0];
+    }
+  };
+  // masked bf16 of those 8 channels
+  auto masked = [&](const f32x4 (&acc)[2][2], int mb, const uint4 (&mvs)[2]) {
+    const uint4 mv = mvs[mb];
     const __bf16* me = (const __bf16*)&mv;
     __bf16 h[8];
 #pragma unroll
@@ -573,13 +582,15 @@ __global__ __launch_bounds__(NBC) void k_back32(const __bf16* __restrict__ dy, c
     {
       const int y = ya + r;  // dz2 row of this wave
       const int row_at[3] = {((y + 3) & 3) * RW, ((y + 4) & 3) * RW, ((y + 5) & 3) * RW};
+      const bool inside = y >= 0 && y < IMG;
+      uint4 mv[2] = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)};
+      if (inside) mask_load(mv, a2, y);
       f32x4 acc[2][2];
       conv_products<CA, C, true, 2, 2>(s_dy, s_wa, row_at, px0, lane, acc, nb0);
-      const bool inside = y >= 0 && y < IMG;
 #pragma unroll
       for (int mb = 0; mb < 2; mb++) {
         const int px = px0 + 16 * mb + (lane & 15);
-        const uint4 hv = inside ? masked(acc, mb, a2, y, px) : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 hv = inside ? masked(acc, mb, mv) : make_uint4(0u, 0u, 0u, 0u);
         *(uint4*)&s_dz[lds_at<C>(((y + 4) & 3) * RW + px + 1, c0 >> 3)] = hv;
         if (y >= yb && y < ye) *(uint4*)&dz2[(((size_t)b * IMG + y) * IMG + px) * C + c0] = hv;
       }
@@ -592,12 +603,14 @@ __global__ __launch_bounds__(NBC) void k_back32(const __bf16* __restrict__ dy, c
     if (st >= 1) {
       const int y = ya - 1 + r;  // dz1 row of this wave
       const int row_at[3] = {((y + 3) & 3) * RW, ((y + 4) & 3) * RW, ((y + 5) & 3) * RW};
+      uint4 mv[2];
+      mask_load(mv, a1, y);
       f32x4 acc[2][2];
       conv_products<C, C, true, 2, 2>(s_dz, s_wb, row_at, px0, lane, acc, nb0);
 #pragma unroll
       for (int mb = 0; mb < 2; mb++) {
         const int px = px0 + 16 * mb + (lane & 15);
-        *(uint4*)&dz1[(((size_t)b * IMG + y) * IMG + px) * C + c0] = masked(acc, mb, a1, y, px);
+        *(uint4*)&dz1[(((size_t)b * IMG + y) * IMG + px) * C + c0] = masked(acc, mb, mv);
       }
     }
     __syncthreads();  // dy rows of the next step in; the reads of s_dz done
