@@ -31,7 +31,7 @@ constexpr size_t OFF_W1 = 0, OFF_B1 = OFF_W1 + W1N, OFF_W2 = OFF_B1 + CH, OFF_B2
                  OFF_W3 = OFF_B2 + CH, OFF_B3 = OFF_W3 + W3N, NDEV = OFF_B3 + COUT;
 constexpr int IN_USED = 15, OUT_USED = 3;
 constexpr int MAX_PART = 256;  // weight-gradient partials (workgroups)
-constexpr int RSEG = 16;       // first-stage ranges of the partial reduction
+constexpr int RSEG = ADAM_RANGES;  // first-stage ranges of the partial reduction
 
 static_assert((size_t)CH * IN_USED * 9 + CH + (size_t)CH * CH * 9 + CH + (size_t)OUT_USED * CH * 9 +
                       OUT_USED ==
@@ -55,6 +55,7 @@ struct lbn_ctx {
   float* part_seg = nullptr;
   double* loss_part = nullptr;
   int last_batch = 0;
+  int grad_parts = 0;  // weight-gradient partials of the last lbn_loss_grad
   std::vector<void*> owned;
 };
 
@@ -221,28 +222,24 @@ lb_status wgrad(lbn_ctx* ctx, const __bf16* x, const __bf16* dz, int batch, size
   return LB_OK;
 }
 
-// every layer's partials summed in two fixed-order stages: RSEG ranges of
-// partials in parallel into ctx->part_seg here, then their sum in increasing
-// range order, which the Adam step does itself (finish_grads writes it into
-// ctx->g when the gradient is read); each parameter's sum is the same sequence
-// as a reduction of its layer alone
-lb_status reduce_grads(lbn_ctx* ctx, int batch) {
-  const int n = (int)NDEV, grid = wgrad_grid(batch);
-  hipStream_t st = ctx->stream;
-  // the partials of the last layer's padded output channels are not stored
-  // nor read; their range sums stay at the zero they start with
-  const PadRows pad{(int)OFF_W3, (int)OFF_B3, COUT, CH, OUT_USED};
-  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, grid, n,
-                     ctx->part_seg, pad);
-  HIPCHK(hipGetLastError());
-  return LB_OK;
-}
+// The partials of the last layer's padded output channels are neither
+// stored nor read (zero gradients).
+PadRows last_layer_pad() { return PadRows{(int)OFF_W3, (int)OFF_B3, COUT, CH, OUT_USED}; }
 
+// The gradient into ctx->g, when it is read: every layer's partials summed in
+// two fixed-order stages, RSEG ranges of partials in parallel into
+// ctx->part_seg, then their sum in increasing range order (each parameter's
+// sum the same sequence as a reduction of its layer alone; the Adam step
+// forms the same sums itself, k_adam_parts).  The padded entries' range sums
+// stay at the zero they start with.
 lb_status finish_grads(lbn_ctx* ctx) {
   const int n = (int)NDEV;
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256, RSEG), dim3(256), 0, st, ctx->part, ctx->grad_parts,
+                     n, ctx->part_seg, last_layer_pad());
   const PadRows none{n, n, 1, 1, 1};
-  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, ctx->part_seg, RSEG, n,
-                     ctx->g, none);
+  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 255) / 256), dim3(256), 0, st, ctx->part_seg, RSEG, n, ctx->g,
+                     none);
   HIPCHK(hipGetLastError());
   return LB_OK;
 }
@@ -383,7 +380,7 @@ lb_status lbn_loss_grad(lbn_ctx* ctx, const float* coarse_dev, const float* thet
   if ((s = wgrad<CH, CH>(ctx, ctx->a1, ctx->dz2, batch, OFF_W2, OFF_B2))) return s;
   // layer 1
   if ((s = wgrad<CIN, CH>(ctx, ctx->x0, ctx->dz1, batch, OFF_W1, OFF_B1))) return s;
-  if ((s = reduce_grads(ctx, batch))) return s;
+  ctx->grad_parts = wgrad_grid(batch);  // summed by the Adam step or finish_grads
   ctx->has_grad = true;
   if (loss) {
     std::vector<double> part(lgrid);
@@ -411,9 +408,12 @@ lb_status lbn_adam_step(lbn_ctx* ctx, float lr, float beta1, float beta2, float 
   ctx->adam_t++;
   const float c1 = 1.0f - (float)std::pow((double)beta1, ctx->adam_t);
   const float c2 = 1.0f - (float)std::pow((double)beta2, ctx->adam_t);
-  // the step also writes the bf16 copies of the updated weights
-  hipLaunchKernelGGL(k_adam, dim3((NDEV + 255) / 256), dim3(256), 0, ctx->stream, ctx->p, ctx->m, ctx->v,
-                     ctx->part_seg, RSEG, (int)NDEV, lr, beta1, beta2, eps, c1, c2, prep_layers(ctx));
+  // the gradient summed from the partials in the same pass; the step also
+  // writes the bf16 copies of the updated weights
+  hipLaunchKernelGGL(k_adam_parts, dim3((NDEV + ADAM_PARAMS - 1) / ADAM_PARAMS), dim3(ADAM_RANGES * ADAM_PARAMS), 0,
+                     ctx->stream, ctx->part, ctx->grad_parts,
+                     (int)NDEV, last_layer_pad(), ctx->p, ctx->m, ctx->v, lr, beta1, beta2, eps, c1, c2,
+                     prep_layers(ctx));
   HIPCHK(hipGetLastError());
   ctx->weights_dirty = false;
   return LB_OK;

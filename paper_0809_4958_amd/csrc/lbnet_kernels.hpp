@@ -927,16 +927,36 @@ __device__ __forceinline__ void put_weight_copies(const PrepLayers& L, int l, in
   L.wt[l][((size_t)(NTAP - 1 - tap) * ci_n + ci) * co_n + co] = h;
 }
 
-// One Adam step of parameter i, and the bf16 copies of the updated weight
-// (the biases stay FP32), so the next forward pass needs no preparation.
-__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ seg, int nseg, int n, float lr, float b1, float b2,
-                       float eps, float c1, float c2, PrepLayers L) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float gi = 0.0f;
+// The weight gradient summed from the partials and one Adam step of each
+// parameter, with the bf16 copies of the updated weights (the biases stay
+// FP32), so the next forward pass needs no preparation.  One pass: a
+// workgroup of 1024 threads takes 64 parameters (a wave reads 64 consecutive
+// values of a partial); thread (s, j)
+// sums range s of the 16 equal ranges of partials of parameter j in
+// increasing order (the first stage of k_reduce_parts), and thread j the 16
+// range sums in increasing order (its second stage), so the gradient is
+// bitwise the two-launch reduction's.  pad.skips(i): a zero gradient.
+constexpr int ADAM_RANGES = 16;
+constexpr int ADAM_PARAMS = 64;  // parameters per workgroup of k_adam_parts
+__global__ __launch_bounds__(ADAM_RANGES * ADAM_PARAMS) void k_adam_parts(const float* __restrict__ part, int n_parts, int n,
+                                                    PadRows pad, float* __restrict__ p, float* __restrict__ m,
+                                                    float* __restrict__ v, float lr, float b1, float b2,
+                                                    float eps, float c1, float c2, PrepLayers L) {
+  __shared__ float rs[ADAM_RANGES][ADAM_PARAMS];
+  const int j = threadIdx.x % ADAM_PARAMS, sg = threadIdx.x / ADAM_PARAMS;
+  const int i = blockIdx.x * ADAM_PARAMS + j;
+  float sum = 0.0f;
+  if (i < n && !pad.skips(i)) {
+    const int per = (n_parts + ADAM_RANGES - 1) / ADAM_RANGES, g0 = sg * per, g1 = min(n_parts, g0 + per);
 #pragma unroll 8
-  for (int s = 0; s < nseg; s++) gi += seg[(size_t)s * n + i];
+    for (int g = g0; g < g1; g++) sum += part[(size_t)g * n + i];
+  }
+  rs[sg][j] = sum;
+  __syncthreads();
+  if (threadIdx.x >= ADAM_PARAMS || i >= n) return;
+  float gi = 0.0f;
+#pragma unroll
+  for (int s = 0; s < ADAM_RANGES; s++) gi += rs[s][j];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
