@@ -222,10 +222,12 @@ __device__ __forceinline__ void store_pixel(const float (&v)[NC], size_t p, int 
 // The products of one tile row for a wave: 32 pixels (px0 ..) of output row
 // y against all CO output slots of the staged weights, K = 9 CI in chunks of
 // 32 (with PF, the fragments of the next two chunks load while a chunk
-// multiplies).  The input
+// multiplies; with KEEP_ORDER, the compiler may not move those loads down to
+// their use, which it otherwise does: measured faster in the backward pass,
+// not in the forward ones).  The input
 // row y + dy starts at LDS pixel row_at[dy + 1] (rows of IMG + 2 pixels, zero
 // halo).
-template <int CI, int CO, bool PF = true, int MB = 2, int NBK = CO / 16>
+template <int CI, int CO, bool PF = true, int MB = 2, int NBK = CO / 16, bool KEEP_ORDER = false>
 __device__ __forceinline__ void conv_products(const __bf16* sx, const __bf16* sw, const int (&row_at)[3], int px0,
                                               int lane, f32x4 (&acc)[MB][NBK], int nb0 = 0) {
   constexpr int KCH = (NTAP * CI + 31) / 32;
@@ -265,6 +267,7 @@ __device__ __forceinline__ void conv_products(const __bf16* sx, const __bf16* sw
 #pragma unroll
     for (int kc = 0; kc < KCH; kc++) {
       if (kc + 2 < KCH) frag(kc + 2, fa[(kc + 2) % 3], fb[(kc + 2) % 3]);
+      if constexpr (KEEP_ORDER) __builtin_amdgcn_sched_barrier(0);
       mult(fa[kc % 3], fb[kc % 3]);
     }
   } else {
@@ -586,7 +589,7 @@ __global__ __launch_bounds__(NBC) void k_back32(const __bf16* __restrict__ dy, c
       uint4 mv[2] = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)};
       if (inside) mask_load(mv, a2, y);
       f32x4 acc[2][2];
-      conv_products<CA, C, true, 2, 2>(s_dy, s_wa, row_at, px0, lane, acc, nb0);
+      conv_products<CA, C, true, 2, 2, true>(s_dy, s_wa, row_at, px0, lane, acc, nb0);
 #pragma unroll
       for (int mb = 0; mb < 2; mb++) {
         const int px = px0 + 16 * mb + (lane & 15);
@@ -606,7 +609,7 @@ __global__ __launch_bounds__(NBC) void k_back32(const __bf16* __restrict__ dy, c
       uint4 mv[2];
       mask_load(mv, a1, y);
       f32x4 acc[2][2];
-      conv_products<C, C, true, 2, 2>(s_dz, s_wb, row_at, px0, lane, acc, nb0);
+      conv_products<C, C, true, 2, 2, true>(s_dz, s_wb, row_at, px0, lane, acc, nb0);
 #pragma unroll
       for (int mb = 0; mb < 2; mb++) {
         const int px = px0 + 16 * mb + (lane & 15);
