@@ -223,8 +223,8 @@ __device__ __forceinline__ void store_pixel(const float (&v)[NC], size_t p, int 
 // y against all CO output slots of the staged weights, K = 9 CI in chunks of
 // 32 (with PF, the fragments of the next two chunks load while a chunk
 // multiplies; with KEEP_ORDER, the compiler may not move those loads down to
-// their use, which it otherwise does: measured faster in the backward pass,
-// not in the forward ones).  The input
+// their use, which it otherwise does: measured faster in the backward pass
+// and the forward's last layer, not in its 64 -> 64 layer).  The input
 // row y + dy starts at LDS pixel row_at[dy + 1] (rows of IMG + 2 pixels, zero
 // halo).
 template <int CI, int CO, bool PF = true, int MB = 2, int NBK = CO / 16, bool KEEP_ORDER = false>
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(NBC) void k_conv23(const __bf16* __restrict__ a1, c
         }
       }
       f32x4 acc[1][1];
-      conv_products<C, COUT, true, 1, 1>(s_a2, s_w3, row_at, px3, lane, acc, 0);
+      conv_products<C, COUT, true, 1, 1, true>(s_a2, s_w3, row_at, px3, lane, acc, 0);
       if constexpr (EPI3 == 3) {
         if (g == 0) {
 #pragma unroll
