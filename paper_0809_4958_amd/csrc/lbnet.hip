@@ -183,11 +183,12 @@ lb_status forward(lbn_ctx* ctx, const float* coarse, const float* theta, int bat
   if (s) return s;
   hipStream_t st = ctx->stream;
   const int R = ctx->cfg.coarse;
-  // lift + layer 1 per (sample, band): bands so that the grid covers the
-  // 256 compute units; x0 kept only outside the window path (training and
-  // lbn_read_buffer read it)
+  // lift + layer 1 per (sample, band): bands so that the grid covers most of
+  // the 256 compute units (each band repeats the sample's preparation, so a
+  // grid of 240 for the 120-image window beats 480); x0 kept only outside
+  // the window path (training and lbn_read_buffer read it)
   int bands = 1;
-  while (bands < IMG / TR && batch * bands < 256) bands *= 2;
+  while (bands < IMG / TR && batch * bands < 240) bands *= 2;
   hipLaunchKernelGGL(k_head, dim3(batch * bands), dim3(NBC), 24 * R * R * sizeof(float), st, coarse, theta, win,
                      R, ctx->w1f, ctx->p + OFF_B1, ctx->a1, u_out ? nullptr : ctx->x0, ctx->base, ctx->scale,
                      bands);
